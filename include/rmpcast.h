@@ -1,0 +1,188 @@
+/*
+ * rmpcast.h -- C ABI of the MI355X raycast-and-policy library (librmpcast.so).
+ *
+ * The library evaluates the raycasting obstacle-avoidance policy of Pantic et al.,
+ * "Obstacle avoidance using raycasting and Riemannian Motion Policies at kHz rates for
+ * MAVs": for a robot state (position x, velocity xdot) it casts N Halton rays through a
+ * voxel map kept on the GPU, evaluates one obstacle policy (f_i, A_i) per ray, metric-sums
+ * them and resolves  f = (sum A_i)^+ sum A_i f_i  (Sec. III-A Eq. 1, Sec. III-E Eq. 11).
+ * The LiDAR variant takes beam directions and ranges from a point cloud instead of casting
+ * rays (Sec. III-G).  All GPU work runs in the library's own HIP kernels for gfx950.
+ *
+ * Conventions for every call:
+ *   - Every call returns an rmpc_status.  On error nothing is written to any output and
+ *     rmpc_last_error() (thread-local) describes the failure.
+ *   - "dev" pointers are device memory of the context's GPU; "host" pointers are ordinary
+ *     host memory.  The library never frees memory it did not allocate.
+ *   - hip_stream is a hipStream_t (NULL = the default stream).  Blocking calls enqueue on
+ *     it and synchronise it before returning.
+ *   - A context is used by one thread at a time.
+ *   - Lengths are metres, times seconds, velocities metres per second.
+ */
+#ifndef RMPCAST_H
+#define RMPCAST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rmpc_ctx rmpc_ctx;
+
+typedef enum {
+    RMPC_OK = 0,
+    RMPC_E_INVALID = -1,        /* bad argument: NULL, NaN/Inf, size out of range, bad dtype */
+    RMPC_E_NOMAP = -2,          /* unknown or released map id */
+    RMPC_E_OUT_OF_BOUNDS = -3,  /* query position outside the map's grid */
+    RMPC_E_NOMEM = -4,          /* the caller's device arena has no room */
+    RMPC_E_HIP = -5,            /* a HIP runtime call failed */
+    RMPC_E_STOPPED = -6         /* reserved for the serving loop */
+} rmpc_status;
+
+/* Voxel storage (reading: a voxel is occupied when its TSDF value at the centre is <= 0;
+ * for occupancy bytes when the byte is non-zero). */
+typedef enum {
+    RMPC_TSDF_F32 = 0,          /* float32 truncated signed distance */
+    RMPC_TSDF_F16 = 1,          /* IEEE binary16 bit patterns (uint16) */
+    RMPC_OCC_U8 = 2             /* uint8 occupancy */
+} rmpc_dtype;
+
+/* A dense voxel grid.  Voxel (i, j, k) has its centre at origin_m + (idx + 1/2) voxel_m and
+ * logical index lin = i + nx * (j + ny * k) (x fastest). */
+typedef struct {
+    int32_t nx, ny, nz;
+    int32_t dtype;              /* rmpc_dtype */
+    double voxel_m;
+    double origin_m[3];         /* world coordinate of the grid's minimum corner */
+} rmpc_map_desc;
+
+/* Policy parameters: the Table I columns ("Static Map" or "LiDAR") plus constants the paper
+ * leaves open. */
+typedef struct {
+    double c;                   /* soft-normalisation parameter (Eq. 4) */
+    double eta_rep, nu_rep;     /* repulsive gain and length scale (Eq. 6) */
+    double eta_damp, nu_damp;   /* damping gain and length scale (Eq. 8) */
+    double radius;              /* policy radius r of the weight w_r (Eq. 9) */
+    double eps;                 /* 0 < eps << 1 in the damping denominator (Eq. 8) */
+    double max_range_m;         /* rays with no occupied voxel within this range miss */
+    double rank_tol;            /* pseudo-inverse keeps eigenvalues > rank_tol * lambda_max */
+    double min_range_m;         /* scan points closer than this are skipped */
+} rmpc_params;
+
+/* Query flags. */
+#define RMPC_Q_ILL 1u            /* an eigenvalue within 10x of the pseudo-inverse cut, or the
+                                    kept condition number exceeds 1e3 */
+#define RMPC_Q_IN_COLLISION 2u   /* the start voxel is occupied: every ray hits at distance 0 */
+#define RMPC_Q_TIE 4u            /* some ray met two face crossings within 1e-5 voxel */
+
+/* Per-ray debug flags (rmpc_trace_debug). */
+#define RMPC_RAY_TIE 1u          /* two face crossings within 1e-5 voxel on the ray's path */
+#define RMPC_RAY_RANGE_TIE 2u    /* a face crossing within 1e-5 voxel of max_range */
+#define RMPC_RAY_START_FACE 4u   /* the start lies within 1e-5 voxel of a face */
+#define RMPC_RAY_IN_COLLISION 8u /* the start voxel is occupied */
+
+/* The combined policy of one query (Eq. 1): f = A^+ b with A = sum A_i, b = sum A_i f_i. */
+typedef struct {
+    double f[3];                /* resolved acceleration, float64 */
+    double A[9];                /* sum of per-ray metrics, row major (float32 compensated sums) */
+    double b[3];                /* sum of A_i (f_rep,i + f_damp,i) */
+    double lambda[3];           /* eigenvalues of A, ascending */
+    int32_t rank;               /* eigenvalues kept by the pseudo-inverse */
+    int32_t n_hit;              /* rays (or valid scan points) with an obstacle */
+    int32_t n_contrib;          /* hits with d < radius and xdot . r > 0 (non-zero metric) */
+    int32_t n_tie;              /* rays carrying RMPC_RAY_TIE */
+    uint32_t flags;             /* RMPC_Q_* */
+    int32_t n_rays;             /* rays cast (or scan points read) */
+    int64_t visits;             /* voxels read over all rays (start voxel included) */
+} rmpc_result;
+
+/* Largest ray count per query (the Halton table length). */
+#define RMPC_MAX_RAYS 65536
+
+/*
+ * rmpc_create -- open a context on GPU `device`.
+ *   arena_dev, arena_bytes: a caller-owned device buffer on that GPU from which the library
+ *     sub-allocates everything it keeps on the device (maps, the ray-direction table,
+ *     reduction partials).  It must stay valid until rmpc_destroy.  At least 2 MiB.
+ *   out: receives the context.
+ * Computes the float32 Halton direction table (Sec. III-E Eq. 10) for RMPC_MAX_RAYS rays on
+ * the device.  Errors: RMPC_E_INVALID (NULL, too small), RMPC_E_HIP.
+ */
+rmpc_status rmpc_create(int device, void *arena_dev, size_t arena_bytes, rmpc_ctx **out);
+
+/* rmpc_destroy -- release the context's pinned host buffers and the context itself.  The
+ * arena stays the caller's.  NULL is accepted. */
+rmpc_status rmpc_destroy(rmpc_ctx *ctx);
+
+/*
+ * rmpc_map_upload -- make a voxel map resident on the GPU ("the map is kept in GPU memory and
+ * shared between all kernels", Sec. III-F).
+ *   desc: grid geometry and storage type; 1 <= nx, ny, nz <= 4096, voxel_m > 0.
+ *   voxels: nx*ny*nz elements of the dtype in logical x-fastest order; host memory when
+ *     voxels_on_device == 0, device memory of the context's GPU otherwise.  Only read during
+ *     the call.
+ *   map_id_out: receives an id >= 0.
+ * The library re-lays the grid into cache-line bricks inside the arena.  Blocking.
+ * Errors: RMPC_E_INVALID, RMPC_E_NOMEM (arena full), RMPC_E_HIP.
+ */
+rmpc_status rmpc_map_upload(rmpc_ctx *ctx, const rmpc_map_desc *desc, const void *voxels,
+                            int voxels_on_device, void *hip_stream, int32_t *map_id_out);
+
+/* rmpc_map_release -- free a map's arena space.  Errors: RMPC_E_NOMAP. */
+rmpc_status rmpc_map_release(rmpc_ctx *ctx, int32_t map_id);
+
+/*
+ * rmpc_query -- the raycasting policy P_ray of one robot state (Sec. III-E Eq. 11).
+ *   x, v: position (world, metres) and velocity, float64 host arrays of 3.
+ *   n_rays: 1 <= n_rays <= RMPC_MAX_RAYS; rays are Halton indices 0 .. n_rays-1.
+ *   params: policy parameters (all finite; c, nu_rep, nu_damp, radius, eps, max_range_m > 0).
+ *   out: host struct receiving the combined policy.
+ * The start grid coordinate is g = float32((x - origin) / voxel_m).  A ray's distance is
+ * where it enters the first occupied voxel (3-D DDA); rays with none within max_range_m or
+ * leaving the grid contribute nothing.  Blocking.
+ * Errors: RMPC_E_INVALID, RMPC_E_NOMAP, RMPC_E_OUT_OF_BOUNDS, RMPC_E_HIP.
+ */
+rmpc_status rmpc_query(rmpc_ctx *ctx, int32_t map_id, const double x[3], const double v[3],
+                       int32_t n_rays, const rmpc_params *params, void *hip_stream,
+                       rmpc_result *out);
+
+/*
+ * rmpc_scan_query -- the LiDAR policy (Sec. III-G): each point p gives direction p/|p| and
+ * distance |p|.
+ *   points_dev: n_points x 3 float32 on the device, robot-relative in a world-aligned frame;
+ *     non-finite points and points with |p| < min_range_m (dropouts as (0,0,0)) are skipped.
+ *   n_points: 0 <= n_points <= 2^24.
+ *   v: velocity in the same frame.  Blocking.
+ * Errors: RMPC_E_INVALID, RMPC_E_HIP.
+ */
+rmpc_status rmpc_scan_query(rmpc_ctx *ctx, const float *points_dev, int32_t n_points,
+                            const double v[3], const rmpc_params *params, void *hip_stream,
+                            rmpc_result *out);
+
+/*
+ * rmpc_trace_debug -- per-ray traversal results of a query, for parity tests.
+ *   hit_lin_dev[n_rays]: logical index of the hit voxel, -1 on a miss.
+ *   dist_dev[n_rays]: distance in metres to where the ray enters it (float64), +inf on a miss.
+ *   flags_dev[n_rays]: RMPC_RAY_* flags.
+ *   visits_dev[n_rays]: voxels read by the ray (start voxel included); may be NULL.
+ * All output buffers are device memory.  Only params->max_range_m is used.  Blocking.
+ * Errors: as rmpc_query.
+ */
+rmpc_status rmpc_trace_debug(rmpc_ctx *ctx, int32_t map_id, const double x[3], int32_t n_rays,
+                             const rmpc_params *params, void *hip_stream, int32_t *hit_lin_dev,
+                             double *dist_dev, uint8_t *flags_dev, int32_t *visits_dev);
+
+/* rmpc_directions -- copy the first n (1 <= n <= RMPC_MAX_RAYS) ray directions, float32
+ * x,y,z triples, into host memory out_host[3n] (Sec. III-E Eq. 10). */
+rmpc_status rmpc_directions(rmpc_ctx *ctx, int32_t n, float *out_host);
+
+/* rmpc_last_error -- text of the calling thread's last error ("" if none). */
+const char *rmpc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RMPCAST_H */

@@ -66,7 +66,7 @@ typedef struct {
     double lam[3];        /* eigenvalues of S, ascending */
     int32_t rank;
     int32_t n_hit;        /* rays that hit an occupied voxel within range */
-    int32_t n_contrib;    /* rays whose metric is non-zero */
+    int32_t n_contrib;    /* hits with d < radius and xdot . r > 0: non-zero metric */
     int32_t n_tie;        /* rays carrying the TIE flag */
     uint32_t flags;       /* query flags: ORC_Q_* */
     int32_t pad;
@@ -511,11 +511,13 @@ void orc_combine(const orc_params *p, const double *rhat, const double *d, const
         if (hit[i] < 0) continue;                 /* a miss contributes nothing (R9) */
         n_hit++;
         double A[9], b[3];
-        orc_rmp_ray(p, rhat + 3 * (int64_t)i, d[i], v, A, b);
-        int nz = 0;
-        for (int k = 0; k < 9; ++k) { nadd(&SA[k], A[k]); nz |= A[k] != 0.0; }
+        const double *rh = rhat + 3 * (int64_t)i;
+        orc_rmp_ray(p, rh, d[i], v, A, b);
+        for (int k = 0; k < 9; ++k) nadd(&SA[k], A[k]);
         for (int k = 0; k < 3; ++k) nadd(&sb[k], b[k]);
-        n_contrib += nz;
+        /* the metric is non-zero exactly when w_r(d) > 0 and g_obs != 0 */
+        double vn = -(v[0] * -rh[0] + v[1] * -rh[1] + v[2] * -rh[2]);
+        n_contrib += d[i] < p->radius && vn > 0.0;
     }
     for (int k = 0; k < 9; ++k) out->S[k] = SA[k].s + SA[k].c;
     for (int k = 0; k < 3; ++k) out->b[k] = sb[k].s + sb[k].c;

@@ -1,0 +1,234 @@
+"""ctypes binding of ``librmpcast.so`` (the C ABI in ``include/rmpcast.h``).
+
+The functions named ``rmpc_*`` marshal arguments for the C entry point of the same name and
+nothing else; every step of a query runs in the library's HIP kernels.  PyTorch supplies the
+device memory (the arena and scan buffers) and streams.  There is no fallback: if the
+library is missing or fails to load, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Dict, Optional, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librmpcast.so")
+
+RMPC_OK, RMPC_E_INVALID, RMPC_E_NOMAP, RMPC_E_OUT_OF_BOUNDS = 0, -1, -2, -3
+RMPC_E_NOMEM, RMPC_E_HIP, RMPC_E_STOPPED = -4, -5, -6
+RMPC_TSDF_F32, RMPC_TSDF_F16, RMPC_OCC_U8 = 0, 1, 2
+DTYPES = {"f32": RMPC_TSDF_F32, "f16": RMPC_TSDF_F16, "u8": RMPC_OCC_U8}
+Q_ILL, Q_IN_COLLISION, Q_TIE = 1, 2, 4
+RAY_TIE, RAY_RANGE_TIE, RAY_START_FACE, RAY_IN_COLLISION = 1, 2, 4, 8
+MAX_RAYS = 65536
+
+
+class RmpcError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where} failed with status {status}: {msg}")
+        self.status = status
+
+
+class MapDesc(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("dtype", C.c_int32),
+                ("voxel_m", C.c_double), ("origin_m", C.c_double * 3)]
+
+
+class Params(C.Structure):
+    _fields_ = [(k, C.c_double) for k in ("c", "eta_rep", "nu_rep", "eta_damp", "nu_damp", "radius",
+                                          "eps", "max_range_m", "rank_tol", "min_range_m")]
+
+
+class Result(C.Structure):
+    _fields_ = [("f", C.c_double * 3), ("A", C.c_double * 9), ("b", C.c_double * 3),
+                ("lam", C.c_double * 3), ("rank", C.c_int32), ("n_hit", C.c_int32),
+                ("n_contrib", C.c_int32), ("n_tie", C.c_int32), ("flags", C.c_uint32),
+                ("n_rays", C.c_int32), ("visits", C.c_int64)]
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run paper_2301_08068_amd/build.py")
+_lib = C.CDLL(LIB_PATH)
+_P = C.POINTER
+_lib.rmpc_last_error.restype = C.c_char_p
+_lib.rmpc_last_error.argtypes = []
+_SIGS = {
+    "rmpc_create": [C.c_int, C.c_void_p, C.c_size_t, _P(C.c_void_p)],
+    "rmpc_destroy": [C.c_void_p],
+    "rmpc_map_upload": [C.c_void_p, _P(MapDesc), C.c_void_p, C.c_int, C.c_void_p, _P(C.c_int32)],
+    "rmpc_map_release": [C.c_void_p, C.c_int32],
+    "rmpc_query": [C.c_void_p, C.c_int32, _P(C.c_double), _P(C.c_double), C.c_int32, _P(Params),
+                   C.c_void_p, _P(Result)],
+    "rmpc_scan_query": [C.c_void_p, C.c_void_p, C.c_int32, _P(C.c_double), _P(Params), C.c_void_p,
+                        _P(Result)],
+    "rmpc_trace_debug": [C.c_void_p, C.c_int32, _P(C.c_double), C.c_int32, _P(Params), C.c_void_p,
+                         C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+    "rmpc_directions": [C.c_void_p, C.c_int32, _P(C.c_float)],
+}
+for _name, _args in _SIGS.items():
+    getattr(_lib, _name).argtypes = _args
+    getattr(_lib, _name).restype = C.c_int
+
+
+def exported_symbols():
+    """Names of the C entry points this binding resolves."""
+    return sorted(list(_SIGS) + ["rmpc_last_error"])
+
+
+def _check(st: int, where: str):
+    if st != RMPC_OK:
+        raise RmpcError(st, where, _lib.rmpc_last_error().decode())
+
+
+def _d3(x):
+    a = (C.c_double * 3)(*[float(v) for v in np.asarray(x, dtype=np.float64).reshape(3)])
+    return a
+
+
+def params_struct(p: Dict[str, float]) -> Params:
+    return Params(p["c"], p["eta_rep"], p["nu_rep"], p["eta_damp"], p["nu_damp"], p["radius"],
+                  p["eps"], p["max_range"], p["rank_tol"], p["min_range"])
+
+
+def result_dict(r: Result) -> Dict:
+    return dict(f=np.array(r.f[:]), S=np.array(r.A[:]).reshape(3, 3), b=np.array(r.b[:]),
+                lam=np.array(r.lam[:]), rank=r.rank, n_hit=r.n_hit, n_contrib=r.n_contrib,
+                n_tie=r.n_tie, flags=r.flags, n_rays=r.n_rays, visits=r.visits)
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return int(stream)
+
+
+# ----------------------------------------------------------------------------- C entry points
+
+def rmpc_create(device: int, arena_ptr: int, arena_bytes: int) -> int:
+    out = C.c_void_p()
+    _check(_lib.rmpc_create(device, C.c_void_p(arena_ptr), arena_bytes, C.byref(out)), "rmpc_create")
+    return out.value
+
+
+def rmpc_destroy(ctx: int) -> None:
+    _check(_lib.rmpc_destroy(C.c_void_p(ctx)), "rmpc_destroy")
+
+
+def rmpc_map_upload(ctx: int, nx: int, ny: int, nz: int, dtype: str, voxel_m: float, origin_m,
+                    voxels_ptr: int, on_device: bool, stream=None) -> int:
+    desc = MapDesc(nx, ny, nz, DTYPES[dtype], float(voxel_m), _d3(origin_m))
+    mid = C.c_int32(-1)
+    _check(_lib.rmpc_map_upload(C.c_void_p(ctx), C.byref(desc), C.c_void_p(voxels_ptr),
+                                int(bool(on_device)), C.c_void_p(_stream_ptr(stream)), C.byref(mid)),
+           "rmpc_map_upload")
+    return mid.value
+
+
+def rmpc_map_release(ctx: int, map_id: int) -> None:
+    _check(_lib.rmpc_map_release(C.c_void_p(ctx), map_id), "rmpc_map_release")
+
+
+def rmpc_query(ctx: int, map_id: int, x, v, n_rays: int, params: Dict[str, float], stream=None) -> Dict:
+    r = Result()
+    ps = params_struct(params)
+    _check(_lib.rmpc_query(C.c_void_p(ctx), map_id, _d3(x), _d3(v), int(n_rays), C.byref(ps),
+                           C.c_void_p(_stream_ptr(stream)), C.byref(r)), "rmpc_query")
+    return result_dict(r)
+
+
+def rmpc_scan_query(ctx: int, points_ptr: int, n_points: int, v, params: Dict[str, float],
+                    stream=None) -> Dict:
+    r = Result()
+    ps = params_struct(params)
+    _check(_lib.rmpc_scan_query(C.c_void_p(ctx), C.c_void_p(points_ptr), int(n_points), _d3(v),
+                                C.byref(ps), C.c_void_p(_stream_ptr(stream)), C.byref(r)),
+           "rmpc_scan_query")
+    return result_dict(r)
+
+
+def rmpc_trace_debug(ctx: int, map_id: int, x, n_rays: int, params: Dict[str, float], hit_ptr: int,
+                     dist_ptr: int, flags_ptr: int, visits_ptr: int = 0, stream=None) -> None:
+    ps = params_struct(params)
+    _check(_lib.rmpc_trace_debug(C.c_void_p(ctx), map_id, _d3(x), int(n_rays), C.byref(ps),
+                                 C.c_void_p(_stream_ptr(stream)), C.c_void_p(hit_ptr),
+                                 C.c_void_p(dist_ptr), C.c_void_p(flags_ptr),
+                                 C.c_void_p(visits_ptr or None)), "rmpc_trace_debug")
+
+
+def rmpc_directions(ctx: int, n: int) -> np.ndarray:
+    out = np.empty((n, 3), dtype=np.float32)
+    _check(_lib.rmpc_directions(C.c_void_p(ctx), int(n), out.ctypes.data_as(_P(C.c_float))),
+           "rmpc_directions")
+    return out
+
+
+# ----------------------------------------------------------------------------- convenience
+
+class Context:
+    """A library context on ``cuda:device`` whose arena is a torch uint8 tensor."""
+
+    def __init__(self, device: int = 0, arena_bytes: int = 1 << 30):
+        import torch
+        self.device = device
+        self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device=f"cuda:{device}")
+        self.ptr = rmpc_create(device, self.arena.data_ptr(), arena_bytes)
+        self._keep = {}
+
+    def close(self):
+        if self.ptr:
+            rmpc_destroy(self.ptr)
+            self.ptr = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def upload(self, data: np.ndarray, voxel_m: float, origin_m, dtype: str = "f32",
+               on_device: bool = True) -> int:
+        """Upload a [nz, ny, nx] array (float32 TSDF, uint16 binary16 bits or uint8)."""
+        import torch
+        want = {"f32": np.float32, "f16": np.uint16, "u8": np.uint8}[dtype]
+        arr = np.ascontiguousarray(data, dtype=want)
+        nz, ny, nx = arr.shape
+        if on_device:
+            t = torch.from_numpy(arr.view(np.uint8).reshape(-1)).to(f"cuda:{self.device}")
+            mid = rmpc_map_upload(self.ptr, nx, ny, nz, dtype, voxel_m, origin_m, t.data_ptr(), True)
+            del t
+        else:
+            mid = rmpc_map_upload(self.ptr, nx, ny, nz, dtype, voxel_m, origin_m, arr.ctypes.data, False)
+        return mid
+
+    def release(self, map_id: int) -> None:
+        rmpc_map_release(self.ptr, map_id)
+
+    def query(self, map_id: int, x, v, n_rays: int, params: Dict[str, float]) -> Dict:
+        return rmpc_query(self.ptr, map_id, x, v, n_rays, params)
+
+    def scan_query(self, points, v, params: Dict[str, float]) -> Dict:
+        """points: a cuda float32 tensor [n, 3] (or a numpy array, uploaded here)."""
+        import torch
+        if isinstance(points, np.ndarray):
+            points = torch.from_numpy(np.ascontiguousarray(points, np.float32)).to(f"cuda:{self.device}")
+        assert points.dtype == torch.float32 and points.is_cuda and points.is_contiguous()
+        return rmpc_scan_query(self.ptr, points.data_ptr(), points.shape[0], v, params)
+
+    def trace(self, map_id: int, x, n_rays: int, params: Dict[str, float]) -> Dict[str, np.ndarray]:
+        import torch
+        dev = f"cuda:{self.device}"
+        hit = torch.empty(n_rays, dtype=torch.int32, device=dev)
+        dist = torch.empty(n_rays, dtype=torch.float64, device=dev)
+        flags = torch.empty(n_rays, dtype=torch.uint8, device=dev)
+        visits = torch.empty(n_rays, dtype=torch.int32, device=dev)
+        rmpc_trace_debug(self.ptr, map_id, x, n_rays, params, hit.data_ptr(), dist.data_ptr(),
+                         flags.data_ptr(), visits.data_ptr())
+        return dict(hit=hit.cpu().numpy(), d=dist.cpu().numpy(), flags=flags.cpu().numpy(),
+                    visits=visits.cpu().numpy())
+
+    def directions(self, n: int) -> np.ndarray:
+        return rmpc_directions(self.ptr, n)

@@ -1,0 +1,437 @@
+// capi.hip -- the C ABI (include/rmpcast.h): context, caller-owned device arena, resident
+// maps, argument validation and the blocking query calls.  Host code only; all per-ray
+// work runs in the kernels of raycast.hip and setup_kernels.hip.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+
+#include "rmpcast.h"
+#include "rmpc_kernels.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+rmpc_status fail(rmpc_status st, const std::string &msg)
+{
+    g_last_error = msg;
+    return st;
+}
+
+#define RMPC_HIP(call)                                                                    \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(RMPC_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_));   \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr size_t kMinArena = 2u << 20;
+constexpr int kMaxDim = 4096;
+
+// First-fit sub-allocator over the caller's arena (offsets only; never touches memory).
+class Arena {
+  public:
+    void init(size_t bytes) { free_.clear(); free_[0] = bytes; }
+    bool alloc(size_t bytes, size_t *off)
+    {
+        bytes = (bytes + kAlign - 1) / kAlign * kAlign;
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                const size_t rest = it->second - bytes;
+                const size_t noff = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[noff] = rest;
+                used_[*off] = bytes;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off)
+    {
+        auto u = used_.find(off);
+        if (u == used_.end()) return;
+        size_t start = off, len = u->second;
+        used_.erase(u);
+        auto nx = free_.lower_bound(start);
+        if (nx != free_.end() && start + len == nx->first) { len += nx->second; nx = free_.erase(nx); }
+        if (nx != free_.begin()) {
+            auto pv = std::prev(nx);
+            if (pv->first + pv->second == start) { start = pv->first; len += pv->second; free_.erase(pv); }
+        }
+        free_[start] = len;
+    }
+
+  private:
+    std::map<size_t, size_t> free_, used_;
+};
+
+struct MapEntry {
+    rmpc_map_desc desc;
+    rmpc::MapView view;
+    size_t off;
+};
+
+}  // namespace
+
+struct rmpc_ctx {
+    int device;
+    uint8_t *arena;
+    size_t arena_bytes;
+    Arena alloc;
+    float *dirs;            // structure of arrays, RMPC_MAX_RAYS per component
+    float *partials;
+    uint32_t *ticket;
+    rmpc_result *result_host;   // pinned, written by the kernels
+    std::map<int32_t, MapEntry> maps;
+    int32_t next_map_id;
+};
+
+namespace {
+
+// Runs a call with the context's device current, restoring the caller's afterwards.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+bool finite3(const double *p) { return p && std::isfinite(p[0]) && std::isfinite(p[1]) && std::isfinite(p[2]); }
+
+rmpc_status check_params(const rmpc_params *p)
+{
+    if (!p) return fail(RMPC_E_INVALID, "params is NULL");
+    const double vals[] = {p->c, p->eta_rep, p->nu_rep, p->eta_damp, p->nu_damp, p->radius,
+                           p->eps, p->max_range_m, p->rank_tol, p->min_range_m};
+    for (double v : vals)
+        if (!std::isfinite(v)) return fail(RMPC_E_INVALID, "non-finite policy parameter");
+    if (!(p->c > 0 && p->nu_rep > 0 && p->nu_damp > 0 && p->radius > 0 && p->eps > 0 &&
+          p->max_range_m > 0 && p->rank_tol >= 0 && p->min_range_m >= 0 && p->eta_rep >= 0 &&
+          p->eta_damp >= 0))
+        return fail(RMPC_E_INVALID, "policy parameter out of range");
+    return RMPC_OK;
+}
+
+rmpc::PolicyF policy_f(const rmpc_params *p, const double v[3])
+{
+    rmpc::PolicyF P;
+    P.vx = (float)v[0];
+    P.vy = (float)v[1];
+    P.vz = (float)v[2];
+    P.c = (float)p->c;
+    P.eta_rep = (float)p->eta_rep;
+    P.inv_nu_rep = (float)(1.0 / p->nu_rep);
+    P.eta_damp = (float)p->eta_damp;
+    P.inv_nu_damp = (float)(1.0 / p->nu_damp);
+    P.radius = (float)p->radius;
+    P.inv_radius = (float)(1.0 / p->radius);
+    P.eps = (float)p->eps;
+    return P;
+}
+
+int ilog2(int v)
+{
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+// Brick edge (log2) per axis for a storage type: about 128-256 bytes per brick.
+void brick_shape(int dtype, int lb[3])
+{
+    lb[0] = lb[1] = lb[2] = 2;                      // 4 x 4 x 4
+    if (dtype == RMPC_OCC_U8) lb[0] = 3;             // 8 x 4 x 4 bytes
+    if (const char *e = std::getenv("RMPC_BRICK_LOG2")) {
+        int a, b, c;
+        if (std::sscanf(e, "%d,%d,%d", &a, &b, &c) == 3 && a >= 0 && b >= 0 && c >= 0 &&
+            a <= 4 && b <= 4 && c <= 4) {
+            lb[0] = a; lb[1] = b; lb[2] = c;
+        }
+    }
+}
+
+size_t elem_bytes(int dtype) { return dtype == RMPC_TSDF_F32 ? 4 : (dtype == RMPC_TSDF_F16 ? 2 : 1); }
+
+// Validates the query state and fills the geometry part of RayArgs.
+rmpc_status setup_query(rmpc_ctx *ctx, int32_t map_id, const double x[3], int32_t n_rays,
+                        const rmpc_params *params, rmpc::RayArgs &A, const MapEntry **me_out)
+{
+    if (!ctx) return fail(RMPC_E_INVALID, "ctx is NULL");
+    if (!finite3(x)) return fail(RMPC_E_INVALID, "position is NULL or not finite");
+    if (n_rays < 1 || n_rays > RMPC_MAX_RAYS) return fail(RMPC_E_INVALID, "n_rays out of [1, 65536]");
+    if (rmpc_status st = check_params(params)) return st;
+    auto it = ctx->maps.find(map_id);
+    if (it == ctx->maps.end()) return fail(RMPC_E_NOMAP, "unknown map id");
+    const MapEntry &me = it->second;
+    const int32_t n[3] = {me.desc.nx, me.desc.ny, me.desc.nz};
+    std::memset(&A, 0, sizeof A);
+    uint32_t start_flags = 0;
+    for (int a = 0; a < 3; ++a) {
+        const float g = (float)((x[a] - me.desc.origin_m[a]) / me.desc.voxel_m);
+        if (!(g >= 0.0f) || !(g < (float)n[a])) return fail(RMPC_E_OUT_OF_BOUNDS, "position outside the grid");
+        A.g[a] = g;
+        A.v0[a] = (int32_t)std::floor(g);
+        const double fr = (double)g - std::floor((double)g);
+        if (fr < 1e-5 || 1.0 - fr < 1e-5) start_flags |= RMPC_RAY_START_FACE;
+    }
+    A.map = me.view;
+    A.dirs = ctx->dirs;
+    A.dir_stride = RMPC_MAX_RAYS;
+    A.n_rays = n_rays;
+    A.lin0 = A.v0[0] + n[0] * (A.v0[1] + n[1] * A.v0[2]);
+    A.start_flags = start_flags;
+    const double tmax = params->max_range_m / me.desc.voxel_m;
+    A.tmax_lo = (float)(tmax * (1.0 - 1e-6) - 2e-5);
+    A.tmax_hi = (float)(tmax * (1.0 + 1e-6) + 2e-5);
+    A.max_range = params->max_range_m;
+    A.h = me.desc.voxel_m;
+    A.radius64 = params->radius;
+    A.rank_tol = params->rank_tol;
+    A.partials = ctx->partials;
+    A.ticket = ctx->ticket;
+    A.result = ctx->result_host;
+    *me_out = &me;
+    return RMPC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *rmpc_last_error(void) { return g_last_error.c_str(); }
+
+rmpc_status rmpc_create(int device, void *arena_dev, size_t arena_bytes, rmpc_ctx **out)
+{
+    if (!out || !arena_dev) return fail(RMPC_E_INVALID, "NULL argument");
+    if (arena_bytes < kMinArena) return fail(RMPC_E_INVALID, "arena smaller than 2 MiB");
+    int ndev = 0;
+    RMPC_HIP(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(RMPC_E_INVALID, "no such device");
+    DeviceGuard dg(device);
+    hipPointerAttribute_t attr;
+    RMPC_HIP(hipPointerGetAttributes(&attr, arena_dev));
+    if (attr.type != hipMemoryTypeDevice || attr.device != device)
+        return fail(RMPC_E_INVALID, "arena is not device memory of this GPU");
+    rmpc_ctx *c = new rmpc_ctx();
+    c->device = device;
+    c->arena = static_cast<uint8_t *>(arena_dev);
+    c->arena_bytes = arena_bytes;
+    c->alloc.init(arena_bytes);
+    c->next_map_id = 0;
+    size_t o_dirs, o_part, o_ticket;
+    if (!c->alloc.alloc(sizeof(float) * 3 * RMPC_MAX_RAYS, &o_dirs) ||
+        !c->alloc.alloc(sizeof(float) * rmpc::kMaxPartialSlots * 32, &o_part) ||
+        !c->alloc.alloc(256, &o_ticket)) {
+        delete c;
+        return fail(RMPC_E_NOMEM, "arena too small for the context tables");
+    }
+    c->dirs = reinterpret_cast<float *>(c->arena + o_dirs);
+    c->partials = reinterpret_cast<float *>(c->arena + o_part);
+    c->ticket = reinterpret_cast<uint32_t *>(c->arena + o_ticket);
+    hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&c->result_host), sizeof(rmpc_result),
+                                 hipHostMallocCoherent);
+    if (e != hipSuccess) {
+        delete c;
+        return fail(RMPC_E_HIP, std::string("hipHostMalloc: ") + hipGetErrorString(e));
+    }
+    std::memset(c->result_host, 0, sizeof(rmpc_result));
+    rmpc::DirsArgs da{c->dirs, RMPC_MAX_RAYS};
+    e = hipMemsetAsync(c->ticket, 0, 256, nullptr);
+    if (e == hipSuccess) e = rmpc::launch_directions(da, nullptr);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) {
+        (void)hipHostFree(c->result_host);
+        delete c;
+        return fail(RMPC_E_HIP, std::string("context setup: ") + hipGetErrorString(e));
+    }
+    *out = c;
+    return RMPC_OK;
+}
+
+rmpc_status rmpc_destroy(rmpc_ctx *ctx)
+{
+    if (!ctx) return RMPC_OK;
+    DeviceGuard dg(ctx->device);
+    (void)hipDeviceSynchronize();
+    (void)hipHostFree(ctx->result_host);
+    delete ctx;
+    return RMPC_OK;
+}
+
+rmpc_status rmpc_map_upload(rmpc_ctx *ctx, const rmpc_map_desc *desc, const void *voxels,
+                            int voxels_on_device, void *hip_stream, int32_t *map_id_out)
+{
+    if (!ctx || !desc || !voxels || !map_id_out) return fail(RMPC_E_INVALID, "NULL argument");
+    if (desc->nx < 1 || desc->ny < 1 || desc->nz < 1 || desc->nx > kMaxDim || desc->ny > kMaxDim ||
+        desc->nz > kMaxDim)
+        return fail(RMPC_E_INVALID, "grid dimensions out of [1, 4096]");
+    if (desc->dtype != RMPC_TSDF_F32 && desc->dtype != RMPC_TSDF_F16 && desc->dtype != RMPC_OCC_U8)
+        return fail(RMPC_E_INVALID, "unknown dtype");
+    if (!(desc->voxel_m > 0) || !std::isfinite(desc->voxel_m) || !finite3(desc->origin_m))
+        return fail(RMPC_E_INVALID, "voxel size or origin invalid");
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    int lb[3];
+    brick_shape(desc->dtype, lb);
+    rmpc::MapView v;
+    std::memset(&v, 0, sizeof v);
+    v.nx = desc->nx; v.ny = desc->ny; v.nz = desc->nz; v.dtype = desc->dtype;
+    v.lbx = lb[0]; v.lby = lb[1]; v.lbz = lb[2];
+    v.nbx = (desc->nx + (1 << lb[0]) - 1) >> lb[0];
+    v.nby = (desc->ny + (1 << lb[1]) - 1) >> lb[1];
+    v.nbz = (desc->nz + (1 << lb[2]) - 1) >> lb[2];
+    const uint64_t n_dst = (uint64_t)v.nbx * v.nby * v.nbz << (lb[0] + lb[1] + lb[2]);
+    if (n_dst >= (1ull << 32)) return fail(RMPC_E_INVALID, "grid too large for 32-bit voxel offsets");
+    const size_t eb = elem_bytes(desc->dtype);
+    size_t off;
+    if (!ctx->alloc.alloc(n_dst * eb, &off)) return fail(RMPC_E_NOMEM, "arena full (map)");
+    v.data = ctx->arena + off;
+    const size_t n_log = (size_t)desc->nx * desc->ny * desc->nz;
+    const void *src = voxels;
+    size_t tmp_off = 0;
+    bool tmp = false;
+    if (!voxels_on_device) {
+        if (!ctx->alloc.alloc(n_log * eb, &tmp_off)) {
+            ctx->alloc.release(off);
+            return fail(RMPC_E_NOMEM, "arena full (upload staging)");
+        }
+        tmp = true;
+        hipError_t e = hipMemcpyAsync(ctx->arena + tmp_off, voxels, n_log * eb, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) {
+            ctx->alloc.release(off);
+            ctx->alloc.release(tmp_off);
+            return fail(RMPC_E_HIP, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
+        }
+        src = ctx->arena + tmp_off;
+    }
+    rmpc::LayoutArgs la{src, v, (int32_t)eb, n_dst};
+    hipError_t e = rmpc::launch_layout(la, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (tmp) ctx->alloc.release(tmp_off);
+    if (e != hipSuccess) {
+        ctx->alloc.release(off);
+        return fail(RMPC_E_HIP, std::string("map layout: ") + hipGetErrorString(e));
+    }
+    const int32_t id = ctx->next_map_id++;
+    ctx->maps[id] = MapEntry{*desc, v, off};
+    *map_id_out = id;
+    return RMPC_OK;
+}
+
+rmpc_status rmpc_map_release(rmpc_ctx *ctx, int32_t map_id)
+{
+    if (!ctx) return fail(RMPC_E_INVALID, "ctx is NULL");
+    auto it = ctx->maps.find(map_id);
+    if (it == ctx->maps.end()) return fail(RMPC_E_NOMAP, "unknown map id");
+    DeviceGuard dg(ctx->device);
+    RMPC_HIP(hipDeviceSynchronize());
+    ctx->alloc.release(it->second.off);
+    ctx->maps.erase(it);
+    return RMPC_OK;
+}
+
+rmpc_status rmpc_query(rmpc_ctx *ctx, int32_t map_id, const double x[3], const double v[3],
+                       int32_t n_rays, const rmpc_params *params, void *hip_stream,
+                       rmpc_result *out)
+{
+    if (!out) return fail(RMPC_E_INVALID, "out is NULL");
+    if (!finite3(v)) return fail(RMPC_E_INVALID, "velocity is NULL or not finite");
+    rmpc::RayArgs A;
+    const MapEntry *me = nullptr;
+    if (rmpc_status st = setup_query(ctx, map_id, x, n_rays, params, A, &me)) return st;
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    A.pol = policy_f(params, v);
+    for (int a = 0; a < 3; ++a) A.vel64[a] = v[a];
+    RMPC_HIP(rmpc::launch_raycast(A, s, false));
+    RMPC_HIP(hipStreamSynchronize(s));
+    std::memcpy(out, ctx->result_host, sizeof(rmpc_result));
+    return RMPC_OK;
+}
+
+rmpc_status rmpc_trace_debug(rmpc_ctx *ctx, int32_t map_id, const double x[3], int32_t n_rays,
+                             const rmpc_params *params, void *hip_stream, int32_t *hit_lin_dev,
+                             double *dist_dev, uint8_t *flags_dev, int32_t *visits_dev)
+{
+    if (!hit_lin_dev || !dist_dev || !flags_dev) return fail(RMPC_E_INVALID, "NULL output");
+    rmpc::RayArgs A;
+    const MapEntry *me = nullptr;
+    if (rmpc_status st = setup_query(ctx, map_id, x, n_rays, params, A, &me)) return st;
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    A.dbg_hit = hit_lin_dev;
+    A.dbg_dist = dist_dev;
+    A.dbg_flags = flags_dev;
+    A.dbg_visits = visits_dev;
+    RMPC_HIP(rmpc::launch_raycast(A, s, true));
+    RMPC_HIP(hipStreamSynchronize(s));
+    return RMPC_OK;
+}
+
+rmpc_status rmpc_scan_query(rmpc_ctx *ctx, const float *points_dev, int32_t n_points,
+                            const double v[3], const rmpc_params *params, void *hip_stream,
+                            rmpc_result *out)
+{
+    if (!ctx || !out) return fail(RMPC_E_INVALID, "NULL argument");
+    if (n_points < 0 || n_points > (1 << 24)) return fail(RMPC_E_INVALID, "n_points out of [0, 2^24]");
+    if (n_points > 0 && !points_dev) return fail(RMPC_E_INVALID, "points_dev is NULL");
+    if (!finite3(v)) return fail(RMPC_E_INVALID, "velocity is NULL or not finite");
+    if (rmpc_status st = check_params(params)) return st;
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    rmpc::ScanArgs A;
+    std::memset(&A, 0, sizeof A);
+    A.points = points_dev;
+    A.n_points = n_points;
+    A.min_range2 = params->min_range_m * params->min_range_m;
+    for (int a = 0; a < 3; ++a) A.vel64[a] = v[a];
+    A.radius64 = params->radius;
+    A.pol = policy_f(params, v);
+    A.rank_tol = params->rank_tol;
+    A.partials = ctx->partials;
+    A.ticket = ctx->ticket;
+    A.result = ctx->result_host;
+    RMPC_HIP(rmpc::launch_scan(A, s));
+    RMPC_HIP(hipStreamSynchronize(s));
+    std::memcpy(out, ctx->result_host, sizeof(rmpc_result));
+    return RMPC_OK;
+}
+
+rmpc_status rmpc_directions(rmpc_ctx *ctx, int32_t n, float *out_host)
+{
+    if (!ctx || !out_host) return fail(RMPC_E_INVALID, "NULL argument");
+    if (n < 1 || n > RMPC_MAX_RAYS) return fail(RMPC_E_INVALID, "n out of [1, 65536]");
+    DeviceGuard dg(ctx->device);
+    float *tmp = static_cast<float *>(std::malloc(sizeof(float) * 3 * (size_t)n));
+    if (!tmp) return fail(RMPC_E_NOMEM, "host allocation failed");
+    hipError_t e = hipSuccess;
+    for (int a = 0; a < 3 && e == hipSuccess; ++a)
+        e = hipMemcpy(tmp + (size_t)a * n, ctx->dirs + (size_t)a * RMPC_MAX_RAYS, sizeof(float) * n,
+                      hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+        std::free(tmp);
+        return fail(RMPC_E_HIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
+    }
+    for (int32_t i = 0; i < n; ++i)
+        for (int a = 0; a < 3; ++a) out_host[3 * (size_t)i + a] = tmp[(size_t)a * n + i];
+    std::free(tmp);
+    return RMPC_OK;
+}
+
+}  // extern "C"

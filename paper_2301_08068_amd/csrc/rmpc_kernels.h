@@ -1,0 +1,93 @@
+// rmpc_kernels.h -- plain-data launch arguments shared by the C-ABI layer and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rmpcast.h"
+
+namespace rmpc {
+
+// Voxel visits planned ahead per lane and round of the traversal.
+constexpr int kLookahead = 4;
+
+// Block-partial slots of one reduction (one per block of a launch).
+constexpr int kMaxPartialSlots = 4096;
+
+// A resident map in brick layout.  Voxel (x, y, z) lives in brick
+// (x >> lbx, y >> lby, z >> lbz); bricks are stored x-fastest and voxels inside a brick
+// too, so a voxel's element offset is X(x) + Y(y) + Z(z), each term a function of one
+// coordinate only.
+struct MapView {
+    const void *data;
+    int32_t nx, ny, nz, dtype;
+    int32_t lbx, lby, lbz;       // log2 of the brick edge along each axis
+    int32_t nbx, nby, nbz;       // bricks along each axis
+};
+
+// Policy constants in float32 (reciprocals precomputed on the host).
+struct PolicyF {
+    float vx, vy, vz;            // robot velocity
+    float c, eta_rep, inv_nu_rep, eta_damp, inv_nu_damp, radius, inv_radius, eps;
+};
+
+// Everything one map query needs.
+struct RayArgs {
+    MapView map;
+    const float *dirs;           // direction table, structure of arrays: x[], y[], z[]
+    int32_t dir_stride;          // elements between the x, y and z arrays
+    int32_t n_rays;
+    float g[3];                  // start in grid units, float32((x - origin) / h)
+    int32_t v0[3];               // start voxel floor(g)
+    int32_t lin0;                // its logical index
+    uint32_t start_flags;        // RMPC_RAY_START_FACE when g is within 1e-5 of a face
+    float tmax_lo, tmax_hi;      // float32 guard band around max_range / h
+    double max_range, h;
+    double vel64[3];             // velocity, float64 (for the exact contribution count)
+    double radius64;
+    PolicyF pol;
+    double rank_tol;
+    float *partials;             // per-block partial sums
+    uint32_t *ticket;            // arrival counter, zero between launches
+    rmpc_result *result;         // written by the last block
+    // debug outputs (trace kernel only)
+    int32_t *dbg_hit;
+    double *dbg_dist;
+    uint8_t *dbg_flags;
+    int32_t *dbg_visits;
+};
+
+// LiDAR scan query.
+struct ScanArgs {
+    const float *points;         // n x 3 float32
+    int32_t n_points;
+    double min_range2;           // squared minimum range, float64
+    double vel64[3];
+    double radius64;
+    PolicyF pol;
+    double rank_tol;
+    float *partials;
+    uint32_t *ticket;
+    rmpc_result *result;
+};
+
+struct DirsArgs {
+    float *out;                  // structure of arrays with stride n
+    int32_t n;
+};
+
+struct LayoutArgs {
+    const void *src;             // logical x-fastest grid
+    MapView dst;                 // brick layout (data is the destination)
+    int32_t elem_bytes;
+    uint64_t n_dst;              // elements in the padded brick array
+};
+
+int ray_grid_blocks(int n_rays);
+int scan_grid_blocks(int n_points);
+hipError_t launch_raycast(const RayArgs &a, hipStream_t s, bool debug);
+hipError_t launch_scan(const ScanArgs &a, hipStream_t s);
+hipError_t launch_directions(const DirsArgs &a, hipStream_t s);
+hipError_t launch_layout(const LayoutArgs &a, hipStream_t s);
+
+}  // namespace rmpc

@@ -1,0 +1,90 @@
+// setup_kernels.hip -- one-time device work: the Halton ray-direction table and the
+// re-layout of an uploaded voxel grid into bricks.
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "rmpc_device.h"
+#include "rmpc_kernels.h"
+
+namespace rmpc {
+
+namespace {
+
+// Radical inverse (van der Corput) of i in base b: the base-b digits of i, mirrored about
+// the radix point, formed as an exact integer ratio num / b^k and rounded once.
+__device__ double radical_inverse(uint32_t i, uint32_t b)
+{
+    uint64_t num = 0, den = 1;
+    while (i != 0) {
+        num = num * b + i % b;
+        den *= b;
+        i /= b;
+    }
+    return (double)num / (double)den;
+}
+
+// Ray i of the 2-D Halton set (Sec. III-E, Eq. 10): polar angle from base 2, azimuth from
+// base 3.  cos(phi) = 1 - 2 H(i,2), sin(phi) = sqrt(1 - cos^2 phi), theta = 2 pi H(i,3);
+// float64 throughout, each component rounded to float32 once.
+__global__ void directions_kernel(DirsArgs A)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    const double u = radical_inverse((uint32_t)i, 2);
+    const double w = radical_inverse((uint32_t)i, 3);
+    const double z = 1.0 - 2.0 * u;
+    const double rho = sqrt(fmax(0.0, 1.0 - z * z));
+    double s, c;
+    sincospi(2.0 * w, &s, &c);
+    A.out[i] = (float)(rho * c);
+    A.out[i + A.n] = (float)(rho * s);
+    A.out[i + 2 * A.n] = (float)z;
+}
+
+// Fill the padded brick array from the logical x-fastest grid; padding holds a free value.
+template <typename T>
+__global__ void layout_kernel(LayoutArgs A, T pad)
+{
+    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= A.n_dst) return;
+    const MapView &m = A.dst;
+    const int lbv = m.lbx + m.lby + m.lbz;
+    const uint64_t brick = e >> lbv;
+    const uint32_t off = (uint32_t)(e & ((1u << lbv) - 1));
+    const int lx = off & ((1 << m.lbx) - 1);
+    const int ly = (off >> m.lbx) & ((1 << m.lby) - 1);
+    const int lz = off >> (m.lbx + m.lby);
+    const uint64_t bx = brick % (uint64_t)m.nbx;
+    const uint64_t by = (brick / (uint64_t)m.nbx) % (uint64_t)m.nby;
+    const uint64_t bz = brick / ((uint64_t)m.nbx * (uint64_t)m.nby);
+    const int64_t x = (int64_t)(bx << m.lbx) + lx;
+    const int64_t y = (int64_t)(by << m.lby) + ly;
+    const int64_t z = (int64_t)(bz << m.lbz) + lz;
+    T v = pad;
+    if (x < m.nx && y < m.ny && z < m.nz)
+        v = static_cast<const T *>(A.src)[x + (int64_t)m.nx * (y + (int64_t)m.ny * z)];
+    static_cast<T *>(const_cast<void *>(m.data))[e] = v;
+}
+
+}  // namespace
+
+hipError_t launch_directions(const DirsArgs &a, hipStream_t s)
+{
+    directions_kernel<<<(a.n + 255) / 256, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_layout(const LayoutArgs &a, hipStream_t s)
+{
+    const uint64_t blocks = (a.n_dst + 255) / 256;
+    switch (a.dst.dtype) {
+    case RMPC_TSDF_F32: layout_kernel<float><<<(unsigned)blocks, 256, 0, s>>>(a, 1.0f); break;
+    case RMPC_TSDF_F16: layout_kernel<uint16_t><<<(unsigned)blocks, 256, 0, s>>>(a, (uint16_t)0x3c00); break;
+    default: layout_kernel<uint8_t><<<(unsigned)blocks, 256, 0, s>>>(a, (uint8_t)0); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace rmpc

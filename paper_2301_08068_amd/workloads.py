@@ -380,7 +380,7 @@ def synth_scan(m: VoxelMap, x: np.ndarray, seed: int, n_elev: int = 64, n_azim: 
         t = np.minimum(t, _ray_enter(prim, np.asarray(x, dtype=np.float64), u))
     rng_m = t + rng.normal(0.0, noise_m, size=t.shape)
     keep = np.isfinite(t) & (t <= max_range_m) & (rng.uniform(size=t.shape) >= dropout)
-    pts = np.where(keep[:, None], u * rng_m[:, None], 0.0)
+    pts = u * np.where(keep, rng_m, 0.0)[:, None]
     return pts.astype(np.float32)
 
 

@@ -1,0 +1,212 @@
+"""GPU parity: the HIP path through the C ABI against the float64 oracle on the same seeded
+inputs (tiny 64^3 map over 1000 states, the 400^3 paper-shaped map at 65536 rays, the
+float16/uint8 encodings, LiDAR scans and edge cases)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from paper_2301_08068_amd import workloads as W  # noqa: E402
+from gpu_common import compare_query, compare_trace  # noqa: E402
+
+P_TINY = W.params("static", max_range=5.0)
+P_PAPER = W.params("static", max_range=10.0)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2301_08068_amd import binding
+    c = binding.Context(0, arena_bytes=1 << 30)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def tiny(ctx, tiny_map):
+    return ctx.upload(tiny_map.tsdf, tiny_map.voxel_m, tiny_map.origin_m, "f32"), \
+        oracle.OracleMap.from_voxelmap(tiny_map)
+
+
+@pytest.fixture(scope="module")
+def paper(ctx, paper_map):
+    return ctx.upload(paper_map.tsdf, paper_map.voxel_m, paper_map.origin_m, "f32"), \
+        oracle.OracleMap.from_voxelmap(paper_map)
+
+
+def test_direction_table_bit_equal(ctx):
+    gpu = ctx.directions(65536)
+    ref = oracle.directions(65536)
+    assert np.array_equal(gpu.view(np.uint32), ref.view(np.uint32))
+
+
+def test_tiny_trace_parity(ctx, tiny, tiny_map):
+    mid, om = tiny
+    dirs = oracle.directions(1024)
+    n_same = n_flag = 0
+    for seed in range(100, 300):
+        x, _ = W.free_state(tiny_map, seed)
+        g = ctx.trace(mid, x, 1024, P_TINY)
+        o = oracle.trace(om, oracle.grid_start(om, x), dirs, P_TINY["max_range"])
+        s, f = compare_trace(g, o, f"seed {seed}")
+        n_same += s
+        n_flag += f
+    print(f"tiny trace: {n_same} / {200 * 1024} rays identical, {n_flag} flagged")
+
+
+def test_tiny_query_parity_1000_states(ctx, tiny, tiny_map):
+    mid, om = tiny
+    dirs = oracle.directions(1024)
+    n_ill = 0
+    for seed in range(100, 1100):
+        x, v = W.free_state(tiny_map, seed)
+        g = ctx.query(mid, x, v, 1024, P_TINY)
+        o = oracle.query(om, x, v, 1024, P_TINY, dirs=dirs)
+        compare_query(g, o, f"seed {seed}")
+        n_ill += bool(o["flags"] & oracle.Q_ILL)
+    print(f"tiny queries: 1000 states, {n_ill} ILL")
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 1000, 4097, 65535, 65536])
+def test_ragged_ray_counts(ctx, tiny, tiny_map, n):
+    mid, om = tiny
+    x, v = W.free_state(tiny_map, 100 + n % 7)
+    g = ctx.query(mid, x, v, n, P_TINY)
+    o = oracle.query(om, x, v, n, P_TINY)
+    compare_query(g, o, f"n={n}")
+    assert g["n_rays"] == n
+
+
+def test_paper_map_parity_65536(ctx, paper, paper_map):
+    mid, om = paper
+    dirs = oracle.directions(65536)
+    for seed in (200, 201, 202):
+        x, v = W.free_state(paper_map, seed)
+        g = ctx.trace(mid, x, 65536, P_PAPER)
+        o = oracle.trace(om, oracle.grid_start(om, x), dirs, P_PAPER["max_range"], nthreads=8)
+        compare_trace(g, o, f"paper seed {seed}")
+        gq = ctx.query(mid, x, v, 65536, P_PAPER)
+        oq = oracle.query(om, x, v, 65536, P_PAPER, dirs=dirs, nthreads=8)
+        compare_query(gq, oq, f"paper seed {seed}")
+
+
+@pytest.mark.parametrize("enc", ["f16", "u8"])
+def test_encodings_match_f32(ctx, paper_map, enc):
+    data = W.encode_f16(paper_map.tsdf) if enc == "f16" else W.encode_u8(paper_map.tsdf)
+    mid_e = ctx.upload(data, paper_map.voxel_m, paper_map.origin_m, enc)
+    om = oracle.OracleMap(data, paper_map.voxel_m, paper_map.origin_m, enc)
+    try:
+        x, v = W.free_state(paper_map, 200)
+        g = ctx.trace(mid_e, x, 65536, P_PAPER)
+        o = oracle.trace(om, oracle.grid_start(om, x), oracle.directions(65536), P_PAPER["max_range"],
+                         nthreads=8)
+        compare_trace(g, o, enc)
+        compare_query(ctx.query(mid_e, x, v, 65536, P_PAPER),
+                      oracle.query(om, x, v, 65536, P_PAPER, nthreads=8), enc)
+    finally:
+        ctx.release(mid_e)
+
+
+def test_host_upload_equals_device_upload(ctx, tiny_map):
+    a = ctx.upload(tiny_map.tsdf, tiny_map.voxel_m, tiny_map.origin_m, "f32", on_device=True)
+    b = ctx.upload(tiny_map.tsdf, tiny_map.voxel_m, tiny_map.origin_m, "f32", on_device=False)
+    x, v = W.free_state(tiny_map, 5)
+    ra, rb = ctx.query(a, x, v, 4096, P_TINY), ctx.query(b, x, v, 4096, P_TINY)
+    assert np.array_equal(ra["S"], rb["S"]) and np.array_equal(ra["f"], rb["f"])
+    ctx.release(a)
+    ctx.release(b)
+
+
+def test_repeat_is_bitwise_identical(ctx, paper, paper_map):
+    mid, _ = paper
+    x, v = W.free_state(paper_map, 210)
+    a = ctx.query(mid, x, v, 65536, P_PAPER)
+    for _ in range(3):
+        b = ctx.query(mid, x, v, 65536, P_PAPER)
+        for k in ("S", "b", "f"):
+            assert np.array_equal(a[k], b[k])
+
+
+def test_zero_velocity_gives_exact_zero(ctx, tiny, tiny_map):
+    mid, _ = tiny
+    for seed in range(100, 120):
+        x, _ = W.free_state(tiny_map, seed)
+        r = ctx.query(mid, x, [0, 0, 0], 1024, P_TINY)
+        assert np.all(r["S"] == 0) and np.all(r["b"] == 0) and np.all(r["f"] == 0)
+        assert r["rank"] == 0 and r["n_contrib"] == 0
+
+
+def test_in_collision_start(ctx, tiny, tiny_map):
+    mid, om = tiny
+    x = np.array([1.05, 1.05, 0.15])           # inside the floor slab
+    g = ctx.query(mid, x, [0.3, 0.2, 1.0], 256, P_TINY)
+    o = oracle.query(om, x, [0.3, 0.2, 1.0], 256, P_TINY)
+    assert g["flags"] & 2 and o["flags"] & oracle.Q_IN_COLLISION
+    compare_query(g, o, "in collision")
+    t = ctx.trace(mid, x, 256, P_TINY)
+    assert np.all(t["hit"] == 10 + 64 * (10 + 64 * 1)) and np.all(t["d"] == 0)
+
+
+def test_scan_parity(ctx, tiny_map, paper_map):
+    L = W.params("lidar")
+    for vm, seed in ((tiny_map, 600), (paper_map, 601)):
+        x, v = W.free_state(vm, seed)
+        pts = W.synth_scan(vm, x, seed)
+        g = ctx.scan_query(pts, v, L)
+        o = oracle.scan(pts, v, L)
+        compare_query(g, o, "scan")
+        assert g["n_rays"] == pts.shape[0]
+
+
+def test_scan_reproduces_grid_query(ctx, tiny, tiny_map):
+    mid, om = tiny
+    dirs = oracle.directions(1024)
+    for seed in range(100, 110):
+        x, v = W.free_state(tiny_map, seed)
+        tr = oracle.trace(om, oracle.grid_start(om, x), dirs, 5.0)
+        hit = tr["hit"] >= 0
+        pts = (dirs[hit].astype(np.float64) * tr["d"][hit, None]).astype(np.float32)
+        q = ctx.query(mid, x, v, 1024, P_TINY)
+        s = ctx.scan_query(pts, v, dict(P_TINY, min_range=1e-9))
+        sS = max(np.abs(q["S"]).max(), 1e-300)
+        assert np.max(np.abs(s["S"] - q["S"])) <= 1e-4 * sS
+        assert np.max(np.abs(s["b"] - q["b"])) <= 1e-4 * max(np.abs(q["b"]).max(), 1e-300)
+
+
+def test_scan_edge_cases(ctx):
+    L = W.params("lidar")
+    empty = ctx.scan_query(np.zeros((0, 3), np.float32), [1, 0, 0], L)
+    assert empty["n_hit"] == 0 and np.all(empty["f"] == 0)
+    bad = np.array([[0, 0, 0], [np.nan, 1, 1], [np.inf, 0, 0], [0.05, 0, 0], [0.5, 0, 0]], np.float32)
+    r = ctx.scan_query(bad, [1, 0, 0], L)
+    o = oracle.scan(bad, [1, 0, 0], L)
+    assert r["n_hit"] == 1 == o["n_hit"]
+    compare_query(r, o, "scan edge")
+
+
+def test_errors_are_reported(ctx, tiny, tiny_map):
+    from paper_2301_08068_amd import binding as B
+    mid, _ = tiny
+    with pytest.raises(B.RmpcError) as e:
+        ctx.query(mid, [-1.0, 1, 1], [0, 0, 0], 64, P_TINY)
+    assert e.value.status == B.RMPC_E_OUT_OF_BOUNDS
+    for bad in ([np.nan, 1, 1], [np.inf, 1, 1]):
+        with pytest.raises(B.RmpcError) as e:
+            ctx.query(mid, bad, [0, 0, 0], 64, P_TINY)
+        assert e.value.status == B.RMPC_E_INVALID
+    for n in (0, 65537, -3):
+        with pytest.raises(B.RmpcError) as e:
+            ctx.query(mid, [1, 1, 1], [0, 0, 0], n, P_TINY)
+        assert e.value.status == B.RMPC_E_INVALID
+    with pytest.raises(B.RmpcError) as e:
+        ctx.query(12345, [1, 1, 1], [0, 0, 0], 64, P_TINY)
+    assert e.value.status == B.RMPC_E_NOMAP
+    with pytest.raises(B.RmpcError) as e:
+        ctx.query(mid, [1, 1, 1], [0, 0, 0], 64, dict(P_TINY, nu_rep=0.0))
+    assert e.value.status == B.RMPC_E_INVALID
+    with pytest.raises(B.RmpcError) as e:
+        ctx.upload(np.zeros((4, 4, 4), np.float32), 0.0, (0, 0, 0))
+    assert e.value.status == B.RMPC_E_INVALID
