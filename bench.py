@@ -1,0 +1,199 @@
+#!/usr/bin/env python3
+"""Throughput of the raycast-and-policy query on one MI355X.
+
+One step is one blocking ``rmpc_query``: cast 65536 Halton rays from one robot state through
+the resident 400^3 paper-shaped map, evaluate one obstacle policy per ray, metric-sum, resolve
+in float64 and read the 144-byte result back to the host (the paper's frame: load, execute,
+block-reduce, read back).  ``value`` is rays per second over the timed steps.
+
+Printed as one JSON line with a ``roofline`` entry for the dominant kernel (algorithmic bytes
+per launch over the dispatch-timed kernel duration) and a ``cpu_baseline`` entry (the float64
+oracle on the host cores, bounded sample).
+"""
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "rays/sec (raycast+RMP+resolve) at 65536 rays/query; served p50/p99 query latency"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_2301_08068_amd/csrc/raycast.hip", "paper_2301_08068_amd/csrc/rmpc_device.h",
+                  "paper_2301_08068_amd/csrc/rmpc_kernels.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "raycast_rmp_paper400_f32_traffic.txt")
+
+CONFIGS = {
+    # name: (map builder, encoding, state seed, rays, max range)
+    "paper": ("paper", "f32", 200, 65536, 10.0),
+    "paper_f16": ("paper", "f16", 200, 65536, 10.0),
+    "paper_u8": ("paper", "u8", 200, 65536, 10.0),
+    "tiny": ("tiny", "f32", 100, 1024, 5.0),
+}
+ELEM_BYTES = {"f32": 4, "f16": 2, "u8": 1}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on
+    the current kernel sources; None otherwise."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def build_map(kind: str, enc: str):
+    from paper_2301_08068_amd import workloads as W
+    vm = W.paper_map(2) if kind == "paper" else W.tiny_map(1)
+    data = {"f32": vm.tsdf, "f16": W.encode_f16(vm.tsdf), "u8": W.encode_u8(vm.tsdf)}[enc]
+    return vm, data
+
+
+def cpu_baseline(vm, data, enc, x, v, n_rays, params, budget_s):
+    """The float64 oracle as it stands, all usable host cores, bounded wall time."""
+    import oracle
+    try:
+        threads = min(len(os.sched_getaffinity(0)), 16)
+    except AttributeError:
+        threads = min(os.cpu_count() or 1, 16)
+    om = oracle.OracleMap(data, vm.voxel_m, vm.origin_m, enc)
+    dirs = oracle.directions(n_rays)
+    oracle.query(om, x, v, n_rays, params, nthreads=threads, dirs=dirs)   # warm-up
+    done, t0 = 0, time.perf_counter()
+    while True:
+        oracle.query(om, x, v, n_rays, params, nthreads=threads, dirs=dirs)
+        done += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    return {"value": done * n_rays / el, "unit": "rays/s", "cores": threads, "kind": "oracle",
+            "sample": f"{done} full queries of {n_rays} rays on the same map and state "
+                      f"({el:.1f} s wall, float64 C oracle, OpenMP over rays)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=30)
+    ap.add_argument("--config", default="paper", choices=sorted(CONFIGS))
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only run a plain device copy of this many bytes 20 times (counter "
+                         "calibration for HBM traffic) and exit")
+    args = ap.parse_args()
+    if args.copy_bytes:
+        import torch
+        a = torch.ones(args.copy_bytes // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(20):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": args.copy_bytes, "launches": 20}), flush=True)
+        return
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the query path runs on a single MI355X and has no "
+              "multi-GPU form (queries shard by state; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2301_08068_amd import build as lib_build
+    if not os.path.exists(lib_build.LIB):
+        lib_build.build()
+    from paper_2301_08068_amd import binding
+    from paper_2301_08068_amd import workloads as W
+
+    kind, enc, seed, n_rays, rmax = CONFIGS[args.config]
+    vm, data = build_map(kind, enc)
+    x, v = W.free_state(vm, seed)
+    params = W.params("static", max_range=rmax)
+
+    ctx = binding.Context(0, arena_bytes=1 << 30)
+    mid = ctx.upload(data, vm.voxel_m, vm.origin_m, enc)
+    for _ in range(args.warmup):
+        r = ctx.query(mid, x, v, n_rays, params)
+    r = ctx.query(mid, x, v, n_rays, params)
+    visits = r["visits"]
+
+    binding.rmpc_set_profiling(ctx.ptr, True)
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        ctx.query(mid, x, v, n_rays, params)
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kms, nl = binding.rmpc_get_profile(ctx.ptr)
+    binding.rmpc_set_profiling(ctx.ptr, False)
+
+    kern_s = kms / 1e3 / max(nl, 1)
+    alg_bytes = visits * ELEM_BYTES[enc] + 12 * n_rays
+    achieved = alg_bytes / kern_s / 1e9
+    traffic = measured_traffic() if args.config == "paper" else None
+    lat_us = sorted(1e6 * t for t in lat)
+    out = {
+        "metric": METRIC,
+        "value": n_rays * args.steps / elapsed,
+        "unit": "rays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{'paper-shaped 400^3 (0.05 m, 200 spheres/boxes + walls, map seed 2)' if kind == 'paper' else 'tiny 64^3 (0.1 m, 20 spheres + floor, map seed 1)'} "
+                         f"{enc} voxel map; one state (seed {seed}); {n_rays} Halton rays per query; "
+                         f"max range {rmax} m; blocking query with result readback"),
+            "rays_per_query": n_rays,
+            "map_storage": enc,
+            "occupied_fraction": round(vm.occupied_fraction(), 4),
+            "mean_visits_per_ray": round(visits / n_rays, 2),
+            "latency_us": {"p50": round(lat_us[len(lat_us) // 2], 1),
+                           "p99": round(lat_us[min(len(lat_us) - 1, int(0.99 * len(lat_us)))], 1)},
+            "kernel_us": round(kern_s * 1e6, 2),
+        },
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": "raycast_rmp_kernel",
+                     "algorithmic_bytes_per_launch": alg_bytes},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(vm, data, enc, x, v, n_rays, params, args.cpu_seconds)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

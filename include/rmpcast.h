@@ -178,6 +178,18 @@ rmpc_status rmpc_trace_debug(rmpc_ctx *ctx, int32_t map_id, const double x[3], i
  * x,y,z triples, into host memory out_host[3n] (Sec. III-E Eq. 10). */
 rmpc_status rmpc_directions(rmpc_ctx *ctx, int32_t n, float *out_host);
 
+/*
+ * rmpc_set_profiling -- measurement aid.  While enabled, each rmpc_query / rmpc_scan_query
+ * kernel is launched with a start and a stop event recorded by its own dispatch, and its
+ * duration is added to a running total.  Enabling (or disabling) resets the total.
+ * Errors: RMPC_E_INVALID, RMPC_E_HIP.
+ */
+rmpc_status rmpc_set_profiling(rmpc_ctx *ctx, int enable);
+
+/* rmpc_get_profile -- total kernel time in milliseconds and number of timed launches since
+ * profiling was last enabled.  Errors: RMPC_E_INVALID. */
+rmpc_status rmpc_get_profile(rmpc_ctx *ctx, double *kernel_ms, int64_t *launches);
+
 /* rmpc_last_error -- text of the calling thread's last error ("" if none). */
 const char *rmpc_last_error(void);
 

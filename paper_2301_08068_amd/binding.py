@@ -67,6 +67,8 @@ _SIGS = {
     "rmpc_trace_debug": [C.c_void_p, C.c_int32, _P(C.c_double), C.c_int32, _P(Params), C.c_void_p,
                          C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
     "rmpc_directions": [C.c_void_p, C.c_int32, _P(C.c_float)],
+    "rmpc_set_profiling": [C.c_void_p, C.c_int],
+    "rmpc_get_profile": [C.c_void_p, _P(C.c_double), _P(C.c_int64)],
 }
 for _name, _args in _SIGS.items():
     getattr(_lib, _name).argtypes = _args
@@ -164,6 +166,17 @@ def rmpc_directions(ctx: int, n: int) -> np.ndarray:
     _check(_lib.rmpc_directions(C.c_void_p(ctx), int(n), out.ctypes.data_as(_P(C.c_float))),
            "rmpc_directions")
     return out
+
+
+def rmpc_set_profiling(ctx: int, enable: bool) -> None:
+    _check(_lib.rmpc_set_profiling(C.c_void_p(ctx), int(bool(enable))), "rmpc_set_profiling")
+
+
+def rmpc_get_profile(ctx: int) -> Tuple[float, int]:
+    ms = C.c_double(0.0)
+    n = C.c_int64(0)
+    _check(_lib.rmpc_get_profile(C.c_void_p(ctx), C.byref(ms), C.byref(n)), "rmpc_get_profile")
+    return ms.value, n.value
 
 
 # ----------------------------------------------------------------------------- convenience

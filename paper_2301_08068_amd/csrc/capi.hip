@@ -93,6 +93,11 @@ struct rmpc_ctx {
     rmpc_result *result_host;   // pinned, written by the kernels
     std::map<int32_t, MapEntry> maps;
     int32_t next_map_id;
+    // kernel timing (rmpc_set_profiling)
+    bool profiling;
+    hipEvent_t ev0, ev1;
+    double prof_ms;
+    int64_t prof_n;
 };
 
 namespace {
@@ -210,6 +215,17 @@ rmpc_status setup_query(rmpc_ctx *ctx, int32_t map_id, const double x[3], int32_
     return RMPC_OK;
 }
 
+// After a synchronised launch: add the dispatch's own duration to the profile.
+rmpc_status account_profile(rmpc_ctx *ctx)
+{
+    if (!ctx->profiling) return RMPC_OK;
+    float ms = 0.0f;
+    RMPC_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    ctx->prof_ms += ms;
+    ctx->prof_n += 1;
+    return RMPC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -234,6 +250,10 @@ rmpc_status rmpc_create(int device, void *arena_dev, size_t arena_bytes, rmpc_ct
     c->arena_bytes = arena_bytes;
     c->alloc.init(arena_bytes);
     c->next_map_id = 0;
+    c->profiling = false;
+    c->ev0 = c->ev1 = nullptr;
+    c->prof_ms = 0.0;
+    c->prof_n = 0;
     size_t o_dirs, o_part, o_ticket;
     if (!c->alloc.alloc(sizeof(float) * 3 * RMPC_MAX_RAYS, &o_dirs) ||
         !c->alloc.alloc(sizeof(float) * rmpc::kMaxPartialSlots * 32, &o_part) ||
@@ -270,6 +290,8 @@ rmpc_status rmpc_destroy(rmpc_ctx *ctx)
     DeviceGuard dg(ctx->device);
     (void)hipDeviceSynchronize();
     (void)hipHostFree(ctx->result_host);
+    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     delete ctx;
     return RMPC_OK;
 }
@@ -359,10 +381,10 @@ rmpc_status rmpc_query(rmpc_ctx *ctx, int32_t map_id, const double x[3], const d
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     A.pol = policy_f(params, v);
     for (int a = 0; a < 3; ++a) A.vel64[a] = v[a];
-    RMPC_HIP(rmpc::launch_raycast(A, s, false));
+    RMPC_HIP(rmpc::launch_raycast(A, s, false, ctx->profiling ? ctx->ev0 : nullptr, ctx->ev1));
     RMPC_HIP(hipStreamSynchronize(s));
     std::memcpy(out, ctx->result_host, sizeof(rmpc_result));
-    return RMPC_OK;
+    return account_profile(ctx);
 }
 
 rmpc_status rmpc_trace_debug(rmpc_ctx *ctx, int32_t map_id, const double x[3], int32_t n_rays,
@@ -407,9 +429,31 @@ rmpc_status rmpc_scan_query(rmpc_ctx *ctx, const float *points_dev, int32_t n_po
     A.partials = ctx->partials;
     A.ticket = ctx->ticket;
     A.result = ctx->result_host;
-    RMPC_HIP(rmpc::launch_scan(A, s));
+    RMPC_HIP(rmpc::launch_scan(A, s, ctx->profiling ? ctx->ev0 : nullptr, ctx->ev1));
     RMPC_HIP(hipStreamSynchronize(s));
     std::memcpy(out, ctx->result_host, sizeof(rmpc_result));
+    return account_profile(ctx);
+}
+
+rmpc_status rmpc_set_profiling(rmpc_ctx *ctx, int enable)
+{
+    if (!ctx) return fail(RMPC_E_INVALID, "ctx is NULL");
+    DeviceGuard dg(ctx->device);
+    if (enable && !ctx->ev0) {
+        RMPC_HIP(hipEventCreate(&ctx->ev0));
+        RMPC_HIP(hipEventCreate(&ctx->ev1));
+    }
+    ctx->profiling = enable != 0;
+    ctx->prof_ms = 0.0;
+    ctx->prof_n = 0;
+    return RMPC_OK;
+}
+
+rmpc_status rmpc_get_profile(rmpc_ctx *ctx, double *kernel_ms, int64_t *launches)
+{
+    if (!ctx || !kernel_ms || !launches) return fail(RMPC_E_INVALID, "NULL argument");
+    *kernel_ms = ctx->prof_ms;
+    *launches = ctx->prof_n;
     return RMPC_OK;
 }
 

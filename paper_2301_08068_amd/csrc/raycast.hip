@@ -14,6 +14,7 @@
 // steps at an exact tie (the lowest index) -- and the hit distance d = T h are the float64
 // values of the definition.
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -311,12 +312,16 @@ __global__ void __launch_bounds__(kBlock) scan_rmp_kernel(ScanArgs A)
 }
 
 template <int DT>
-hipError_t launch_dt(const RayArgs &A, int grid, hipStream_t s, bool debug)
+hipError_t launch_dt(const RayArgs &A, int grid, hipStream_t s, bool debug, hipEvent_t e0, hipEvent_t e1)
 {
+    const dim3 blk(kBlock);
     if (debug) {
-        trace_debug_kernel<DT, kLookahead><<<(A.n_rays + kBlock - 1) / kBlock, kBlock, 0, s>>>(A);
+        const dim3 g((A.n_rays + kBlock - 1) / kBlock);
+        if (e0) hipExtLaunchKernelGGL(trace_debug_kernel<DT, kLookahead>, g, blk, 0, s, e0, e1, 0, A);
+        else trace_debug_kernel<DT, kLookahead><<<g, blk, 0, s>>>(A);
     } else {
-        raycast_rmp_kernel<DT, kLookahead><<<grid, kBlock, 0, s>>>(A);
+        if (e0) hipExtLaunchKernelGGL(raycast_rmp_kernel<DT, kLookahead>, dim3(grid), blk, 0, s, e0, e1, 0, A);
+        else raycast_rmp_kernel<DT, kLookahead><<<grid, blk, 0, s>>>(A);
     }
     return hipGetLastError();
 }
@@ -335,19 +340,21 @@ int scan_grid_blocks(int n_points)
     return b < 1 ? 1 : (b > 1024 ? 1024 : b);
 }
 
-hipError_t launch_scan(const ScanArgs &A, hipStream_t s)
+hipError_t launch_scan(const ScanArgs &A, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
-    scan_rmp_kernel<<<scan_grid_blocks(A.n_points), kBlock, 0, s>>>(A);
+    const dim3 g(scan_grid_blocks(A.n_points)), blk(kBlock);
+    if (e0) hipExtLaunchKernelGGL(scan_rmp_kernel, g, blk, 0, s, e0, e1, 0, A);
+    else scan_rmp_kernel<<<g, blk, 0, s>>>(A);
     return hipGetLastError();
 }
 
-hipError_t launch_raycast(const RayArgs &A, hipStream_t s, bool debug)
+hipError_t launch_raycast(const RayArgs &A, hipStream_t s, bool debug, hipEvent_t e0, hipEvent_t e1)
 {
     const int grid = ray_grid_blocks(A.n_rays);
     switch (A.map.dtype) {
-    case RMPC_TSDF_F32: return launch_dt<RMPC_TSDF_F32>(A, grid, s, debug);
-    case RMPC_TSDF_F16: return launch_dt<RMPC_TSDF_F16>(A, grid, s, debug);
-    default: return launch_dt<RMPC_OCC_U8>(A, grid, s, debug);
+    case RMPC_TSDF_F32: return launch_dt<RMPC_TSDF_F32>(A, grid, s, debug, e0, e1);
+    case RMPC_TSDF_F16: return launch_dt<RMPC_TSDF_F16>(A, grid, s, debug, e0, e1);
+    default: return launch_dt<RMPC_OCC_U8>(A, grid, s, debug, e0, e1);
     }
 }
 

@@ -85,8 +85,12 @@ struct LayoutArgs {
 
 int ray_grid_blocks(int n_rays);
 int scan_grid_blocks(int n_points);
-hipError_t launch_raycast(const RayArgs &a, hipStream_t s, bool debug);
-hipError_t launch_scan(const ScanArgs &a, hipStream_t s);
+// When ev0/ev1 are non-null the kernel is launched with hipExtLaunchKernelGGL so the two
+// events carry the dispatch's own start and end timestamps.
+hipError_t launch_raycast(const RayArgs &a, hipStream_t s, bool debug, hipEvent_t ev0 = nullptr,
+                          hipEvent_t ev1 = nullptr);
+hipError_t launch_scan(const ScanArgs &a, hipStream_t s, hipEvent_t ev0 = nullptr,
+                       hipEvent_t ev1 = nullptr);
 hipError_t launch_directions(const DirsArgs &a, hipStream_t s);
 hipError_t launch_layout(const LayoutArgs &a, hipStream_t s);
 
