@@ -90,9 +90,19 @@ def _d3(x):
     return a
 
 
+_PARAM_KEYS = ("c", "eta_rep", "nu_rep", "eta_damp", "nu_damp", "radius", "eps", "max_range",
+               "rank_tol", "min_range")
+_param_cache: Dict[tuple, Params] = {}
+
+
 def params_struct(p: Dict[str, float]) -> Params:
-    return Params(p["c"], p["eta_rep"], p["nu_rep"], p["eta_damp"], p["nu_damp"], p["radius"],
-                  p["eps"], p["max_range"], p["rank_tol"], p["min_range"])
+    key = tuple(float(p[k]) for k in _PARAM_KEYS)
+    ps = _param_cache.get(key)
+    if ps is None:
+        if len(_param_cache) > 256:
+            _param_cache.clear()
+        ps = _param_cache[key] = Params(*key)
+    return ps
 
 
 def result_dict(r: Result) -> Dict:
@@ -184,12 +194,14 @@ def rmpc_get_profile(ctx: int) -> Tuple[float, int]:
 class Context:
     """A library context on ``cuda:device`` whose arena is a torch uint8 tensor."""
 
-    def __init__(self, device: int = 0, arena_bytes: int = 1 << 30):
+    def __init__(self, device: int = 0, arena_bytes: int = 1 << 30, stream=None):
         import torch
         self.device = device
         self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device=f"cuda:{device}")
         self.ptr = rmpc_create(device, self.arena.data_ptr(), arena_bytes)
-        self._keep = {}
+        # queries go to this stream (default: the torch stream current at creation)
+        self.stream = int(stream) if stream is not None else \
+            torch.cuda.current_stream(device).cuda_stream
 
     def close(self):
         if self.ptr:
@@ -221,7 +233,7 @@ class Context:
         rmpc_map_release(self.ptr, map_id)
 
     def query(self, map_id: int, x, v, n_rays: int, params: Dict[str, float]) -> Dict:
-        return rmpc_query(self.ptr, map_id, x, v, n_rays, params)
+        return rmpc_query(self.ptr, map_id, x, v, n_rays, params, stream=self.stream)
 
     def scan_query(self, points, v, params: Dict[str, float]) -> Dict:
         """points: a cuda float32 tensor [n, 3] (or a numpy array, uploaded here)."""
@@ -229,7 +241,7 @@ class Context:
         if isinstance(points, np.ndarray):
             points = torch.from_numpy(np.ascontiguousarray(points, np.float32)).to(f"cuda:{self.device}")
         assert points.dtype == torch.float32 and points.is_cuda and points.is_contiguous()
-        return rmpc_scan_query(self.ptr, points.data_ptr(), points.shape[0], v, params)
+        return rmpc_scan_query(self.ptr, points.data_ptr(), points.shape[0], v, params, stream=self.stream)
 
     def trace(self, map_id: int, x, n_rays: int, params: Dict[str, float]) -> Dict[str, np.ndarray]:
         import torch
@@ -239,7 +251,7 @@ class Context:
         flags = torch.empty(n_rays, dtype=torch.uint8, device=dev)
         visits = torch.empty(n_rays, dtype=torch.int32, device=dev)
         rmpc_trace_debug(self.ptr, map_id, x, n_rays, params, hit.data_ptr(), dist.data_ptr(),
-                         flags.data_ptr(), visits.data_ptr())
+                         flags.data_ptr(), visits.data_ptr(), stream=self.stream)
         return dict(hit=hit.cpu().numpy(), d=dist.cpu().numpy(), flags=flags.cpu().numpy(),
                     visits=visits.cpu().numpy())
 

@@ -8,8 +8,13 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
+#include <chrono>
+#include <list>
 #include <map>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "rmpcast.h"
 #include "rmpc_kernels.h"
@@ -88,9 +93,16 @@ struct rmpc_ctx {
     size_t arena_bytes;
     Arena alloc;
     float *dirs;            // structure of arrays, RMPC_MAX_RAYS per component
+    int32_t *order;         // all Halton indices in direction-coherent (Hilbert) order
+    int32_t *counts;        // compaction scratch
+    // ordered lists of the first N rays, one per recently used N (LRU)
+    std::map<int32_t, size_t> lists;
+    std::list<int32_t> lru;
     float *partials;
     uint32_t *ticket;
     rmpc_result *result_host;   // pinned, written by the kernels
+    uint64_t *done_host;        // pinned completion word (sequence number of the last result)
+    uint64_t seq;
     std::map<int32_t, MapEntry> maps;
     int32_t next_map_id;
     // kernel timing (rmpc_set_profiling)
@@ -173,9 +185,103 @@ void brick_shape(int dtype, int lb[3])
 
 size_t elem_bytes(int dtype) { return dtype == RMPC_TSDF_F32 ? 4 : (dtype == RMPC_TSDF_F16 ? 2 : 1); }
 
+// Index of cell (x, y) along a Hilbert curve filling an n x n grid (n a power of two).
+uint64_t hilbert_index(uint32_t n, uint32_t x, uint32_t y)
+{
+    uint64_t d = 0;
+    for (uint32_t s = n / 2; s > 0; s /= 2) {
+        const uint32_t rx = (x & s) ? 1u : 0u, ry = (y & s) ? 1u : 0u;
+        d += (uint64_t)s * s * ((3u * rx) ^ ry);
+        if (ry == 0) {                       // turn the quadrant so the curve stays connected
+            if (rx == 1) { x = n - 1 - x; y = n - 1 - y; }
+            std::swap(x, y);
+        }
+    }
+    return d;
+}
+
+// Scheduling order of the ray table: directions folded onto the octahedron's square map and
+// sorted along a 1024 x 1024 Hilbert curve, so consecutive rays point in nearby directions.
+// Only the order in which rays are assigned to lanes depends on it, never a result bit
+// beyond the summation order.
+std::vector<int32_t> coherent_order(const std::vector<float> &soa, int n)
+{
+    std::vector<std::pair<uint64_t, int32_t>> key(n);
+    for (int i = 0; i < n; ++i) {
+        const float x = soa[i], y = soa[i + n], z = soa[i + 2 * n];
+        const float l1 = std::fabs(x) + std::fabs(y) + std::fabs(z);
+        float px = x / l1, py = y / l1;
+        if (z < 0.0f) {
+            const float ox = (1.0f - std::fabs(py)) * (px >= 0.0f ? 1.0f : -1.0f);
+            const float oy = (1.0f - std::fabs(px)) * (py >= 0.0f ? 1.0f : -1.0f);
+            px = ox; py = oy;
+        }
+        const uint32_t qx = std::min<uint32_t>(1023u, (uint32_t)((px + 1.0f) * 512.0f));
+        const uint32_t qy = std::min<uint32_t>(1023u, (uint32_t)((py + 1.0f) * 512.0f));
+        key[i] = {hilbert_index(1024, qx, qy), i};
+    }
+    std::sort(key.begin(), key.end());
+    std::vector<int32_t> order(n);
+    for (int i = 0; i < n; ++i) order[i] = key[i].second;
+    return order;
+}
+
+// The ordered list of the first n rays (cached per n; the full table is `order` itself).
+rmpc_status ray_list(rmpc_ctx *ctx, int32_t n, hipStream_t s, const int32_t **out)
+{
+    if (n == RMPC_MAX_RAYS) { *out = ctx->order; return RMPC_OK; }
+    auto it = ctx->lists.find(n);
+    if (it != ctx->lists.end()) {
+        ctx->lru.remove(n);
+        ctx->lru.push_front(n);
+        *out = reinterpret_cast<const int32_t *>(ctx->arena + it->second);
+        return RMPC_OK;
+    }
+    constexpr size_t kMaxLists = 64;
+    size_t off;
+    while (!ctx->alloc.alloc(sizeof(int32_t) * (size_t)n, &off)) {
+        if (ctx->lru.empty()) return fail(RMPC_E_NOMEM, "arena full (ray list)");
+        const int32_t victim = ctx->lru.back();
+        ctx->lru.pop_back();
+        RMPC_HIP(hipStreamSynchronize(s));
+        ctx->alloc.release(ctx->lists[victim]);
+        ctx->lists.erase(victim);
+    }
+    if (ctx->lists.size() >= kMaxLists) {
+        const int32_t victim = ctx->lru.back();
+        ctx->lru.pop_back();
+        RMPC_HIP(hipStreamSynchronize(s));
+        ctx->alloc.release(ctx->lists[victim]);
+        ctx->lists.erase(victim);
+    }
+    int32_t *list = reinterpret_cast<int32_t *>(ctx->arena + off);
+    rmpc::CompactArgs ca{ctx->order, RMPC_MAX_RAYS, n, ctx->counts, list};
+    hipError_t e = rmpc::launch_compact(ca, s);
+    if (e != hipSuccess) {
+        ctx->alloc.release(off);
+        return fail(RMPC_E_HIP, std::string("ray list: ") + hipGetErrorString(e));
+    }
+    ctx->lists[n] = off;
+    ctx->lru.push_front(n);
+    *out = list;
+    return RMPC_OK;
+}
+
+// Lanes per ray: enough segments that a query keeps about kLaneTarget lanes busy, each
+// segment at least 4 voxels long, at most 16.
+int segments_for(int32_t n_rays, double span)
+{
+    long target = 1l << 17;
+    if (const char *e = std::getenv("RMPC_LANE_TARGET")) target = std::max(1l, std::atol(e));
+    int S = 1;
+    while (S < 16 && (long)n_rays * S * 2 <= target && span / (2 * S) >= 4.0) S *= 2;
+    return S;
+}
+
 // Validates the query state and fills the geometry part of RayArgs.
 rmpc_status setup_query(rmpc_ctx *ctx, int32_t map_id, const double x[3], int32_t n_rays,
-                        const rmpc_params *params, rmpc::RayArgs &A, const MapEntry **me_out)
+                        const rmpc_params *params, hipStream_t stream, rmpc::RayArgs &A,
+                        const MapEntry **me_out)
 {
     if (!ctx) return fail(RMPC_E_INVALID, "ctx is NULL");
     if (!finite3(x)) return fail(RMPC_E_INVALID, "position is NULL or not finite");
@@ -195,6 +301,7 @@ rmpc_status setup_query(rmpc_ctx *ctx, int32_t map_id, const double x[3], int32_
         const double fr = (double)g - std::floor((double)g);
         if (fr < 1e-5 || 1.0 - fr < 1e-5) start_flags |= RMPC_RAY_START_FACE;
     }
+    if (rmpc_status st = ray_list(ctx, n_rays, stream, &A.rays)) return st;
     A.map = me.view;
     A.dirs = ctx->dirs;
     A.dir_stride = RMPC_MAX_RAYS;
@@ -204,6 +311,13 @@ rmpc_status setup_query(rmpc_ctx *ctx, int32_t map_id, const double x[3], int32_
     const double tmax = params->max_range_m / me.desc.voxel_m;
     A.tmax_lo = (float)(tmax * (1.0 - 1e-6) - 2e-5);
     A.tmax_hi = (float)(tmax * (1.0 + 1e-6) + 2e-5);
+    const double diag = std::sqrt((double)n[0] * n[0] + (double)n[1] * n[1] + (double)n[2] * n[2]) + 2.0;
+    A.tmax_v = std::min(tmax, diag);
+    A.segments = segments_for(n_rays, A.tmax_v);
+    if ((long)n_rays * A.segments > (long)rmpc::kMaxPartialSlots * 256)
+        return fail(RMPC_E_INVALID, "too many lanes for one launch");
+    A.lookahead = rmpc::kLookahead;
+    if (const char *e = std::getenv("RMPC_LOOKAHEAD")) A.lookahead = std::atoi(e);
     A.max_range = params->max_range_m;
     A.h = me.desc.voxel_m;
     A.radius64 = params->radius;
@@ -211,8 +325,32 @@ rmpc_status setup_query(rmpc_ctx *ctx, int32_t map_id, const double x[3], int32_
     A.partials = ctx->partials;
     A.ticket = ctx->ticket;
     A.result = ctx->result_host;
+    A.done = ctx->done_host;
+    A.seq = ++ctx->seq;
     *me_out = &me;
     return RMPC_OK;
+}
+
+// Wait for a query's result: spin on the completion word the kernel sets after writing the
+// result (a few microseconds sooner than a stream synchronisation), checking the stream for
+// errors now and then.
+rmpc_status wait_result(rmpc_ctx *ctx, hipStream_t s, uint64_t seq)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    for (uint64_t it = 1;; ++it) {
+        if (__atomic_load_n(ctx->done_host, __ATOMIC_ACQUIRE) == seq) return RMPC_OK;
+        if ((it & 1023) == 0) {
+            if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(60))
+                return fail(RMPC_E_HIP, "query kernel did not finish within 60 s");
+            const hipError_t e = hipStreamQuery(s);
+            if (e == hipSuccess) {
+                if (__atomic_load_n(ctx->done_host, __ATOMIC_ACQUIRE) == seq) return RMPC_OK;
+                return fail(RMPC_E_HIP, "kernel finished without publishing its result");
+            }
+            if (e != hipErrorNotReady) return fail(RMPC_E_HIP, std::string("query kernel: ") + hipGetErrorString(e));
+        }
+        __builtin_ia32_pause();
+    }
 }
 
 // After a synchronised launch: add the dispatch's own duration to the profile.
@@ -254,14 +392,18 @@ rmpc_status rmpc_create(int device, void *arena_dev, size_t arena_bytes, rmpc_ct
     c->ev0 = c->ev1 = nullptr;
     c->prof_ms = 0.0;
     c->prof_n = 0;
-    size_t o_dirs, o_part, o_ticket;
+    size_t o_dirs, o_part, o_ticket, o_order, o_counts;
     if (!c->alloc.alloc(sizeof(float) * 3 * RMPC_MAX_RAYS, &o_dirs) ||
-        !c->alloc.alloc(sizeof(float) * rmpc::kMaxPartialSlots * 32, &o_part) ||
+        !c->alloc.alloc(sizeof(int32_t) * RMPC_MAX_RAYS, &o_order) ||
+        !c->alloc.alloc(sizeof(int32_t) * 1024, &o_counts) ||
+        !c->alloc.alloc(sizeof(float) * (rmpc::kMaxPartialSlots + 8) * 32, &o_part) ||
         !c->alloc.alloc(256, &o_ticket)) {
         delete c;
         return fail(RMPC_E_NOMEM, "arena too small for the context tables");
     }
     c->dirs = reinterpret_cast<float *>(c->arena + o_dirs);
+    c->order = reinterpret_cast<int32_t *>(c->arena + o_order);
+    c->counts = reinterpret_cast<int32_t *>(c->arena + o_counts);
     c->partials = reinterpret_cast<float *>(c->arena + o_part);
     c->ticket = reinterpret_cast<uint32_t *>(c->arena + o_ticket);
     hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&c->result_host), sizeof(rmpc_result),
@@ -271,10 +413,26 @@ rmpc_status rmpc_create(int device, void *arena_dev, size_t arena_bytes, rmpc_ct
         return fail(RMPC_E_HIP, std::string("hipHostMalloc: ") + hipGetErrorString(e));
     }
     std::memset(c->result_host, 0, sizeof(rmpc_result));
+    e = hipHostMalloc(reinterpret_cast<void **>(&c->done_host), 64, hipHostMallocCoherent);
+    if (e != hipSuccess) {
+        (void)hipHostFree(c->result_host);
+        delete c;
+        return fail(RMPC_E_HIP, std::string("hipHostMalloc: ") + hipGetErrorString(e));
+    }
+    *c->done_host = 0;
+    c->seq = 0;
     rmpc::DirsArgs da{c->dirs, RMPC_MAX_RAYS};
     e = hipMemsetAsync(c->ticket, 0, 256, nullptr);
     if (e == hipSuccess) e = rmpc::launch_directions(da, nullptr);
     if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    if (e == hipSuccess) {
+        std::vector<float> soa(3 * (size_t)RMPC_MAX_RAYS);
+        e = hipMemcpy(soa.data(), c->dirs, sizeof(float) * soa.size(), hipMemcpyDeviceToHost);
+        if (e == hipSuccess) {
+            const std::vector<int32_t> order = coherent_order(soa, RMPC_MAX_RAYS);
+            e = hipMemcpy(c->order, order.data(), sizeof(int32_t) * order.size(), hipMemcpyHostToDevice);
+        }
+    }
     if (e != hipSuccess) {
         (void)hipHostFree(c->result_host);
         delete c;
@@ -290,6 +448,7 @@ rmpc_status rmpc_destroy(rmpc_ctx *ctx)
     DeviceGuard dg(ctx->device);
     (void)hipDeviceSynchronize();
     (void)hipHostFree(ctx->result_host);
+    (void)hipHostFree(ctx->done_host);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     delete ctx;
@@ -374,16 +533,18 @@ rmpc_status rmpc_query(rmpc_ctx *ctx, int32_t map_id, const double x[3], const d
 {
     if (!out) return fail(RMPC_E_INVALID, "out is NULL");
     if (!finite3(v)) return fail(RMPC_E_INVALID, "velocity is NULL or not finite");
-    rmpc::RayArgs A;
-    const MapEntry *me = nullptr;
-    if (rmpc_status st = setup_query(ctx, map_id, x, n_rays, params, A, &me)) return st;
+    if (!ctx) return fail(RMPC_E_INVALID, "ctx is NULL");
     DeviceGuard dg(ctx->device);
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    rmpc::RayArgs A;
+    const MapEntry *me = nullptr;
+    if (rmpc_status st = setup_query(ctx, map_id, x, n_rays, params, s, A, &me)) return st;
     A.pol = policy_f(params, v);
     for (int a = 0; a < 3; ++a) A.vel64[a] = v[a];
     RMPC_HIP(rmpc::launch_raycast(A, s, false, ctx->profiling ? ctx->ev0 : nullptr, ctx->ev1));
-    RMPC_HIP(hipStreamSynchronize(s));
+    if (rmpc_status st = wait_result(ctx, s, A.seq)) return st;
     std::memcpy(out, ctx->result_host, sizeof(rmpc_result));
+    if (ctx->profiling) RMPC_HIP(hipEventSynchronize(ctx->ev1));
     return account_profile(ctx);
 }
 
@@ -392,11 +553,12 @@ rmpc_status rmpc_trace_debug(rmpc_ctx *ctx, int32_t map_id, const double x[3], i
                              double *dist_dev, uint8_t *flags_dev, int32_t *visits_dev)
 {
     if (!hit_lin_dev || !dist_dev || !flags_dev) return fail(RMPC_E_INVALID, "NULL output");
-    rmpc::RayArgs A;
-    const MapEntry *me = nullptr;
-    if (rmpc_status st = setup_query(ctx, map_id, x, n_rays, params, A, &me)) return st;
+    if (!ctx) return fail(RMPC_E_INVALID, "ctx is NULL");
     DeviceGuard dg(ctx->device);
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    rmpc::RayArgs A;
+    const MapEntry *me = nullptr;
+    if (rmpc_status st = setup_query(ctx, map_id, x, n_rays, params, s, A, &me)) return st;
     A.dbg_hit = hit_lin_dev;
     A.dbg_dist = dist_dev;
     A.dbg_flags = flags_dev;
@@ -429,9 +591,12 @@ rmpc_status rmpc_scan_query(rmpc_ctx *ctx, const float *points_dev, int32_t n_po
     A.partials = ctx->partials;
     A.ticket = ctx->ticket;
     A.result = ctx->result_host;
+    A.done = ctx->done_host;
+    A.seq = ++ctx->seq;
     RMPC_HIP(rmpc::launch_scan(A, s, ctx->profiling ? ctx->ev0 : nullptr, ctx->ev1));
-    RMPC_HIP(hipStreamSynchronize(s));
+    if (rmpc_status st = wait_result(ctx, s, A.seq)) return st;
     std::memcpy(out, ctx->result_host, sizeof(rmpc_result));
+    if (ctx->profiling) RMPC_HIP(hipEventSynchronize(ctx->ev1));
     return account_profile(ctx);
 }
 

@@ -1,18 +1,25 @@
-// raycast.hip -- the fused raycast-and-policy kernel (Sec. III-E, III-F) and its debug twin.
+// raycast.hip -- the fused raycast-and-policy kernel (Sec. III-E, III-F), its debug twin and
+// the LiDAR scan kernel (Sec. III-G).
 //
-// One lane owns one ray at a time.  It walks the voxel grid with a 3-D DDA (Amanatides &
-// Woo) from the float32 start g along the float32 Halton direction r, planning K voxel
-// visits ahead (the visited addresses do not depend on the loaded values, so K loads are
-// in flight per lane), stops at the first occupied voxel, evaluates the obstacle policy of
-// Sec. III-C in registers and adds it to compensated float32 sums.  The grid-wide sum is
-// resolved in float64 by the last block to finish.
+// Each ray's parameter range [0, max_range / h] is split into S segments that S adjacent
+// lanes walk at the same time (S = 1, 2, 4, 8 or 16): the first hit along a ray is the hit of
+// the lowest segment that finds one, so a query's critical path is one segment long instead of
+// one ray.  Inside a segment a lane runs a 3-D DDA (Amanatides & Woo) on the float32 start g
+// and the float32 Halton direction r, planning K voxel visits ahead (the visited addresses do
+// not depend on the loaded values, so K loads are in flight), and stops at the first occupied
+// voxel, at its segment's end, at max_range or at the grid's edge.  A wave ballot after every
+// round stops lanes whose ray already has a hit in a lower segment.  The lane holding the
+// ray's hit evaluates the obstacle policy of Sec. III-C in registers and adds it to
+// compensated float32 sums; the last block to finish resolves in float64.
 //
 // Exactness: face crossings are compared in float32 as T = (B - g) / r with B the integer
-// boundary (never accumulated).  When the two nearest crossings lie within a guard band
-// that bounds the float32 error, or the range test is that close, the decision is redone
-// in float64 from the same formula, so every traversal decision -- including which axis
-// steps at an exact tie (the lowest index) -- and the hit distance d = T h are the float64
-// values of the definition.
+// boundary (never accumulated).  When the two nearest crossings, or a crossing and max_range,
+// lie within a guard band that bounds the float32 error, the decision is redone in float64
+// from the same formula, so every traversal decision -- including which axis steps at an
+// exact tie (the lowest index) -- and the hit distance d = T h are the float64 values of the
+// definition.  A segment starts at a float64-located voxel on the ray's walk, at a parameter
+// chosen at least kSegMargin away from every face crossing, so the float32 end test of the
+// previous segment and the start of the next agree exactly.
 
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
@@ -27,11 +34,19 @@ namespace rmpc {
 namespace {
 
 constexpr float kInf = __builtin_huge_valf();
+constexpr double kSegMargin = 1e-3;      // voxel units between a segment boundary and any crossing
 
-// Float64 crossing parameter of the next face along one axis (r != 0).
+// Float64 crossing parameter of the next face along one axis (r != 0) from voxel coordinate v.
 __device__ __forceinline__ double cross64(int v, float g, float r)
 {
     const double B = r > 0.0f ? (double)(v + 1) : (double)v;
+    return (B - (double)g) / (double)r;
+}
+
+// Float64 parameter at which the ray entered voxel coordinate v along one axis (r != 0).
+__device__ __forceinline__ double entry64(int v, float g, float r)
+{
+    const double B = r > 0.0f ? (double)v : (double)(v + 1);
     return (B - (double)g) / (double)r;
 }
 
@@ -45,152 +60,226 @@ __device__ __forceinline__ bool start_occupied(const RayArgs &A)
     return Voxel<DT>::occ(vox[a]);
 }
 
-struct TraceOut {
-    double d;          // metres, +inf on a miss
-    int32_t hit_lin;   // logical index (debug builds), -1 on a miss
-    uint32_t flags;
-    int32_t visits;
+// Segment boundary of a ray near t_nom: the first of 16 candidates t = t_nom + 0.05 c (voxel
+// units) whose distance to every face crossing of the ray is at least kSegMargin.  Within 0.8
+// voxel units each axis crosses at most two faces, so at most six candidates are excluded and
+// the search cannot fail for real inputs; `ok` is false otherwise.  Returns the voxel there.
+__device__ __forceinline__ double seg_boundary(double t_nom, float gx, float gy, float gz, float rx,
+                                               float ry, float rz, int &vx, int &vy, int &vz, bool &ok)
+{
+    ok = false;
+    double t = t_nom;
+    for (int c = 0; c < 16 && !ok; ++c) {
+        t = t_nom + 0.05 * c;
+        vx = (int)floor((double)gx + t * (double)rx);
+        vy = (int)floor((double)gy + t * (double)ry);
+        vz = (int)floor((double)gz + t * (double)rz);
+        bool good = true;
+        if (rx != 0.0f) good = good && cross64(vx, gx, rx) - t >= kSegMargin && t - entry64(vx, gx, rx) >= kSegMargin;
+        if (ry != 0.0f) good = good && cross64(vy, gy, ry) - t >= kSegMargin && t - entry64(vy, gy, ry) >= kSegMargin;
+        if (rz != 0.0f) good = good && cross64(vz, gz, rz) - t >= kSegMargin && t - entry64(vz, gz, rz) >= kSegMargin;
+        ok = good;
+    }
+    return t;
+}
+
+// One lane's walk through one segment of one ray.
+struct Walker {
+    int vx, vy, vz;
+    float Tx, Ty, Tz;                 // float32 parameters of the next faces
+    float t_hi;                       // stop once the next crossing exceeds this (float32)
+    float t_lo;                       // crossings at or beyond this get the float64 range test
+    bool last;                        // the segment ending at max_range
+    int steps;                        // voxels entered so far
+    int tie_at, rtie_at;              // first decision index with a (range) near-tie
+    // outcome
     bool hit;
+    int hit_step;                     // 0-based index of the step that entered the hit voxel
+    double d;                         // metres
+    int hx, hy, hz;                   // hit voxel (debug)
 };
 
-// Walk one ray.  K voxel visits are planned per round; DEBUG also reports the hit voxel.
+__device__ __forceinline__ uint32_t voxel_offset(const MapView &m, int x, int y, int z)
+{
+    return addr_x(m, x) + addr_y(m, y) + addr_z(m, z);
+}
+
+// Plan K steps, load their voxels, stop at the first occupied one.  Returns true while the
+// walk goes on.  The common path has no branches: the axis step is done with selects, each
+// step's load is issued as soon as its address is known, and steps past the end of the walk
+// load a harmless in-grid address and are ignored.  Only the axis of each step is kept (2
+// bits); the hit voxel's coordinates are recovered by undoing the later steps.
 template <int DT, int K, bool DEBUG>
-__device__ __forceinline__ TraceOut trace_ray(const RayArgs &A, float rx, float ry, float rz)
+__device__ __forceinline__ bool walk_round(const RayArgs &A, Walker &w, float gx, float gy, float gz,
+                                           float rx, float ry, float rz, float irx, float iry, float irz,
+                                           uint32_t safe_addr)
 {
     using VT = typename Voxel<DT>::T;
     const MapView &m = A.map;
     const VT *vox = static_cast<const VT *>(m.data);
-    TraceOut o;
-    o.flags = A.start_flags;
-    o.hit_lin = -1;
-    o.d = __builtin_huge_val();
-    o.hit = false;
-    o.visits = 1;
+    const int px = rx > 0.0f, py = ry > 0.0f, pz = rz > 0.0f;
+    const int sx = px ? 1 : -1, sy = py ? 1 : -1, sz = pz ? 1 : -1;
+    VT val[K];
+    uint32_t axes = 0;                // 2 bits per planned step
+    int nplan = 0;
+    bool going = true;                // no termination yet in this round
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        // nearest and second-nearest crossings (no NaNs occur: +inf marks an axis never crossed)
+        const float t1 = __builtin_amdgcn_fmed3f(w.Tx, fminf(w.Ty, w.Tz), -kInf);
+        const float t2 = __builtin_amdgcn_fmed3f(w.Tx, w.Ty, w.Tz);
+        int a = w.Tx == t1 ? 0 : (w.Ty == t1 ? 1 : 2);
+        if (going && t2 - t1 < 2e-5f + 1e-6f * t2) {
+            // decide in float64 exactly as the definition does
+            const double X = rx != 0.0f ? cross64(w.vx, gx, rx) : __builtin_huge_val();
+            const double Y = ry != 0.0f ? cross64(w.vy, gy, ry) : __builtin_huge_val();
+            const double Z = rz != 0.0f ? cross64(w.vz, gz, rz) : __builtin_huge_val();
+            a = 0;
+            double m1 = X;
+            if (Y < m1) { a = 1; m1 = Y; }
+            if (Z < m1) { a = 2; m1 = Z; }
+            const bool tie = (a != 0 && X - m1 < 1e-5) || (a != 1 && Y - m1 < 1e-5) ||
+                             (a != 2 && Z - m1 < 1e-5);
+            if (tie && w.tie_at > w.steps + k) w.tie_at = w.steps + k;
+        }
+        const bool bx = a == 0, by = a == 1, bz = a == 2;
+        const float ta = bx ? w.Tx : (by ? w.Ty : w.Tz);
+        bool stop = ta > w.t_hi;
+        if (going && !stop && ta >= w.t_lo) {
+            // range test (closed interval) in float64 inside the guard band
+            const double T64 = bx ? cross64(w.vx, gx, rx) : (by ? cross64(w.vy, gy, ry) : cross64(w.vz, gz, rz));
+            const double dist = T64 * A.h;
+            stop = dist > A.max_range;
+            if (fabs(dist - A.max_range) < 1e-5 * A.h && w.rtie_at > w.steps + k) w.rtie_at = w.steps + k;
+        }
+        w.vx = bx ? w.vx + sx : w.vx;
+        w.vy = by ? w.vy + sy : w.vy;
+        w.vz = bz ? w.vz + sz : w.vz;
+        w.Tx = bx ? ((float)(w.vx + px) - gx) * irx : w.Tx;
+        w.Ty = by ? ((float)(w.vy + py) - gy) * iry : w.Ty;
+        w.Tz = bz ? ((float)(w.vz + pz) - gz) * irz : w.Tz;
+        const bool inside = (unsigned)w.vx < (unsigned)m.nx && (unsigned)w.vy < (unsigned)m.ny &&
+                            (unsigned)w.vz < (unsigned)m.nz;
+        going = going && !stop && inside;
+        val[k] = vox[going ? voxel_offset(m, w.vx, w.vy, w.vz) : safe_addr];
+        axes |= (uint32_t)a << (2 * k);
+        nplan += going ? 1 : 0;
+    }
+    int hk = -1;
+#pragma unroll
+    for (int k = K - 1; k >= 0; --k)
+        if (k < nplan && Voxel<DT>::occ(val[k])) hk = k;
+    if (hk >= 0) {
+        // undo the steps after hk to get the hit voxel
+        int hx = w.vx, hy = w.vy, hz = w.vz;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (k > hk) {
+                const uint32_t ak = (axes >> (2 * k)) & 3u;
+                hx -= ak == 0 ? sx : 0;
+                hy -= ak == 1 ? sy : 0;
+                hz -= ak == 2 ? sz : 0;
+            }
+        }
+        const uint32_t a = (axes >> (2 * hk)) & 3u;
+        const double T64 = a == 0 ? entry64(hx, gx, rx) : (a == 1 ? entry64(hy, gy, ry) : entry64(hz, gz, rz));
+        w.d = T64 * A.h;
+        if (DEBUG) { w.hx = hx; w.hy = hy; w.hz = hz; }
+        w.hit = true;
+        w.hit_step = w.steps + hk;
+        w.steps += hk + 1;
+        return false;
+    }
+    w.steps += nplan;
+    return nplan == K;
+}
 
-    int vx = A.v0[0], vy = A.v0[1], vz = A.v0[2];
+// Per-ray outcome, valid in the lane that reports the ray (its hit segment, else segment 0).
+struct RayOut {
+    bool report;
+    bool hit;
+    double d;
+    uint32_t flags;
+    int visits_lane;                  // this lane's share of the ray's visits
+    int hit_lin;                      // debug
+};
+
+// Walk one ray with the S lanes of its group; every lane of the wave must call this.
+template <int DT, int K, bool DEBUG>
+__device__ __forceinline__ RayOut trace_group(const RayArgs &A, bool valid, int seg, int S,
+                                              float rx, float ry, float rz)
+{
+    const MapView &m = A.map;
     const float gx = A.g[0], gy = A.g[1], gz = A.g[2];
     const float irx = rx != 0.0f ? 1.0f / rx : kInf;
     const float iry = ry != 0.0f ? 1.0f / ry : kInf;
     const float irz = rz != 0.0f ? 1.0f / rz : kInf;
-    const int px = rx > 0.0f, py = ry > 0.0f, pz = rz > 0.0f;     // face offset of the next boundary
-    const int sx = px ? 1 : -1, sy = py ? 1 : -1, sz = pz ? 1 : -1;
-    float Tx = rx != 0.0f ? ((float)(vx + px) - gx) * irx : kInf;
-    float Ty = ry != 0.0f ? ((float)(vy + py) - gy) * iry : kInf;
-    float Tz = rz != 0.0f ? ((float)(vz + pz) - gz) * irz : kInf;
-    uint32_t ax = addr_x(m, vx), ay = addr_y(m, vy), az = addr_z(m, vz);
-
-    int step = 0;                 // iterations done (one per face crossing)
-    int tie_at = 1 << 30;         // first iteration with a near-tie
-    int rtie_at = 1 << 30;        // first iteration with a range near-tie
-    bool done = false;
-
-    while (!done) {
-        uint32_t addr[K];
-        int info[K];              // axis in bits 0..1, coordinate along it above
-        int hx[K], hy[K], hz[K];  // full coordinates (debug only)
-        int nplan = 0;
-        bool ended = false;       // a range/grid termination inside this round
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            if (!ended) {
-                // nearest crossing, lowest axis on exact ties
-                int a = 0;
-                float t1 = Tx;
-                if (Ty < t1) { a = 1; t1 = Ty; }
-                if (Tz < t1) { a = 2; t1 = Tz; }
-                const float t2 = a == 0 ? fminf(Ty, Tz) : (a == 1 ? fminf(Tx, Tz) : fminf(Tx, Ty));
-                if (t2 - t1 < 2e-5f + 1e-6f * t2) {
-                    // decide in float64 exactly as the definition does
-                    const double X = rx != 0.0f ? cross64(vx, gx, rx) : __builtin_huge_val();
-                    const double Y = ry != 0.0f ? cross64(vy, gy, ry) : __builtin_huge_val();
-                    const double Z = rz != 0.0f ? cross64(vz, gz, rz) : __builtin_huge_val();
-                    a = 0;
-                    double m1 = X;
-                    if (Y < m1) { a = 1; m1 = Y; }
-                    if (Z < m1) { a = 2; m1 = Z; }
-                    const bool tie = (a != 0 && X - m1 < 1e-5) || (a != 1 && Y - m1 < 1e-5) ||
-                                     (a != 2 && Z - m1 < 1e-5);
-                    if (tie && tie_at > step + k) tie_at = step + k;
-                    t1 = a == 0 ? Tx : (a == 1 ? Ty : Tz);
-                }
-                // range test (closed interval), float64 inside the guard band
-                bool beyond = t1 > A.tmax_hi;
-                if (!beyond && t1 >= A.tmax_lo) {
-                    const double T64 = a == 0 ? cross64(vx, gx, rx)
-                                     : (a == 1 ? cross64(vy, gy, ry) : cross64(vz, gz, rz));
-                    const double dist = T64 * A.h;
-                    beyond = dist > A.max_range;
-                    if (fabs(dist - A.max_range) < 1e-5 * A.h && rtie_at > step + k) rtie_at = step + k;
-                }
-                if (beyond) {
-                    ended = true;
-                } else {
-                    int coord;
-                    if (a == 0) {
-                        vx += sx; coord = vx;
-                        Tx = ((float)(vx + px) - gx) * irx;
-                        ax = addr_x(m, vx);
-                    } else if (a == 1) {
-                        vy += sy; coord = vy;
-                        Ty = ((float)(vy + py) - gy) * iry;
-                        ay = addr_y(m, vy);
-                    } else {
-                        vz += sz; coord = vz;
-                        Tz = ((float)(vz + pz) - gz) * irz;
-                        az = addr_z(m, vz);
-                    }
-                    if ((unsigned)vx >= (unsigned)m.nx || (unsigned)vy >= (unsigned)m.ny ||
-                        (unsigned)vz >= (unsigned)m.nz) {
-                        ended = true;                        // left the grid: a miss
-                    } else {
-                        addr[k] = ax + ay + az;
-                        info[k] = a | (coord << 2);
-                        if (DEBUG) { hx[k] = vx; hy[k] = vy; hz[k] = vz; }
-                        nplan = k + 1;
-                    }
-                }
-            }
-        }
-        VT val[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-            if (k < nplan) val[k] = vox[addr[k]];
-        int hk = -1;
-#pragma unroll
-        for (int k = K - 1; k >= 0; --k)
-            if (k < nplan && Voxel<DT>::occ(val[k])) hk = k;
-        if (hk >= 0) {
-            int inf = 0, cx = 0, cy = 0, cz = 0;
-#pragma unroll
-            for (int k = 0; k < K; ++k)
-                if (k == hk) {
-                    inf = info[k];
-                    if (DEBUG) { cx = hx[k]; cy = hy[k]; cz = hz[k]; }
-                }
-            const int a = inf & 3, c = inf >> 2;
-            // the face entered: lower face when moving up, upper face when moving down
-            double T64;
-            if (a == 0) T64 = cross64(c - sx, gx, rx);
-            else if (a == 1) T64 = cross64(c - sy, gy, ry);
-            else T64 = cross64(c - sz, gz, rz);
-            o.d = T64 * A.h;
-            o.hit = true;
-            o.visits += hk + 1;
-            if (DEBUG) o.hit_lin = cx + m.nx * (cy + m.ny * cz);
-            if (tie_at <= step + hk) o.flags |= kRayTie;
-            if (rtie_at <= step + hk) o.flags |= kRayRangeTie;
-            done = true;
-        } else {
-            o.visits += nplan;
-            step += nplan;
-            if (ended) {
-                // the iteration that ended the ray is number `step` (0-based)
-                if (tie_at <= step) o.flags |= kRayTie;
-                if (rtie_at <= step) o.flags |= kRayRangeTie;
-                done = true;
-            }
+    const double tmax = A.tmax_v;
+    Walker w;
+    w.steps = 0;
+    w.tie_at = w.rtie_at = 1 << 30;
+    w.hit = false;
+    w.hit_step = -1;
+    w.d = __builtin_huge_val();
+    w.hx = w.hy = w.hz = 0;
+    bool active = valid;
+    // segment start
+    if (seg == 0) {
+        w.vx = A.v0[0]; w.vy = A.v0[1]; w.vz = A.v0[2];
+    } else {
+        bool ok;
+        seg_boundary(tmax * seg / S, gx, gy, gz, rx, ry, rz, w.vx, w.vy, w.vz, ok);
+        if (!ok || (unsigned)w.vx >= (unsigned)m.nx || (unsigned)w.vy >= (unsigned)m.ny ||
+            (unsigned)w.vz >= (unsigned)m.nz) {
+            active = false;                               // empty segment (or past the grid)
+            w.vx = A.v0[0]; w.vy = A.v0[1]; w.vz = A.v0[2];
         }
     }
+    // segment end: the next boundary that exists, else max_range
+    w.last = true;
+    w.t_hi = A.tmax_hi;
+    w.t_lo = A.tmax_lo;
+    for (int e = seg + 1; e < S && w.last; ++e) {
+        int ux, uy, uz;
+        bool ok;
+        const double te = seg_boundary(tmax * e / S, gx, gy, gz, rx, ry, rz, ux, uy, uz, ok);
+        if (ok) {
+            w.last = false;
+            w.t_hi = (float)te;       // no crossing lies within kSegMargin of te
+            w.t_lo = kInf;
+        }
+    }
+    const int px = rx > 0.0f, py = ry > 0.0f, pz = rz > 0.0f;
+    w.Tx = rx != 0.0f ? ((float)(w.vx + px) - gx) * irx : kInf;
+    w.Ty = ry != 0.0f ? ((float)(w.vy + py) - gy) * iry : kInf;
+    w.Tz = rz != 0.0f ? ((float)(w.vz + pz) - gz) * irz : kInf;
+    const uint32_t safe_addr = voxel_offset(m, A.v0[0], A.v0[1], A.v0[2]);
+
+    const int lane = threadIdx.x & (kWave - 1);
+    const int base = lane & ~(S - 1);
+    const uint64_t seg_bits = (1ull << S) - 1ull;        // S <= 16
+    const uint64_t lower = ((1ull << seg) - 1ull) << base;
+    for (;;) {
+        const uint64_t hm = __ballot(w.hit);
+        if (hm & lower) active = false;                  // a lower segment already hit
+        if (!__any(active)) break;
+        if (active) active = walk_round<DT, K, DEBUG>(A, w, gx, gy, gz, rx, ry, rz, irx, iry, irz, safe_addr);
+    }
+    // combine the group: the lowest segment with a hit owns the ray
+    const uint64_t gh = (__ballot(w.hit) >> base) & seg_bits;
+    const int h = gh ? __ffsll((unsigned long long)gh) - 1 : S;
+    const bool keep = valid && seg <= h;
+    RayOut o;
+    o.visits_lane = keep ? w.steps + (seg == 0 ? 1 : 0) : 0;
+    const bool tie = keep && w.tie_at <= (seg == h ? w.hit_step : (1 << 29));
+    const bool rtie = keep && w.rtie_at <= (seg == h ? w.hit_step : (1 << 29));
+    const uint64_t tm = (__ballot(tie) >> base) & seg_bits;
+    const uint64_t rm = (__ballot(rtie) >> base) & seg_bits;
+    o.report = valid && seg == (h < S ? h : 0);
+    o.hit = w.hit && seg == h;
+    o.d = o.hit ? w.d : __builtin_huge_val();
+    o.flags = A.start_flags | (tm ? kRayTie : 0u) | (rm ? kRayRangeTie : 0u);
+    o.hit_lin = o.hit ? w.hx + m.nx * (w.hy + m.ny * w.hz) : -1;
     return o;
 }
 
@@ -233,61 +322,91 @@ __device__ __forceinline__ int contributes(const RayArgs &A, float rx, float ry,
     return d < A.radius64 && vn > 0.0;
 }
 
+// Blocks are dispatched round-robin over the 8 XCDs (block b runs on XCD b % 8).  Give each
+// XCD a contiguous run of tiles so that its L2 sees one compact cone of ray directions.
+__device__ __forceinline__ int xcd_tile(int b, int nb)
+{
+    const int q = nb >> 3, r = nb & 7, x = b & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
+// Lane -> (ray position, segment); the grid covers every lane once (n_rays * S lanes), so a
+// lane traces first and only then holds accumulators.  Waves stay whole: the traversal uses
+// wave-wide ballots, and lanes past the end take part as idle members.
 template <int DT, int K>
 __global__ void __launch_bounds__(kBlock) raycast_rmp_kernel(RayArgs A)
 {
-    __shared__ float lds[kWavesPerBlock * kPartialWords];
+    __shared__ float lds[kReduceLdsWords];
+    const bool in_coll = start_occupied<DT>(A);
+    const int S = A.segments;
+    const int p = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const bool valid = p < A.n_rays * S;
+    const int j = valid ? p / S : 0;
+    const int seg = p & (S - 1);
+    const int i = A.rays[j];
+    const float rx = A.dirs[i], ry = A.dirs[i + A.dir_stride], rz = A.dirs[i + 2 * A.dir_stride];
     Acc acc;
     acc.zero();
-    const bool in_coll = start_occupied<DT>(A);
-    const int stride = gridDim.x * kBlock;
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < A.n_rays; i += stride) {
-        const float rx = A.dirs[i], ry = A.dirs[i + A.dir_stride], rz = A.dirs[i + 2 * A.dir_stride];
-        double d;
-        bool hit;
-        uint32_t fl;
-        int vis;
-        if (in_coll) {
-            d = 0.0; hit = true; fl = kRayInCollision; vis = 1;
-        } else {
-            const TraceOut t = trace_ray<DT, K, false>(A, rx, ry, rz);
-            d = t.d; hit = t.hit; fl = t.flags; vis = t.visits;
+    if (in_coll) {
+        if (valid && seg == 0) {
+            acc.visits = 1;
+            acc.n_hit = 1;
+            acc.n_contrib = contributes(A, rx, ry, rz, 0.0);
+            policy_accumulate(A.pol, rx, ry, rz, 0.0f, acc);
         }
-        acc.visits += vis;
-        acc.n_tie += (fl & kRayTie) != 0;
-        if (hit) {
-            acc.n_hit += 1;
-            acc.n_contrib += contributes(A, rx, ry, rz, d);
-            policy_accumulate(A.pol, rx, ry, rz, (float)d, acc);
+    } else {
+        const RayOut o = trace_group<DT, K, false>(A, valid, seg, S, rx, ry, rz);
+        acc.visits = o.visits_lane;
+        if (o.report) {
+            acc.n_tie = (o.flags & kRayTie) != 0;
+            if (o.hit) {
+                acc.n_hit = 1;
+                acc.n_contrib = contributes(A, rx, ry, rz, o.d);
+                policy_accumulate(A.pol, rx, ry, rz, (float)o.d, acc);
+            }
         }
     }
     grid_finish(acc, A.partials, A.ticket, A.rank_tol, A.n_rays,
-                in_coll ? RMPC_Q_IN_COLLISION : 0u, A.result, lds);
+                in_coll ? RMPC_Q_IN_COLLISION : 0u, A.result, A.done, A.seq, lds);
 }
 
 template <int DT, int K>
 __global__ void __launch_bounds__(kBlock) trace_debug_kernel(RayArgs A)
 {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= A.n_rays) return;
+    const int S = A.segments;
+    const int total = A.n_rays * S;
+    const int p = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const bool valid = p < total;
+    const int j = valid ? p / S : 0;
+    const int seg = p & (S - 1);
+    const int i = A.rays[j];
     const float rx = A.dirs[i], ry = A.dirs[i + A.dir_stride], rz = A.dirs[i + 2 * A.dir_stride];
-    TraceOut t;
     if (start_occupied<DT>(A)) {
-        t.d = 0.0; t.hit = true; t.flags = kRayInCollision; t.visits = 1; t.hit_lin = A.lin0;
-    } else {
-        t = trace_ray<DT, K, true>(A, rx, ry, rz);
+        if (valid && seg == 0) {
+            A.dbg_hit[i] = A.lin0;
+            A.dbg_dist[i] = 0.0;
+            A.dbg_flags[i] = (uint8_t)(A.start_flags | kRayInCollision);
+            if (A.dbg_visits) A.dbg_visits[i] = 1;
+        }
+        return;
     }
-    A.dbg_hit[i] = t.hit ? t.hit_lin : -1;
-    A.dbg_dist[i] = t.d;
-    A.dbg_flags[i] = (uint8_t)t.flags;
-    if (A.dbg_visits) A.dbg_visits[i] = t.visits;
+    const RayOut o = trace_group<DT, K, true>(A, valid, seg, S, rx, ry, rz);
+    // the ray's visit count is the sum over its group
+    int v = o.visits_lane;
+    for (int off = 1; off < S; off <<= 1) v += __shfl_xor(v, off, kWave);
+    if (o.report) {
+        A.dbg_hit[i] = o.hit ? o.hit_lin : -1;
+        A.dbg_dist[i] = o.d;
+        A.dbg_flags[i] = (uint8_t)o.flags;
+        if (A.dbg_visits) A.dbg_visits[i] = v;
+    }
 }
 
 // LiDAR scan policy (Sec. III-G): point p gives direction p/|p| and distance |p|.
 // Non-finite points and points closer than min_range are skipped.
 __global__ void __launch_bounds__(kBlock) scan_rmp_kernel(ScanArgs A)
 {
-    __shared__ float lds[kWavesPerBlock * kPartialWords];
+    __shared__ float lds[kReduceLdsWords];
     Acc acc;
     acc.zero();
     const int stride = gridDim.x * kBlock;
@@ -308,29 +427,39 @@ __global__ void __launch_bounds__(kBlock) scan_rmp_kernel(ScanArgs A)
         acc.n_contrib += d64 < A.radius64 && vp > 0.0;
         policy_accumulate(A.pol, px * inv, py * inv, pz * inv, (float)d64, acc);
     }
-    grid_finish(acc, A.partials, A.ticket, A.rank_tol, A.n_points, 0u, A.result, lds);
+    grid_finish(acc, A.partials, A.ticket, A.rank_tol, A.n_points, 0u, A.result, A.done, A.seq, lds);
+}
+
+template <int DT, int K>
+hipError_t launch_k(const RayArgs &A, int grid, hipStream_t s, bool debug, hipEvent_t e0, hipEvent_t e1)
+{
+    const dim3 blk(kBlock);
+    if (debug) {
+        const dim3 g((A.n_rays * A.segments + kBlock - 1) / kBlock);
+        if (e0) hipExtLaunchKernelGGL(trace_debug_kernel<DT, K>, g, blk, 0, s, e0, e1, 0, A);
+        else trace_debug_kernel<DT, K><<<g, blk, 0, s>>>(A);
+    } else {
+        if (e0) hipExtLaunchKernelGGL(raycast_rmp_kernel<DT, K>, dim3(grid), blk, 0, s, e0, e1, 0, A);
+        else raycast_rmp_kernel<DT, K><<<grid, blk, 0, s>>>(A);
+    }
+    return hipGetLastError();
 }
 
 template <int DT>
 hipError_t launch_dt(const RayArgs &A, int grid, hipStream_t s, bool debug, hipEvent_t e0, hipEvent_t e1)
 {
-    const dim3 blk(kBlock);
-    if (debug) {
-        const dim3 g((A.n_rays + kBlock - 1) / kBlock);
-        if (e0) hipExtLaunchKernelGGL(trace_debug_kernel<DT, kLookahead>, g, blk, 0, s, e0, e1, 0, A);
-        else trace_debug_kernel<DT, kLookahead><<<g, blk, 0, s>>>(A);
-    } else {
-        if (e0) hipExtLaunchKernelGGL(raycast_rmp_kernel<DT, kLookahead>, dim3(grid), blk, 0, s, e0, e1, 0, A);
-        else raycast_rmp_kernel<DT, kLookahead><<<grid, blk, 0, s>>>(A);
+    switch (A.lookahead) {
+    case 4: return launch_k<DT, 4>(A, grid, s, debug, e0, e1);
+    case 16: return launch_k<DT, 16>(A, grid, s, debug, e0, e1);
+    default: return launch_k<DT, 8>(A, grid, s, debug, e0, e1);
     }
-    return hipGetLastError();
 }
 
 }  // namespace
 
-int ray_grid_blocks(int n_rays)
+int ray_grid_blocks(int lanes)
 {
-    int b = (n_rays + kBlock - 1) / kBlock;
+    int b = (lanes + kBlock - 1) / kBlock;
     return b < 1 ? 1 : (b > kMaxBlocks ? kMaxBlocks : b);
 }
 
@@ -350,7 +479,7 @@ hipError_t launch_scan(const ScanArgs &A, hipStream_t s, hipEvent_t e0, hipEvent
 
 hipError_t launch_raycast(const RayArgs &A, hipStream_t s, bool debug, hipEvent_t e0, hipEvent_t e1)
 {
-    const int grid = ray_grid_blocks(A.n_rays);
+    const int grid = ray_grid_blocks(A.n_rays * A.segments);
     switch (A.map.dtype) {
     case RMPC_TSDF_F32: return launch_dt<RMPC_TSDF_F32>(A, grid, s, debug, e0, e1);
     case RMPC_TSDF_F16: return launch_dt<RMPC_TSDF_F16>(A, grid, s, debug, e0, e1);

@@ -23,18 +23,21 @@ constexpr uint32_t kRayRangeTie = RMPC_RAY_RANGE_TIE;
 constexpr uint32_t kRayStartFace = RMPC_RAY_START_FACE;
 constexpr uint32_t kRayInCollision = RMPC_RAY_IN_COLLISION;
 
+// Per-axis parts of a voxel's element offset.  Brick counts per row and per plane are below
+// 2^24 for every grid the library accepts, so 24-bit multiplies (full rate) are exact; the
+// host guarantees the total offset fits 32 bits.
 __device__ __forceinline__ uint32_t addr_x(const MapView &m, int x)
 {
     return ((uint32_t)(x >> m.lbx) << (m.lbx + m.lby + m.lbz)) + (uint32_t)(x & ((1 << m.lbx) - 1));
 }
 __device__ __forceinline__ uint32_t addr_y(const MapView &m, int y)
 {
-    return (uint32_t)(y >> m.lby) * ((uint32_t)m.nbx << (m.lbx + m.lby + m.lbz)) +
+    return (__umul24((uint32_t)(y >> m.lby), (uint32_t)m.nbx) << (m.lbx + m.lby + m.lbz)) +
            ((uint32_t)(y & ((1 << m.lby) - 1)) << m.lbx);
 }
 __device__ __forceinline__ uint32_t addr_z(const MapView &m, int z)
 {
-    return (uint32_t)(z >> m.lbz) * ((uint32_t)(m.nbx * m.nby) << (m.lbx + m.lby + m.lbz)) +
+    return (__umul24((uint32_t)(z >> m.lbz), (uint32_t)(m.nbx * m.nby)) << (m.lbx + m.lby + m.lbz)) +
            ((uint32_t)(z & ((1 << m.lbz) - 1)) << (m.lbx + m.lby));
 }
 
@@ -102,79 +105,129 @@ struct Acc {
     }
 };
 
-// Butterfly reduction across the 64 lanes; every lane ends with the same total, combined
-// in a fixed pattern (so the result does not depend on timing).
-__device__ __forceinline__ void wave_reduce(Acc &a)
-{
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        Acc o;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) {
-            o.s[k] = __shfl_xor(a.s[k], off, kWave);
-            o.c[k] = __shfl_xor(a.c[k], off, kWave);
-        }
-        o.n_hit = __shfl_xor(a.n_hit, off, kWave);
-        o.n_contrib = __shfl_xor(a.n_contrib, off, kWave);
-        o.n_tie = __shfl_xor(a.n_tie, off, kWave);
-        o.visits = __shfl_xor(a.visits, off, kWave);
-        // lower lane first so both partners form the identical sum
-        if (threadIdx.x & off) {
-            Acc lo = o;
-            lo.merge(a);
-            a = lo;
-        } else {
-            a.merge(o);
-        }
-    }
-}
+// ------------------------------------------------------------------------------------
+// block and grid reductions of Acc
+//
+// A block writes one row per thread to LDS; 13 groups of 16 "column" lanes then merge one
+// quantity each (9 compensated pairs, 4 integers): lane q of a group merges rows q, q+16, ...
+// in row order, and the 16 lanes combine with a butterfly that always puts the lower lane
+// first.  Every step has a fixed order, so results do not depend on timing.
+// ------------------------------------------------------------------------------------
 
-// Block reduction: waves reduce, then wave totals are merged in wave order by thread 0.
-// Returns the total in thread 0.  `lds` holds kWavesPerBlock * kPartialWords words.
-__device__ __forceinline__ void block_reduce(Acc &a, float *lds)
-{
-    wave_reduce(a);
-    const int wid = threadIdx.x / kWave;
-    if ((threadIdx.x & (kWave - 1)) == 0) {
-        float *p = lds + wid * kPartialWords;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) { p[k] = a.s[k]; p[9 + k] = a.c[k]; }
-        int32_t *q = reinterpret_cast<int32_t *>(p + 18);
-        q[0] = a.n_hit; q[1] = a.n_contrib; q[2] = a.n_tie; q[3] = a.visits;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < kWavesPerBlock; ++w) {
-            const float *p = lds + w * kPartialWords;
-            Acc o;
-#pragma unroll
-            for (int k = 0; k < 9; ++k) { o.s[k] = p[k]; o.c[k] = p[9 + k]; }
-            const int32_t *q = reinterpret_cast<const int32_t *>(p + 18);
-            o.n_hit = q[0]; o.n_contrib = q[1]; o.n_tie = q[2]; o.visits = q[3];
-            a.merge(o);
-        }
-    }
-}
+constexpr int kRowWords = 23;                 // odd row stride: conflict-free column reads
+constexpr int kColumns = 13;                  // 9 pairs + 4 integers
+constexpr int kColLanes = 16;
+constexpr int kReduceLdsWords = kBlock * kRowWords;
+constexpr int kGroups = 8;                    // ticket groups (blocks b with b % 8 == g)
 
-__device__ __forceinline__ void store_partial(float *dst, const Acc &a)
+__device__ __forceinline__ void row_store(float *row, const Acc &a)
 {
 #pragma unroll
-    for (int k = 0; k < 9; ++k) { dst[k] = a.s[k]; dst[9 + k] = a.c[k]; }
-    int32_t *q = reinterpret_cast<int32_t *>(dst + 18);
+    for (int k = 0; k < 9; ++k) { row[k] = a.s[k]; row[9 + k] = a.c[k]; }
+    int32_t *q = reinterpret_cast<int32_t *>(row + 18);
     q[0] = a.n_hit; q[1] = a.n_contrib; q[2] = a.n_tie; q[3] = a.visits;
 }
 
-__device__ __forceinline__ void load_partial(const float *src, Acc &a)
+// Merge one column value (pair or integer) into (s, c).
+__device__ __forceinline__ void col_merge(int col, float &s, float &c, const float *src)
+{
+    if (col < 9) {
+        csum_merge(s, c, src[col], src[9 + col]);
+    } else {
+        const int32_t v = reinterpret_cast<const int32_t *>(src)[9 + col];
+        s = __int_as_float(__float_as_int(s) + v);
+    }
+}
+
+// Butterfly over the 16 lanes of a column group (lower lane first).
+__device__ __forceinline__ void col_butterfly(int col, float &s, float &c)
 {
 #pragma unroll
-    for (int k = 0; k < 9; ++k) { a.s[k] = src[k]; a.c[k] = src[9 + k]; }
-    const int32_t *q = reinterpret_cast<const int32_t *>(src + 18);
-    a.n_hit = q[0]; a.n_contrib = q[1]; a.n_tie = q[2]; a.visits = q[3];
+    for (int off = 1; off < kColLanes; off <<= 1) {
+        const float s2 = __shfl_xor(s, off, kWave);
+        const float c2 = __shfl_xor(c, off, kWave);
+        if (col < 9) {
+            if (threadIdx.x & off) {
+                float ls = s2, lc = c2;
+                csum_merge(ls, lc, s, c);
+                s = ls; c = lc;
+            } else {
+                csum_merge(s, c, s2, c2);
+            }
+        } else {
+            s = __int_as_float(__float_as_int(s) + __float_as_int(s2));
+        }
+    }
+}
+
+// Column lanes (threadIdx < 13 * 16) with q == 0 end up holding the block total of their
+// column; they write it to out[] in partial layout (18 floats, then 4 integers).
+__device__ __forceinline__ void block_reduce_store(const Acc &a, float *lds, float *out)
+{
+    row_store(lds + threadIdx.x * kRowWords, a);
+    __syncthreads();
+    const int col = threadIdx.x / kColLanes, q = threadIdx.x % kColLanes;
+    if (col < kColumns) {
+        float s = 0.0f, c = 0.0f;
+        for (int r = q; r < kBlock; r += kColLanes) col_merge(col, s, c, lds + r * kRowWords);
+        col_butterfly(col, s, c);
+        if (q == 0) {
+            if (col < 9) { out[col] = s; out[9 + col] = c; }
+            else out[9 + col] = s;
+        }
+    }
+}
+
+// Merge partial rows src[stride * j], j = 0..n-1 (global memory), column-wise, into out[]
+// (LDS).  Loads of one lane are independent and issued together.
+__device__ __forceinline__ void merge_partials(const float *src, int stride, int n, float *out)
+{
+    const int col = threadIdx.x / kColLanes, q = threadIdx.x % kColLanes;
+    if (col < kColumns) {
+        float s = 0.0f, c = 0.0f;
+        for (int j0 = q; j0 < n; j0 += 8 * kColLanes) {
+            float vs[8], vc[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int j = j0 + u * kColLanes;
+                const float *p = src + (size_t)stride * j;
+                vs[u] = j < n ? (col < 9 ? p[col] : p[9 + col]) : 0.0f;
+                vc[u] = j < n && col < 9 ? p[9 + col] : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (j0 + u * kColLanes < n) {
+                    if (col < 9) csum_merge(s, c, vs[u], vc[u]);
+                    else s = __int_as_float(__float_as_int(s) + __float_as_int(vs[u]));
+                }
+            }
+        }
+        col_butterfly(col, s, c);
+        if (q == 0) {
+            if (col < 9) { out[col] = s; out[9 + col] = c; }
+            else out[9 + col] = s;
+        }
+    }
 }
 
 // ------------------------------------------------------------------------------------
 // float64 resolve: f = S^+ b  (Eq. 1 with the pseudo-inverse cut rank_tol * lambda_max)
 // ------------------------------------------------------------------------------------
+
+// Reciprocal and reciprocal square root from the hardware estimates plus two Newton steps
+// (relative error near 1 ulp; a Jacobi rotation only needs c^2 + s^2 = 1 to that level).
+__device__ __forceinline__ double rcp64(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(fma(-x, r, 1.0), r, r);
+    return fma(fma(-x, r, 1.0), r, r);
+}
+__device__ __forceinline__ double rsqrt64(double x)
+{
+    double r = __builtin_amdgcn_rsq(x);
+    r = r * fma(-0.5 * x * r, r, 1.5);
+    return r * fma(-0.5 * x * r, r, 1.5);
+}
 
 // One Jacobi rotation in the (P, Q) plane that annihilates S[P][Q]; V accumulates the
 // eigenvectors as columns.  Compile-time indices keep everything in registers.
@@ -183,9 +236,18 @@ __device__ __forceinline__ void jacobi_rotate(double (&S)[3][3], double (&V)[3][
 {
     const double spq = S[P][Q];
     if (spq == 0.0) return;
-    const double theta = (S[Q][Q] - S[P][P]) / (2.0 * spq);
-    const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-    const double c = 1.0 / sqrt(t * t + 1.0);
+    const double theta = (S[Q][Q] - S[P][P]) * (0.5 * rcp64(spq));
+    const double at = fabs(theta);
+    // t = sign(theta) / (|theta| + sqrt(theta^2 + 1)), the smaller root of t^2 + 2 t theta = 1
+    double t;
+    if (at > 1e100) {
+        t = 0.5 * rcp64(theta);
+    } else {
+        const double y = fma(at, at, 1.0);
+        t = rcp64(at + y * rsqrt64(y));
+        t = theta < 0.0 ? -t : t;
+    }
+    const double c = rsqrt64(fma(t, t, 1.0));
     const double s = t * c;
     constexpr int R = 3 - P - Q;                 // the untouched index
     const double spp = S[P][P], sqq = S[Q][Q], srp = S[R][P], srq = S[R][Q];
@@ -287,36 +349,70 @@ __device__ inline void finalize_result(const Acc &a, double rank_tol, int32_t n_
     out->visits = a.visits;
 }
 
-// Grid-level finish: every block stores its partial; the last block to arrive (ticket)
-// merges all partials in block order and resolves.  Deterministic for a fixed grid.
-__device__ inline void grid_finish(Acc &a, float *partials, uint32_t *ticket, double rank_tol,
-                                   int32_t n_rays, uint32_t extra_flags, rmpc_result *out,
-                                   float *lds)
+__device__ __forceinline__ void acc_from_partial(const float *p, Acc &a)
 {
-    __shared__ int is_last;
-    block_reduce(a, lds);
-    if (threadIdx.x == 0) {
-        store_partial(partials + (size_t)blockIdx.x * kPartialWords, a);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) { a.s[k] = p[k]; a.c[k] = p[9 + k]; }
+    const int32_t *q = reinterpret_cast<const int32_t *>(p + 18);
+    a.n_hit = q[0]; a.n_contrib = q[1]; a.n_tie = q[2]; a.visits = q[3];
+}
+
+// Grid-level finish.  Every block stores its partial; blocks form kGroups groups (b % 8);
+// the last block of a group to arrive merges the group's partials into a group partial, and
+// the last group merger merges the group partials and resolves.  Tickets live in
+// ticket[0..kGroups] and are reset for the next launch by the final block.  Deterministic for
+// a fixed grid: every merge runs in a fixed order.
+//   partials: kMaxBlocks block rows, then kGroups group rows (kPartialWords each).
+//   done/seq: after the result is written, *done is set to seq (host-visible completion).
+__device__ inline void grid_finish(const Acc &a, float *partials, uint32_t *ticket, double rank_tol,
+                                   int32_t n_rays, uint32_t extra_flags, rmpc_result *out,
+                                   uint64_t *done, uint64_t seq, float *lds)
+{
+    __shared__ int stage;                    // 0 done, 1 group merger, 2 final merger
+    __shared__ float tot[kPartialWords];
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int g = b % kGroups;
+    const int ngroups = nb < kGroups ? nb : kGroups;
+    const int in_group = (nb - g + kGroups - 1) / kGroups;
+    block_reduce_store(a, lds, tot);
+    __syncthreads();
+    float *grow = partials + (size_t)kMaxBlocks * kPartialWords;
+    if (threadIdx.x < kWave) {               // wave 0 stores the block row, then takes a ticket
+        if (threadIdx.x < 22) partials[(size_t)b * kPartialWords + threadIdx.x] = tot[threadIdx.x];
         __threadfence();
-        const uint32_t prev = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL,
-                                                     __HIP_MEMORY_SCOPE_AGENT);
-        is_last = prev == gridDim.x - 1;
+        if (threadIdx.x == 0) {
+            const uint32_t prev = __hip_atomic_fetch_add(ticket + g, 1u, __ATOMIC_ACQ_REL,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+            stage = prev == (uint32_t)(in_group - 1) ? 1 : 0;
+        }
     }
     __syncthreads();
-    if (!is_last) return;
+    if (stage == 0) return;
     __threadfence();
-    Acc t;
-    t.zero();
-    for (uint32_t blk = threadIdx.x; blk < gridDim.x; blk += kBlock) {
-        Acc o;
-        load_partial(partials + (size_t)blk * kPartialWords, o);
-        t.merge(o);
+    merge_partials(partials + (size_t)g * kPartialWords, kGroups * kPartialWords, in_group, tot);
+    __syncthreads();
+    if (threadIdx.x < kWave) {
+        if (threadIdx.x < 22) grow[(size_t)g * kPartialWords + threadIdx.x] = tot[threadIdx.x];
+        __threadfence();
+        if (threadIdx.x == 0) {
+            const uint32_t prev = __hip_atomic_fetch_add(ticket + kGroups, 1u, __ATOMIC_ACQ_REL,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+            stage = prev == (uint32_t)(ngroups - 1) ? 2 : 0;
+        }
     }
-    __syncthreads();                       // lds reuse
-    block_reduce(t, lds);
+    __syncthreads();
+    if (stage != 2) return;
+    __threadfence();
+    merge_partials(grow, kPartialWords, ngroups, tot);
+    __syncthreads();
     if (threadIdx.x == 0) {
+        Acc t;
+        acc_from_partial(tot, t);
+        for (int k = 0; k <= kGroups; ++k)
+            __hip_atomic_store(ticket + k, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         finalize_result(t, rank_tol, n_rays, extra_flags, out);
-        __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // publish: the result is visible to the host before the sequence number
+        __hip_atomic_store(done, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 

@@ -8,8 +8,8 @@
 
 namespace rmpc {
 
-// Voxel visits planned ahead per lane and round of the traversal.
-constexpr int kLookahead = 4;
+// Voxel visits planned ahead per lane and round of the traversal (4, 8 or 16).
+constexpr int kLookahead = 16;
 
 // Block-partial slots of one reduction (one per block of a launch).
 constexpr int kMaxPartialSlots = 4096;
@@ -36,12 +36,16 @@ struct RayArgs {
     MapView map;
     const float *dirs;           // direction table, structure of arrays: x[], y[], z[]
     int32_t dir_stride;          // elements between the x, y and z arrays
+    const int32_t *rays;         // the n_rays Halton indices to cast, in direction-coherent order
     int32_t n_rays;
     float g[3];                  // start in grid units, float32((x - origin) / h)
     int32_t v0[3];               // start voxel floor(g)
     int32_t lin0;                // its logical index
     uint32_t start_flags;        // RMPC_RAY_START_FACE when g is within 1e-5 of a face
     float tmax_lo, tmax_hi;      // float32 guard band around max_range / h
+    double tmax_v;               // parameter span split into segments: min(max_range / h, grid diagonal)
+    int32_t segments;            // lanes per ray (1, 2, 4, 8 or 16)
+    int32_t lookahead;           // voxel visits planned per round (4, 8 or 16)
     double max_range, h;
     double vel64[3];             // velocity, float64 (for the exact contribution count)
     double radius64;
@@ -50,6 +54,8 @@ struct RayArgs {
     float *partials;             // per-block partial sums
     uint32_t *ticket;            // arrival counter, zero between launches
     rmpc_result *result;         // written by the last block
+    uint64_t *done;              // host-visible completion word, set to seq after the result
+    uint64_t seq;
     // debug outputs (trace kernel only)
     int32_t *dbg_hit;
     double *dbg_dist;
@@ -69,11 +75,22 @@ struct ScanArgs {
     float *partials;
     uint32_t *ticket;
     rmpc_result *result;
+    uint64_t *done;
+    uint64_t seq;
 };
 
 struct DirsArgs {
     float *out;                  // structure of arrays with stride n
     int32_t n;
+};
+
+// Keep, in order, the entries of `order` (a permutation of 0..n_all-1) that are < n.
+struct CompactArgs {
+    const int32_t *order;
+    int32_t n_all;
+    int32_t n;
+    int32_t *counts;             // n_all / 1024 per-chunk counts (scratch)
+    int32_t *out;                // n entries
 };
 
 struct LayoutArgs {
@@ -93,5 +110,6 @@ hipError_t launch_scan(const ScanArgs &a, hipStream_t s, hipEvent_t ev0 = nullpt
                        hipEvent_t ev1 = nullptr);
 hipError_t launch_directions(const DirsArgs &a, hipStream_t s);
 hipError_t launch_layout(const LayoutArgs &a, hipStream_t s);
+hipError_t launch_compact(const CompactArgs &a, hipStream_t s);
 
 }  // namespace rmpc

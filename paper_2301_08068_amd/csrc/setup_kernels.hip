@@ -68,7 +68,54 @@ __global__ void layout_kernel(LayoutArgs A, T pad)
     static_cast<T *>(const_cast<void *>(m.data))[e] = v;
 }
 
+// Chunk-wise count of entries < n (one 1024-entry chunk per block).
+__global__ void __launch_bounds__(1024) compact_count_kernel(CompactArgs A)
+{
+    __shared__ int wsum[16];
+    const int j = blockIdx.x * 1024 + threadIdx.x;
+    const bool keep = j < A.n_all && A.order[j] < A.n;
+    const uint64_t m = __ballot(keep);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = __popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < 16; ++w) t += wsum[w];
+        A.counts[blockIdx.x] = t;
+    }
+}
+
+// Stable scatter of the kept entries: chunk offset from the counts of earlier chunks,
+// wave offset from earlier waves, lane offset from the ballot.
+__global__ void __launch_bounds__(1024) compact_scatter_kernel(CompactArgs A)
+{
+    __shared__ int wsum[16];
+    __shared__ int base;
+    const int j = blockIdx.x * 1024 + threadIdx.x;
+    const bool keep = j < A.n_all && A.order[j] < A.n;
+    const uint64_t m = __ballot(keep);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) wsum[w] = __popcll(m);
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int b = 0; b < (int)blockIdx.x; ++b) t += A.counts[b];
+        base = t;
+    }
+    __syncthreads();
+    int off = base;
+    for (int u = 0; u < w; ++u) off += wsum[u];
+    off += __popcll(m & ((1ull << lane) - 1ull));
+    if (keep) A.out[off] = A.order[j];
+}
+
 }  // namespace
+
+hipError_t launch_compact(const CompactArgs &a, hipStream_t s)
+{
+    const int blocks = (a.n_all + 1023) / 1024;
+    compact_count_kernel<<<blocks, 1024, 0, s>>>(a);
+    compact_scatter_kernel<<<blocks, 1024, 0, s>>>(a);
+    return hipGetLastError();
+}
 
 hipError_t launch_directions(const DirsArgs &a, hipStream_t s)
 {
