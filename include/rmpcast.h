@@ -174,6 +174,65 @@ rmpc_status rmpc_trace_debug(rmpc_ctx *ctx, int32_t map_id, const double x[3], i
                              const rmpc_params *params, void *hip_stream, int32_t *hit_lin_dev,
                              double *dist_dev, uint8_t *flags_dev, int32_t *visits_dev);
 
+/* A query of a batch. */
+#define RMPC_KIND_MAP 0
+#define RMPC_KIND_SCAN 1
+typedef struct {
+    int32_t kind;               /* RMPC_KIND_MAP or RMPC_KIND_SCAN */
+    int32_t map_id;             /* map queries: the resident map */
+    int32_t n;                  /* map queries: rays (1..65536); scan queries: points (0..2^24) */
+    int32_t reserved;
+    double x[3];                /* map queries: position (world, metres) */
+    double v[3];                /* velocity */
+    const float *points_dev;    /* scan queries: n x 3 float32 on the device (robot-relative) */
+} rmpc_query_desc;
+
+/* Launch configuration (rmpc_config_set, rmpc_tune_batch).  Results do not depend on
+ * lookahead, blocks_per_cu or use_graph; the segmentation (lane_target_log2) changes only the
+ * summation order. */
+#define RMPC_CONFIG_QUERY 0     /* rmpc_query and rmpc_trace_debug */
+#define RMPC_CONFIG_BATCH 1     /* rmpc_query_batch */
+typedef struct {
+    int32_t lookahead;          /* voxel visits planned per round: 4, 8 or 16 */
+    int32_t lane_target_log2;   /* split rays into segments until a query has ~2^this lanes (10..22) */
+    int32_t blocks_per_cu;      /* batches: resident blocks per CU of the persistent kernel (0 = max) */
+    int32_t use_graph;          /* batches: 1 = replay the launch from a captured hipGraph */
+} rmpc_launch_config;
+
+/*
+ * rmpc_query_batch -- many map and scan queries in one persistent fused launch (the
+ * combination of Sec. III-E/III-G applied to each query independently).
+ *   q[n]: queries, 1 <= n; map queries use map_params, scan queries scan_params (either may
+ *     be NULL if no query of that kind is present).
+ *   out[n]: host results, the same as rmpc_query / rmpc_scan_query would return for each
+ *     query alone; bitwise identical when the query's ray segmentation is the same.
+ * Queries are validated first; any invalid one fails the whole call (the message names its
+ * index) and nothing is written.  Large batches are split into several launches.  Blocking.
+ * Errors: RMPC_E_INVALID, RMPC_E_NOMAP, RMPC_E_OUT_OF_BOUNDS, RMPC_E_NOMEM, RMPC_E_HIP.
+ */
+rmpc_status rmpc_query_batch(rmpc_ctx *ctx, const rmpc_query_desc *q, int32_t n,
+                             const rmpc_params *map_params, const rmpc_params *scan_params,
+                             void *hip_stream, rmpc_result *out);
+
+/* rmpc_config_set / _get -- the launch configuration of single queries (which =
+ * RMPC_CONFIG_QUERY) or of batches (RMPC_CONFIG_BATCH).  Errors: RMPC_E_INVALID. */
+rmpc_status rmpc_config_set(rmpc_ctx *ctx, int32_t which, const rmpc_launch_config *cfg);
+rmpc_status rmpc_config_get(rmpc_ctx *ctx, int32_t which, rmpc_launch_config *cfg);
+
+/*
+ * rmpc_tune_batch -- time rmpc_query_batch on this batch for a grid of configurations
+ * (lookahead, segmentation target, resident blocks) and keep the fastest as the context's
+ * RMPC_CONFIG_BATCH (use_graph is kept as set).
+ *   cache_path: optional JSON file; a configuration cached there under this GPU's
+ *     architecture, the batch's storage types and its mean ray count bucket is used without
+ *     timing, and a newly timed one is added.  NULL: no file.
+ *   best: optional, receives the chosen configuration.
+ * Runs the batch several times.  Errors: as rmpc_query_batch.
+ */
+rmpc_status rmpc_tune_batch(rmpc_ctx *ctx, const rmpc_query_desc *q, int32_t n,
+                            const rmpc_params *map_params, const rmpc_params *scan_params,
+                            void *hip_stream, const char *cache_path, rmpc_launch_config *best);
+
 /* rmpc_directions -- copy the first n (1 <= n <= RMPC_MAX_RAYS) ray directions, float32
  * x,y,z triples, into host memory out_host[3n] (Sec. III-E Eq. 10). */
 rmpc_status rmpc_directions(rmpc_ctx *ctx, int32_t n, float *out_host);

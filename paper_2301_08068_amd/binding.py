@@ -42,6 +42,20 @@ class Params(C.Structure):
                                           "eps", "max_range_m", "rank_tol", "min_range_m")]
 
 
+class QueryDesc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("map_id", C.c_int32), ("n", C.c_int32), ("reserved", C.c_int32),
+                ("x", C.c_double * 3), ("v", C.c_double * 3), ("points_dev", C.c_void_p)]
+
+
+class LaunchConfig(C.Structure):
+    _fields_ = [("lookahead", C.c_int32), ("lane_target_log2", C.c_int32),
+                ("blocks_per_cu", C.c_int32), ("use_graph", C.c_int32)]
+
+
+KIND_MAP, KIND_SCAN = 0, 1
+CONFIG_QUERY, CONFIG_BATCH = 0, 1
+
+
 class Result(C.Structure):
     _fields_ = [("f", C.c_double * 3), ("A", C.c_double * 9), ("b", C.c_double * 3),
                 ("lam", C.c_double * 3), ("rank", C.c_int32), ("n_hit", C.c_int32),
@@ -67,6 +81,12 @@ _SIGS = {
     "rmpc_trace_debug": [C.c_void_p, C.c_int32, _P(C.c_double), C.c_int32, _P(Params), C.c_void_p,
                          C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
     "rmpc_directions": [C.c_void_p, C.c_int32, _P(C.c_float)],
+    "rmpc_query_batch": [C.c_void_p, _P(QueryDesc), C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                         _P(Result)],
+    "rmpc_config_set": [C.c_void_p, C.c_int32, _P(LaunchConfig)],
+    "rmpc_config_get": [C.c_void_p, C.c_int32, _P(LaunchConfig)],
+    "rmpc_tune_batch": [C.c_void_p, _P(QueryDesc), C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                        C.c_char_p, _P(LaunchConfig)],
     "rmpc_set_profiling": [C.c_void_p, C.c_int],
     "rmpc_get_profile": [C.c_void_p, _P(C.c_double), _P(C.c_int64)],
 }
@@ -178,6 +198,54 @@ def rmpc_directions(ctx: int, n: int) -> np.ndarray:
     return out
 
 
+def query_descs(queries) -> "C.Array":
+    """Build a QueryDesc array from dicts: {"kind": "map", "map_id", "n", "x", "v"} or
+    {"kind": "scan", "points_ptr", "n", "v"}."""
+    arr = (QueryDesc * len(queries))()
+    for k, q in enumerate(queries):
+        d = arr[k]
+        d.kind = KIND_MAP if q["kind"] == "map" else KIND_SCAN
+        d.map_id = int(q.get("map_id", -1))
+        d.n = int(q["n"])
+        d.x = _d3(q.get("x", (0.0, 0.0, 0.0)))
+        d.v = _d3(q["v"])
+        d.points_dev = C.c_void_p(int(q.get("points_ptr", 0)) or None)
+    return arr
+
+
+def rmpc_query_batch(ctx: int, descs, map_params: Optional[Dict[str, float]],
+                     scan_params: Optional[Dict[str, float]], stream=None) -> list:
+    n = len(descs)
+    out = (Result * n)()
+    mp = C.byref(params_struct(map_params)) if map_params else None
+    sp = C.byref(params_struct(scan_params)) if scan_params else None
+    _check(_lib.rmpc_query_batch(C.c_void_p(ctx), descs, n, mp, sp, C.c_void_p(_stream_ptr(stream)), out),
+           "rmpc_query_batch")
+    return [result_dict(r) for r in out]
+
+
+def rmpc_config_set(ctx: int, which: int, lookahead: int, lane_target_log2: int,
+                    blocks_per_cu: int = 0, use_graph: int = 0) -> None:
+    cfg = LaunchConfig(lookahead, lane_target_log2, blocks_per_cu, use_graph)
+    _check(_lib.rmpc_config_set(C.c_void_p(ctx), which, C.byref(cfg)), "rmpc_config_set")
+
+
+def rmpc_config_get(ctx: int, which: int) -> Dict[str, int]:
+    cfg = LaunchConfig()
+    _check(_lib.rmpc_config_get(C.c_void_p(ctx), which, C.byref(cfg)), "rmpc_config_get")
+    return {k: getattr(cfg, k) for k, _ in LaunchConfig._fields_}
+
+
+def rmpc_tune_batch(ctx: int, descs, map_params, scan_params, cache_path: Optional[str] = None,
+                    stream=None) -> Dict[str, int]:
+    cfg = LaunchConfig()
+    mp = C.byref(params_struct(map_params)) if map_params else None
+    sp = C.byref(params_struct(scan_params)) if scan_params else None
+    _check(_lib.rmpc_tune_batch(C.c_void_p(ctx), descs, len(descs), mp, sp, C.c_void_p(_stream_ptr(stream)),
+                                cache_path.encode() if cache_path else None, C.byref(cfg)), "rmpc_tune_batch")
+    return {k: getattr(cfg, k) for k, _ in LaunchConfig._fields_}
+
+
 def rmpc_set_profiling(ctx: int, enable: bool) -> None:
     _check(_lib.rmpc_set_profiling(C.c_void_p(ctx), int(bool(enable))), "rmpc_set_profiling")
 
@@ -257,3 +325,26 @@ class Context:
 
     def directions(self, n: int) -> np.ndarray:
         return rmpc_directions(self.ptr, n)
+
+    def query_batch(self, queries, map_params=None, scan_params=None) -> list:
+        """queries: list of dicts (see query_descs); scan points as cuda float32 tensors under
+        "points" are kept alive here for the call."""
+        keep = []
+        qs = []
+        for q in queries:
+            q = dict(q)
+            if q["kind"] == "scan" and "points" in q:
+                pts = q.pop("points")
+                keep.append(pts)
+                q["points_ptr"] = pts.data_ptr()
+                q["n"] = pts.shape[0]
+            qs.append(q)
+        return rmpc_query_batch(self.ptr, query_descs(qs), map_params, scan_params, stream=self.stream)
+
+    def config(self, which: int, **kw) -> Dict[str, int]:
+        cur = rmpc_config_get(self.ptr, which)
+        if kw:
+            cur.update(kw)
+            rmpc_config_set(self.ptr, which, cur["lookahead"], cur["lane_target_log2"],
+                            cur["blocks_per_cu"], cur["use_graph"])
+        return cur

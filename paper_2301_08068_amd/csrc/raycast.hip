@@ -330,20 +330,20 @@ __device__ __forceinline__ int xcd_tile(int b, int nb)
     return x * q + (x < r ? x : r) + (b >> 3);
 }
 
-// Lane -> (ray position, segment); the grid covers every lane once (n_rays * S lanes), so a
-// lane traces first and only then holds accumulators.  Waves stay whole: the traversal uses
-// wave-wide ballots, and lanes past the end take part as idle members.
+// One 256-lane tile of a map query: lane -> (ray position, segment).  Waves stay whole (the
+// traversal uses wave-wide ballots); lanes past the end, or whose list entry is >= n_rays,
+// take part as idle members.  A lane traces first and only then holds accumulators.
 template <int DT, int K>
-__global__ void __launch_bounds__(kBlock) raycast_rmp_kernel(RayArgs A)
+__device__ __forceinline__ void ray_tile(const RayArgs &A, int tile, int n_tiles, const FinishSlots &F,
+                                         float *lds)
 {
-    __shared__ float lds[kReduceLdsWords];
     const bool in_coll = start_occupied<DT>(A);
     const int S = A.segments;
-    const int p = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    const bool valid = p < A.n_rays * S;
-    const int j = valid ? p / S : 0;
+    const int p = tile * kBlock + threadIdx.x;
+    const int j = p < A.n_list * S ? p / S : 0;
     const int seg = p & (S - 1);
     const int i = A.rays[j];
+    const bool valid = p < A.n_list * S && i < A.n_rays;
     const float rx = A.dirs[i], ry = A.dirs[i + A.dir_stride], rz = A.dirs[i + 2 * A.dir_stride];
     Acc acc;
     acc.zero();
@@ -366,20 +366,124 @@ __global__ void __launch_bounds__(kBlock) raycast_rmp_kernel(RayArgs A)
             }
         }
     }
-    grid_finish(acc, A.partials, A.ticket, A.rank_tol, A.n_rays,
-                in_coll ? RMPC_Q_IN_COLLISION : 0u, A.result, A.done, A.seq, lds);
+    grid_finish(acc, tile, n_tiles, F, A.rank_tol, A.n_rays, in_coll ? RMPC_Q_IN_COLLISION : 0u, lds);
+}
+
+// One tile of a LiDAR scan query (Sec. III-G): point p gives direction p/|p| and distance
+// |p|; non-finite points and points closer than min_range are skipped.  Tile t covers points
+// t*256 + lane + k * n_tiles * 256.
+__device__ __forceinline__ void scan_tile(const ScanArgs &A, int tile, int n_tiles, const FinishSlots &F,
+                                          float *lds)
+{
+    Acc acc;
+    acc.zero();
+    const int stride = n_tiles * kBlock;
+    for (int i = tile * kBlock + threadIdx.x; i < A.n_points; i += stride) {
+        const float px = A.points[3 * (size_t)i], py = A.points[3 * (size_t)i + 1],
+                    pz = A.points[3 * (size_t)i + 2];
+        if (!(isfinite(px) && isfinite(py) && isfinite(pz))) continue;
+        double n2, vp;
+        {
+#pragma clang fp contract(off)
+            n2 = ((double)px * (double)px + (double)py * (double)py) + (double)pz * (double)pz;
+            vp = (A.vel64[0] * (double)px + A.vel64[1] * (double)py) + A.vel64[2] * (double)pz;
+        }
+        if (!(n2 >= A.min_range2)) continue;
+        const double d64 = sqrt(n2);
+        const float inv = (float)(1.0 / d64);
+        acc.n_hit += 1;
+        acc.n_contrib += d64 < A.radius64 && vp > 0.0;
+        policy_accumulate(A.pol, px * inv, py * inv, pz * inv, (float)d64, acc);
+    }
+    grid_finish(acc, tile, n_tiles, F, A.rank_tol, A.n_points, 0u, lds);
+}
+
+__device__ __forceinline__ FinishSlots single_slots(float *partials, uint32_t *ticket, rmpc_result *out,
+                                                    uint64_t *done, uint64_t seq)
+{
+    FinishSlots F;
+    F.tile_rows = partials;
+    F.group_rows = partials + (size_t)kMaxBlocks * kPartialWords;
+    F.tickets = ticket;
+    F.out = out;
+    F.finished = nullptr;
+    F.n_queries = 1;
+    F.done = done;
+    F.seq = seq;
+    return F;
+}
+
+// One map query per launch; block b takes tile xcd_tile(b).
+template <int DT, int K>
+__global__ void __launch_bounds__(kBlock) raycast_rmp_kernel(RayArgs A)
+{
+    __shared__ float lds[kReduceLdsWords];
+    ray_tile<DT, K>(A, xcd_tile(blockIdx.x, gridDim.x), gridDim.x,
+                    single_slots(A.partials, A.ticket, A.result, A.done, A.seq), lds);
+}
+
+// Many map and scan queries in one persistent launch: resident blocks take tiles from a
+// counter (work[0]) until none are left; tile rows, tickets and results are per query, so a
+// query's result does not depend on which block ran which tile.  The last block to leave
+// resets the counters for the next launch.
+template <int K>
+__global__ void __launch_bounds__(kBlock) batch_kernel(BatchArgs B)
+{
+    __shared__ float lds[kReduceLdsWords];
+    __shared__ int s_tile;
+    const int n_tiles = B.hdr->n_tiles;
+    const int n_queries = B.hdr->n_queries;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0)
+            s_tile = (int)__hip_atomic_fetch_add(B.work, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const int tile = s_tile;
+        if (tile >= n_tiles) break;
+        int lo = 0, hi = n_queries - 1;      // last query with tile_begin <= tile
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (B.q[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
+        }
+        const BatchQuery &Q = B.q[lo];
+        FinishSlots F;
+        F.tile_rows = B.partials + (size_t)Q.tile_begin * kPartialWords;
+        F.group_rows = B.partials + (size_t)(B.group_row_base + lo * kGroups) * kPartialWords;
+        F.tickets = B.tickets + lo * (kGroups + 1);
+        F.out = B.results + lo;
+        F.finished = B.work + 2;
+        F.n_queries = n_queries;
+        F.done = B.done;
+        F.seq = B.hdr->seq;
+        const int t = tile - Q.tile_begin;
+        if (Q.kind == 0) {
+            switch (Q.ray.map.dtype) {
+            case RMPC_TSDF_F32: ray_tile<RMPC_TSDF_F32, K>(Q.ray, t, Q.n_tiles, F, lds); break;
+            case RMPC_TSDF_F16: ray_tile<RMPC_TSDF_F16, K>(Q.ray, t, Q.n_tiles, F, lds); break;
+            default: ray_tile<RMPC_OCC_U8, K>(Q.ray, t, Q.n_tiles, F, lds); break;
+            }
+        } else {
+            scan_tile(Q.scan, t, Q.n_tiles, F, lds);
+        }
+    }
+    if (threadIdx.x == 0) {
+        const uint32_t prev = __hip_atomic_fetch_add(B.work + 1, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (prev == gridDim.x - 1) {
+            __hip_atomic_store(B.work, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(B.work + 1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
 }
 
 template <int DT, int K>
 __global__ void __launch_bounds__(kBlock) trace_debug_kernel(RayArgs A)
 {
     const int S = A.segments;
-    const int total = A.n_rays * S;
     const int p = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    const bool valid = p < total;
-    const int j = valid ? p / S : 0;
+    const int j = p < A.n_list * S ? p / S : 0;
     const int seg = p & (S - 1);
     const int i = A.rays[j];
+    const bool valid = p < A.n_list * S && i < A.n_rays;
     const float rx = A.dirs[i], ry = A.dirs[i + A.dir_stride], rz = A.dirs[i + 2 * A.dir_stride];
     if (start_occupied<DT>(A)) {
         if (valid && seg == 0) {
@@ -402,32 +506,11 @@ __global__ void __launch_bounds__(kBlock) trace_debug_kernel(RayArgs A)
     }
 }
 
-// LiDAR scan policy (Sec. III-G): point p gives direction p/|p| and distance |p|.
-// Non-finite points and points closer than min_range are skipped.
+// One scan query per launch.
 __global__ void __launch_bounds__(kBlock) scan_rmp_kernel(ScanArgs A)
 {
     __shared__ float lds[kReduceLdsWords];
-    Acc acc;
-    acc.zero();
-    const int stride = gridDim.x * kBlock;
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < A.n_points; i += stride) {
-        const float px = A.points[3 * (size_t)i], py = A.points[3 * (size_t)i + 1],
-                    pz = A.points[3 * (size_t)i + 2];
-        if (!(isfinite(px) && isfinite(py) && isfinite(pz))) continue;
-        double n2, vp;
-        {
-#pragma clang fp contract(off)
-            n2 = ((double)px * (double)px + (double)py * (double)py) + (double)pz * (double)pz;
-            vp = (A.vel64[0] * (double)px + A.vel64[1] * (double)py) + A.vel64[2] * (double)pz;
-        }
-        if (!(n2 >= A.min_range2)) continue;
-        const double d64 = sqrt(n2);
-        const float inv = (float)(1.0 / d64);
-        acc.n_hit += 1;
-        acc.n_contrib += d64 < A.radius64 && vp > 0.0;
-        policy_accumulate(A.pol, px * inv, py * inv, pz * inv, (float)d64, acc);
-    }
-    grid_finish(acc, A.partials, A.ticket, A.rank_tol, A.n_points, 0u, A.result, A.done, A.seq, lds);
+    scan_tile(A, blockIdx.x, gridDim.x, single_slots(A.partials, A.ticket, A.result, A.done, A.seq), lds);
 }
 
 template <int DT, int K>
@@ -435,7 +518,7 @@ hipError_t launch_k(const RayArgs &A, int grid, hipStream_t s, bool debug, hipEv
 {
     const dim3 blk(kBlock);
     if (debug) {
-        const dim3 g((A.n_rays * A.segments + kBlock - 1) / kBlock);
+        const dim3 g((A.n_list * A.segments + kBlock - 1) / kBlock);
         if (e0) hipExtLaunchKernelGGL(trace_debug_kernel<DT, K>, g, blk, 0, s, e0, e1, 0, A);
         else trace_debug_kernel<DT, K><<<g, blk, 0, s>>>(A);
     } else {
@@ -477,9 +560,31 @@ hipError_t launch_scan(const ScanArgs &A, hipStream_t s, hipEvent_t e0, hipEvent
     return hipGetLastError();
 }
 
+int batch_blocks_per_cu(int lookahead)
+{
+    int nb = 0;
+    hipError_t e;
+    switch (lookahead) {
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel<4>, kBlock, 0); break;
+    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel<16>, kBlock, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel<8>, kBlock, 0); break;
+    }
+    return e == hipSuccess && nb > 0 ? nb : 1;
+}
+
+hipError_t launch_batch(const BatchArgs &a, int blocks, int lookahead, hipStream_t s)
+{
+    switch (lookahead) {
+    case 4: batch_kernel<4><<<blocks, kBlock, 0, s>>>(a); break;
+    case 16: batch_kernel<16><<<blocks, kBlock, 0, s>>>(a); break;
+    default: batch_kernel<8><<<blocks, kBlock, 0, s>>>(a); break;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_raycast(const RayArgs &A, hipStream_t s, bool debug, hipEvent_t e0, hipEvent_t e1)
 {
-    const int grid = ray_grid_blocks(A.n_rays * A.segments);
+    const int grid = ray_grid_blocks(A.n_list * A.segments);
     switch (A.map.dtype) {
     case RMPC_TSDF_F32: return launch_dt<RMPC_TSDF_F32>(A, grid, s, debug, e0, e1);
     case RMPC_TSDF_F16: return launch_dt<RMPC_TSDF_F16>(A, grid, s, debug, e0, e1);

@@ -118,7 +118,7 @@ constexpr int kRowWords = 23;                 // odd row stride: conflict-free c
 constexpr int kColumns = 13;                  // 9 pairs + 4 integers
 constexpr int kColLanes = 16;
 constexpr int kReduceLdsWords = kBlock * kRowWords;
-constexpr int kGroups = 8;                    // ticket groups (blocks b with b % 8 == g)
+
 
 __device__ __forceinline__ void row_store(float *row, const Acc &a)
 {
@@ -357,31 +357,41 @@ __device__ __forceinline__ void acc_from_partial(const float *p, Acc &a)
     a.n_hit = q[0]; a.n_contrib = q[1]; a.n_tie = q[2]; a.visits = q[3];
 }
 
-// Grid-level finish.  Every block stores its partial; blocks form kGroups groups (b % 8);
-// the last block of a group to arrive merges the group's partials into a group partial, and
-// the last group merger merges the group partials and resolves.  Tickets live in
-// ticket[0..kGroups] and are reset for the next launch by the final block.  Deterministic for
-// a fixed grid: every merge runs in a fixed order.
-//   partials: kMaxBlocks block rows, then kGroups group rows (kPartialWords each).
-//   done/seq: after the result is written, *done is set to seq (host-visible completion).
-__device__ inline void grid_finish(const Acc &a, float *partials, uint32_t *ticket, double rank_tol,
-                                   int32_t n_rays, uint32_t extra_flags, rmpc_result *out,
-                                   uint64_t *done, uint64_t seq, float *lds)
+// Where one reduction keeps its state: tile rows (one per tile), kGroups group rows, kGroups+1
+// tickets, the result slot, and the completion publication.  A batch shares `finished`
+// (queries done so far) among its queries and publishes once, when the last one is done.
+struct FinishSlots {
+    float *tile_rows;
+    float *group_rows;
+    uint32_t *tickets;
+    rmpc_result *out;
+    uint32_t *finished;          // null for a single query
+    int32_t n_queries;
+    uint64_t *done;
+    uint64_t seq;
+};
+
+// Finish tile b of nb.  Every tile stores its partial in row b; tiles form kGroups groups
+// (b % 8); the last tile of a group to arrive merges the group's rows into a group row, and
+// the last group merger merges the group rows and resolves.  Tickets are reset for the next
+// launch by the final merger.  Deterministic for a fixed tiling: every merge has a fixed
+// order.  All threads of the block call this and return together (except the final merger's
+// thread 0, which finishes alone).
+__device__ inline void grid_finish(const Acc &a, int b, int nb, const FinishSlots &F,
+                                   double rank_tol, int32_t n_rays, uint32_t extra_flags, float *lds)
 {
     __shared__ int stage;                    // 0 done, 1 group merger, 2 final merger
     __shared__ float tot[kPartialWords];
-    const int nb = gridDim.x, b = blockIdx.x;
     const int g = b % kGroups;
     const int ngroups = nb < kGroups ? nb : kGroups;
     const int in_group = (nb - g + kGroups - 1) / kGroups;
     block_reduce_store(a, lds, tot);
     __syncthreads();
-    float *grow = partials + (size_t)kMaxBlocks * kPartialWords;
-    if (threadIdx.x < kWave) {               // wave 0 stores the block row, then takes a ticket
-        if (threadIdx.x < 22) partials[(size_t)b * kPartialWords + threadIdx.x] = tot[threadIdx.x];
+    if (threadIdx.x < kWave) {               // wave 0 stores the tile row, then takes a ticket
+        if (threadIdx.x < 22) F.tile_rows[(size_t)b * kPartialWords + threadIdx.x] = tot[threadIdx.x];
         __threadfence();
         if (threadIdx.x == 0) {
-            const uint32_t prev = __hip_atomic_fetch_add(ticket + g, 1u, __ATOMIC_ACQ_REL,
+            const uint32_t prev = __hip_atomic_fetch_add(F.tickets + g, 1u, __ATOMIC_ACQ_REL,
                                                          __HIP_MEMORY_SCOPE_AGENT);
             stage = prev == (uint32_t)(in_group - 1) ? 1 : 0;
         }
@@ -389,13 +399,13 @@ __device__ inline void grid_finish(const Acc &a, float *partials, uint32_t *tick
     __syncthreads();
     if (stage == 0) return;
     __threadfence();
-    merge_partials(partials + (size_t)g * kPartialWords, kGroups * kPartialWords, in_group, tot);
+    merge_partials(F.tile_rows + (size_t)g * kPartialWords, kGroups * kPartialWords, in_group, tot);
     __syncthreads();
     if (threadIdx.x < kWave) {
-        if (threadIdx.x < 22) grow[(size_t)g * kPartialWords + threadIdx.x] = tot[threadIdx.x];
+        if (threadIdx.x < 22) F.group_rows[(size_t)g * kPartialWords + threadIdx.x] = tot[threadIdx.x];
         __threadfence();
         if (threadIdx.x == 0) {
-            const uint32_t prev = __hip_atomic_fetch_add(ticket + kGroups, 1u, __ATOMIC_ACQ_REL,
+            const uint32_t prev = __hip_atomic_fetch_add(F.tickets + kGroups, 1u, __ATOMIC_ACQ_REL,
                                                          __HIP_MEMORY_SCOPE_AGENT);
             stage = prev == (uint32_t)(ngroups - 1) ? 2 : 0;
         }
@@ -403,16 +413,24 @@ __device__ inline void grid_finish(const Acc &a, float *partials, uint32_t *tick
     __syncthreads();
     if (stage != 2) return;
     __threadfence();
-    merge_partials(grow, kPartialWords, ngroups, tot);
+    merge_partials(F.group_rows, kPartialWords, ngroups, tot);
     __syncthreads();
     if (threadIdx.x == 0) {
         Acc t;
         acc_from_partial(tot, t);
         for (int k = 0; k <= kGroups; ++k)
-            __hip_atomic_store(ticket + k, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        finalize_result(t, rank_tol, n_rays, extra_flags, out);
-        // publish: the result is visible to the host before the sequence number
-        __hip_atomic_store(done, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(F.tickets + k, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        finalize_result(t, rank_tol, n_rays, extra_flags, F.out);
+        bool publish = true;
+        if (F.finished) {
+            // system scope: every query's result reaches the host before the publication
+            const uint32_t prev = __hip_atomic_fetch_add(F.finished, 1u, __ATOMIC_ACQ_REL,
+                                                         __HIP_MEMORY_SCOPE_SYSTEM);
+            publish = prev == (uint32_t)(F.n_queries - 1);
+            if (publish) __hip_atomic_store(F.finished, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        // publish: the results are visible to the host before the sequence number
+        if (publish) __hip_atomic_store(F.done, F.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 

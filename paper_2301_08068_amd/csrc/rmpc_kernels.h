@@ -11,6 +11,12 @@ namespace rmpc {
 // Voxel visits planned ahead per lane and round of the traversal (4, 8 or 16).
 constexpr int kLookahead = 16;
 
+// Threads per block of the query kernels (one tile = this many lanes).
+constexpr int kBlockThreads = 256;
+
+// Reductions merge tile partials in this many groups (tiles t with t % 8 == g).
+constexpr int kGroups = 8;
+
 // Block-partial slots of one reduction (one per block of a launch).
 constexpr int kMaxPartialSlots = 4096;
 
@@ -36,7 +42,8 @@ struct RayArgs {
     MapView map;
     const float *dirs;           // direction table, structure of arrays: x[], y[], z[]
     int32_t dir_stride;          // elements between the x, y and z arrays
-    const int32_t *rays;         // the n_rays Halton indices to cast, in direction-coherent order
+    const int32_t *rays;         // ordered Halton indices; entries >= n_rays are skipped
+    int32_t n_list;              // length of `rays` (>= n_rays)
     int32_t n_rays;
     float g[3];                  // start in grid units, float32((x - origin) / h)
     int32_t v0[3];               // start voxel floor(g)
@@ -79,6 +86,40 @@ struct ScanArgs {
     uint64_t seq;
 };
 
+// One query of a batched launch.
+struct BatchQuery {
+    int32_t kind;                // 0: map query (ray), 1: scan query (scan)
+    int32_t tile_begin;          // first tile of this query in the batch
+    int32_t n_tiles;             // 256-lane tiles of this query
+    int32_t pad;
+    union {
+        RayArgs ray;
+        ScanArgs scan;
+    };
+};
+
+// Per-launch header of a batch, in device memory (so a captured launch can be replayed).
+struct BatchHeader {
+    int32_t n_queries;
+    int32_t n_tiles;
+    uint64_t seq;
+};
+
+// Launch arguments of the persistent batch kernel (pointers only).
+struct BatchArgs {
+    const BatchHeader *hdr;
+    const BatchQuery *q;
+    uint32_t *work;              // [0] next tile, [1] blocks exited, [2] queries finished
+    uint32_t *tickets;           // kGroups + 1 per query
+    float *partials;             // tile rows of all queries, then kGroups group rows per query
+    int32_t group_row_base;      // row index of the first group row
+    rmpc_result *results;        // one per query (pinned host memory)
+    uint64_t *done;              // completion word, set to hdr->seq when all queries are done
+};
+
+constexpr int kBatchMaxQueries = 4096;
+constexpr int kBatchMaxTiles = 262144;
+
 struct DirsArgs {
     float *out;                  // structure of arrays with stride n
     int32_t n;
@@ -111,5 +152,9 @@ hipError_t launch_scan(const ScanArgs &a, hipStream_t s, hipEvent_t ev0 = nullpt
 hipError_t launch_directions(const DirsArgs &a, hipStream_t s);
 hipError_t launch_layout(const LayoutArgs &a, hipStream_t s);
 hipError_t launch_compact(const CompactArgs &a, hipStream_t s);
+// Persistent fused batch: `blocks` resident blocks pull tiles from a counter.
+hipError_t launch_batch(const BatchArgs &a, int blocks, int lookahead, hipStream_t s);
+// Resident blocks per CU of the batch kernel for a lookahead.
+int batch_blocks_per_cu(int lookahead);
 
 }  // namespace rmpc

@@ -1,0 +1,189 @@
+"""GPU tests of the batched path: many map and scan queries of uneven size in one persistent
+launch give each query the result it gets alone (bitwise when the ray segmentation matches,
+else within 1e-4), match the oracle, replay correctly from a captured graph, split oversize
+batches, reject invalid queries and cache tuned configurations."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from paper_2301_08068_amd import workloads as W  # noqa: E402
+from gpu_common import compare_query  # noqa: E402
+
+P_TINY = W.params("static", max_range=5.0)
+P_PAPER = W.params("static", max_range=10.0)
+L = W.params("lidar")
+
+
+@pytest.fixture(scope="module")
+def env(tiny_map, paper_map):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2301_08068_amd import binding as B
+    ctx = B.Context(0, arena_bytes=1 << 30)
+    maps = {
+        "tiny": ctx.upload(tiny_map.tsdf, tiny_map.voxel_m, tiny_map.origin_m, "f32"),
+        "f32": ctx.upload(paper_map.tsdf, paper_map.voxel_m, paper_map.origin_m, "f32"),
+        "f16": ctx.upload(W.encode_f16(paper_map.tsdf), paper_map.voxel_m, paper_map.origin_m, "f16"),
+        "u8": ctx.upload(W.encode_u8(paper_map.tsdf), paper_map.voxel_m, paper_map.origin_m, "u8"),
+    }
+    yield ctx, maps
+    ctx.close()
+
+
+def _mixed_queries(tiny_map, paper_map, maps, n_map=24, n_scan=4, seed=7):
+    rng = np.random.default_rng(seed)
+    qs = []
+    counts = W.ray_counts(n_map, seed=399, lo=16, hi=65536)
+    for k in range(n_map):
+        key = ["f32", "f16", "u8"][k % 3]
+        x, v = W.free_state(paper_map, 200 + k)
+        qs.append(dict(kind="map", map_id=maps[key], n=int(counts[k]), x=x, v=v, P=P_PAPER))
+    for k in range(6):
+        x, v = W.free_state(tiny_map, 100 + k)
+        qs.append(dict(kind="map", map_id=maps["tiny"], n=int(rng.integers(1, 4096)), x=x, v=v, P=P_TINY))
+    for k in range(n_scan):
+        x, v = W.free_state(paper_map, 600 + k)
+        pts = W.synth_scan(paper_map, x, 600 + k, n_elev=32, n_azim=512)
+        qs.append(dict(kind="scan", points=torch.from_numpy(pts).cuda(), v=v))
+    order = rng.permutation(len(qs))
+    return [qs[i] for i in order]
+
+
+def _alone(ctx, q):
+    if q["kind"] == "map":
+        return ctx.query(q["map_id"], q["x"], q["v"], q["n"], q["P"])
+    return ctx.scan_query(q["points"], q["v"], L)
+
+
+def _strip(q):
+    return {k: v for k, v in q.items() if k != "P"}
+
+
+def test_batch_equals_alone_bitwise(env, tiny_map, paper_map):
+    from paper_2301_08068_amd import binding as B
+    ctx, maps = env
+    qcfg = ctx.config(B.CONFIG_QUERY)
+    ctx.config(B.CONFIG_BATCH, lane_target_log2=qcfg["lane_target_log2"], use_graph=0)
+    qs = _mixed_queries(tiny_map, paper_map, maps)
+    mixed = [q for q in qs if q["kind"] == "map" and q["P"] is P_PAPER]
+    res = ctx.query_batch([_strip(q) for q in mixed], map_params=P_PAPER)
+    for q, r in zip(mixed, res):
+        a = _alone(ctx, q)
+        for k in ("S", "b", "f", "lam"):
+            assert np.array_equal(r[k], a[k]), (k, q["n"])
+        for k in ("rank", "n_hit", "n_contrib", "n_tie", "flags", "visits", "n_rays"):
+            assert r[k] == a[k], k
+    scans = [q for q in qs if q["kind"] == "scan"]
+    res = ctx.query_batch(scans, scan_params=L)
+    for q, r in zip(scans, res):
+        a = _alone(ctx, q)
+        assert np.array_equal(r["S"], a["S"]) and np.array_equal(r["f"], a["f"])
+
+
+def test_mixed_batch_matches_oracle_and_alone(env, tiny_map, paper_map):
+    from paper_2301_08068_amd import binding as B
+    ctx, maps = env
+    ctx.config(B.CONFIG_BATCH, lane_target_log2=14, use_graph=0)       # other segmentation
+    qs = _mixed_queries(tiny_map, paper_map, maps, seed=11)
+    # one launch for map and scan queries together (paper-map parameter set)
+    sel = [q for q in qs if q["kind"] == "scan" or q["P"] is P_PAPER]
+    res = ctx.query_batch([_strip(q) for q in sel], map_params=P_PAPER, scan_params=L)
+    enc_map = {maps["f32"]: ("f32", paper_map.tsdf), maps["f16"]: ("f16", W.encode_f16(paper_map.tsdf)),
+               maps["u8"]: ("u8", W.encode_u8(paper_map.tsdf))}
+    oms = {mid: oracle.OracleMap(d, paper_map.voxel_m, paper_map.origin_m, e) for mid, (e, d) in enc_map.items()}
+    for q, r in zip(sel, res):
+        a = _alone(ctx, q)
+        compare_query(r, a, "batch vs alone")
+        if q["kind"] == "map":
+            o = oracle.query(oms[q["map_id"]], q["x"], q["v"], q["n"], P_PAPER, nthreads=8)
+        else:
+            o = oracle.scan(q["points"].cpu().numpy(), q["v"], L)
+        compare_query(r, o, "batch vs oracle")
+
+
+def test_graph_replays_match_eager(env, tiny_map, paper_map):
+    from paper_2301_08068_amd import binding as B
+    ctx, maps = env
+    qs = [_strip(q) for q in _mixed_queries(tiny_map, paper_map, maps, seed=3) if q["kind"] == "map"
+          and q["P"] is P_PAPER][:16]
+    ctx.config(B.CONFIG_BATCH, lane_target_log2=15, use_graph=0)
+    eager = ctx.query_batch(qs, map_params=P_PAPER)
+    ctx.config(B.CONFIG_BATCH, use_graph=1)
+    try:
+        for rep in range(4):
+            # eager work and synchronisation between replays
+            x, v = W.free_state(tiny_map, 100 + rep)
+            ctx.query(maps["tiny"], x, v, 1024, P_TINY)
+            torch.cuda.synchronize()
+            got = ctx.query_batch(qs, map_params=P_PAPER)
+            for g, e in zip(got, eager):
+                assert np.array_equal(g["S"], e["S"]) and np.array_equal(g["f"], e["f"]), rep
+                assert g["visits"] == e["visits"]
+        # a different batch through the same captured launch
+        other = qs[::-1][:9]
+        got = ctx.query_batch(other, map_params=P_PAPER)
+        eager_other = [e for e in reversed(eager)][:9]
+        for g, e in zip(got, eager_other):
+            assert np.array_equal(g["S"], e["S"])
+    finally:
+        ctx.config(B.CONFIG_BATCH, use_graph=0)
+
+
+def test_oversize_batch_is_split(env, paper_map):
+    from paper_2301_08068_amd import binding as B
+    ctx, maps = env
+    # 65536 rays at 2^18 lanes -> 4 segments -> 1024 tiles per query; 300 queries exceed one launch
+    ctx.config(B.CONFIG_BATCH, lane_target_log2=18, use_graph=0)
+    xs = [W.free_state(paper_map, 900 + k) for k in range(6)]
+    qs = [dict(kind="map", map_id=maps["u8"], n=65536, x=xs[k % 6][0], v=xs[k % 6][1]) for k in range(300)]
+    res = ctx.query_batch(qs, map_params=P_PAPER)
+    ctx.config(B.CONFIG_QUERY, lane_target_log2=18)
+    try:
+        for k in range(6):
+            a = ctx.query(maps["u8"], xs[k][0], xs[k][1], 65536, P_PAPER)
+            for r in res[k::6]:
+                assert np.array_equal(r["S"], a["S"]) and np.array_equal(r["f"], a["f"])
+    finally:
+        ctx.config(B.CONFIG_QUERY, lane_target_log2=17)
+
+
+def test_invalid_query_fails_whole_batch(env, paper_map):
+    from paper_2301_08068_amd import binding as B
+    ctx, maps = env
+    x, v = W.free_state(paper_map, 5)
+    good = dict(kind="map", map_id=maps["f32"], n=1024, x=x, v=v)
+    for bad, status in ((dict(good, n=0), B.RMPC_E_INVALID), (dict(good, x=[-1.0, 1, 1]), B.RMPC_E_OUT_OF_BOUNDS),
+                        (dict(good, map_id=999), B.RMPC_E_NOMAP), (dict(good, v=[np.nan, 0, 0]), B.RMPC_E_INVALID)):
+        with pytest.raises(B.RmpcError) as e:
+            ctx.query_batch([good, good, bad, good], map_params=P_PAPER)
+        assert e.value.status == status and "query 2" in str(e.value)
+    with pytest.raises(B.RmpcError):
+        ctx.query_batch([dict(kind="scan", n=10, v=v, points_ptr=0)], scan_params=L)
+
+
+def test_tuner_picks_and_caches(env, paper_map, tmp_path):
+    from paper_2301_08068_amd import binding as B
+    ctx, maps = env
+    counts = W.ray_counts(32, seed=399)
+    qs = []
+    for k in range(32):
+        x, v = W.free_state(paper_map, 300 + k)
+        qs.append(dict(kind="map", map_id=maps["f32"], n=int(counts[k]), x=x, v=v))
+    descs = B.query_descs(qs)
+    path = str(tmp_path / "tune.json")
+    best = B.rmpc_tune_batch(ctx.ptr, descs, P_PAPER, None, cache_path=path)
+    assert best["lookahead"] in (4, 8, 16) and 10 <= best["lane_target_log2"] <= 22
+    cached = json.load(open(path))
+    assert len(cached) == 1 and list(cached.values())[0][:2] == [best["lookahead"], best["lane_target_log2"]]
+    again = B.rmpc_tune_batch(ctx.ptr, descs, P_PAPER, None, cache_path=path)
+    assert again == best
+    res = ctx.query_batch(qs, map_params=P_PAPER)
+    o = oracle.query(oracle.OracleMap.from_voxelmap(paper_map), qs[0]["x"], qs[0]["v"], qs[0]["n"], P_PAPER,
+                     nthreads=8)
+    compare_query(res[0], o, "tuned batch")
