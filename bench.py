@@ -140,12 +140,174 @@ def batch_bench(args):
     print(json.dumps(out), flush=True)
 
 
+SERVE_RATES = (2000, 5000, 10000, 20000)
+
+
+def _serve_rate(binding, ctx, reqs, n_units, is_grid, arrivals, server_kw, warm):
+    """One open-loop Poisson run: submit each request at its arrival time, collect results as
+    they complete, return per-request latency from scheduled arrival (s) and counters."""
+    import numpy as np
+    binding.rmpc_server_start(ctx.ptr, **server_kw)
+    try:
+        for r in warm:                                  # warm-up (not timed)
+            binding.rmpc_submit(ctx.ptr, r)
+        got = 0
+        while got < len(warm):
+            got += binding.rmpc_poll_completed(ctx.ptr, 512, raw=True)[3]
+        base = binding.rmpc_server_stats(ctx.ptr)
+        n = len(reqs)
+        idx_of = {}
+        sub = np.zeros(n)
+        lat = np.full(n, np.nan)
+        done_t = 0.0
+        i = done = 0
+        t0 = time.perf_counter()
+        last_progress = t0
+        while done < n:
+            now = time.perf_counter() - t0
+            while i < n and arrivals[i] <= now:
+                idx_of[binding.rmpc_submit(ctx.ptr, reqs[i])] = i
+                sub[i] = time.perf_counter() - t0
+                i += 1
+            tks, lats, _, k = binding.rmpc_poll_completed(ctx.ptr, 1024, raw=True)
+            if k:
+                tnow = time.perf_counter()
+                done_t = tnow - t0
+                last_progress = tnow
+                for t, l in zip(tks, lats):
+                    j = idx_of.pop(t)
+                    lat[j] = (sub[j] - arrivals[j]) + l     # arrival -> result on the host
+                done += k
+            elif time.perf_counter() - last_progress > 60.0:
+                raise RuntimeError("serving run made no progress for 60 s")
+        st = binding.rmpc_server_stats(ctx.ptr)
+    finally:
+        binding.rmpc_server_stop(ctx.ptr)
+    units = float(np.sum(n_units))
+    lag = sub - arrivals[:n]
+    return {
+        "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
+        "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3),
+        "p50_grid_ms": round(1e3 * float(np.percentile(lat[is_grid], 50)), 3),
+        "p99_grid_ms": round(1e3 * float(np.percentile(lat[is_grid], 99)), 3),
+        "p50_scan_ms": round(1e3 * float(np.percentile(lat[~is_grid], 50)), 3),
+        "p99_scan_ms": round(1e3 * float(np.percentile(lat[~is_grid], 99)), 3),
+        "evals_per_s": units / done_t,
+        "offered_evals_per_s": units / float(arrivals[n - 1]),
+        "launches": st["launches"] - base["launches"],
+        "mean_batch": round(n / max(1, st["launches"] - base["launches"]), 2),
+        "batch_max": st["batch_max"],
+        "staging_waits": st["staging_waits"] - base["staging_waits"],
+        "refused": st["refused"] - base["refused"],
+        "staging_peak_bytes": st["staging_peak"],
+        "submit_lag_p99_ms": round(1e3 * float(np.percentile(lag, 99)), 3),
+        "wall_s": round(done_t, 3),
+    }
+
+
+def serve_bench(args):
+    """Serving: an open-loop Poisson stream of half grid-raycast requests (ray counts
+    log-uniform in [4096, 65536]) and half 64 x 1024 LiDAR-scan requests (points staged from
+    pinned host memory) over four resident maps (two 400^3 fp16 TSDF, two 256^3 u8
+    occupancy), continuous batching over several launch slots against a one-request-per-launch
+    server on the same stream."""
+    import numpy as np
+    import torch
+    from paper_2301_08068_amd import binding
+    from paper_2301_08068_amd import workloads as W
+    vms = [("f16", W.paper_map(10)), ("f16", W.paper_map(11)), ("u8", W.occ_source_map(12)),
+           ("u8", W.occ_source_map(13))]
+    ctx = binding.Context(0, arena_bytes=2 << 30)
+    mids, resident = [], 0
+    for enc, vm in vms:
+        data = W.encode_f16(vm.tsdf) if enc == "f16" else W.encode_u8(vm.tsdf)
+        resident += data.nbytes
+        mids.append(ctx.upload(data, vm.voxel_m, vm.origin_m, enc))
+    n_states, n_scans = 64, 2
+    states = [[W.free_state(vm, 1000 * m + k) for k in range(n_states)] for m, (_, vm) in enumerate(vms)]
+    scans = [[torch.from_numpy(W.synth_scan(vm, states[m][k][0], 600 + 10 * m + k)).pin_memory()
+              for k in range(n_scans)] for m, (_, vm) in enumerate(vms)]
+    mp, sp = W.params("static", max_range=10.0), W.params("lidar")
+    n = args.serve_requests
+    rng = np.random.default_rng(501)
+    is_grid = rng.uniform(size=n) < 0.5
+    m_idx = rng.integers(0, len(vms), size=n)
+    s_idx = rng.integers(0, n_states, size=n)
+    c_idx = rng.integers(0, n_scans, size=n)
+    counts = W.ray_counts(n, seed=399)
+    reqs, units = [], np.zeros(n)
+    for j in range(n):
+        m, (x, v) = int(m_idx[j]), states[int(m_idx[j])][int(s_idx[j])]
+        if is_grid[j]:
+            q = dict(kind="map", map_id=mids[m], n=int(counts[j]), x=x, v=v)
+            reqs.append(binding.request(q))
+            units[j] = counts[j]
+        else:
+            pts = scans[m][int(c_idx[j])]
+            reqs.append(binding.request(dict(kind="scan", n=pts.shape[0], v=states[m][int(c_idx[j])][1]),
+                                        pts.data_ptr()))
+            units[j] = pts.shape[0]
+    launch = ctx.config(binding.CONFIG_BATCH)
+    scan_bytes = 12 * 65536
+    modes = {
+        "continuous": dict(n_slots=args.serve_slots, max_batch=256, map_params=mp, scan_params=sp,
+                           launch=launch, staging_bytes=64 * scan_bytes),
+        "one_per_launch": dict(n_slots=1, max_batch=1, map_params=mp, scan_params=sp, launch=launch,
+                               staging_bytes=2 * scan_bytes),
+    }
+    # equality with the alone result on a sample of the mix
+    sample = list(range(0, n, max(1, n // 48)))[:48]
+    rows = []
+    for rate in SERVE_RATES:
+        arrivals = W.poisson_arrivals(rate, n, seed=500)
+        row = {"rate_req_s": rate}
+        for name, kw in modes.items():
+            row[name] = _serve_rate(binding, ctx, reqs, units, is_grid, arrivals, kw, reqs[:64])
+            print(json.dumps({"progress": f"rate {rate} {name}", **row[name]}), file=sys.stderr, flush=True)
+        rows.append(row)
+    binding.rmpc_server_start(ctx.ptr, **modes["continuous"])
+    try:
+        tks = [binding.rmpc_submit(ctx.ptr, reqs[j]) for j in sample]
+        got = {}
+        while len(got) < len(tks):
+            for t, r, _ in binding.rmpc_poll_completed(ctx.ptr, 64):
+                got[t] = r
+    finally:
+        binding.rmpc_server_stop(ctx.ptr)
+    equal = 0
+    for t, j in zip(tks, sample):
+        q = reqs[j].q
+        if q.kind == binding.KIND_MAP:
+            alone = ctx.query_batch([dict(kind="map", map_id=q.map_id, n=q.n, x=list(q.x), v=list(q.v))],
+                                    map_params=mp)[0]
+        else:
+            m = int(m_idx[j])
+            alone = ctx.query_batch([dict(kind="scan", points=scans[m][int(c_idx[j])].cuda(), v=list(q.v))],
+                                    scan_params=sp)[0]
+        equal += int(np.array_equal(got[t]["f"], alone["f"]) and np.array_equal(got[t]["S"], alone["S"]))
+    top = rows[-1]["continuous"]
+    out = {"metric": METRIC, "value": top["evals_per_s"], "unit": "ray-policy evaluations/s (grid rays + scan points)",
+           "n_gpus": 1, "steps": n, "warmup": 64, "ms_per_step": None, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f16/u8 maps, f32 sums, f64 resolve",
+           "data": "synthetic",
+           "config": {"workload": f"Poisson arrivals at {list(SERVE_RATES)} req/s, {n} requests each; 50 % grid "
+                                  "queries (rays log-uniform in [4096, 65536]) and 50 % 64x1024 LiDAR scans "
+                                  "(pinned host points, staged by the server); 4 resident maps (two 400^3 fp16 "
+                                  "TSDF, two 256^3 u8 occupancy)",
+                      "resident_map_bytes": resident, "launch": launch, "slots": args.serve_slots,
+                      "rates": rows, "sample_equal_alone": f"{equal}/{len(sample)}"}}
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=30)
-    ap.add_argument("--config", default="paper", choices=sorted(CONFIGS) + ["batch"])
+    ap.add_argument("--config", default="paper", choices=sorted(CONFIGS) + ["batch", "serve"])
+    ap.add_argument("--serve-requests", type=int, default=20000)
+    ap.add_argument("--serve-slots", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -177,6 +339,9 @@ def main():
     from paper_2301_08068_amd import workloads as W
     if args.config == "batch":
         batch_bench(args)
+        return
+    if args.config == "serve":
+        serve_bench(args)
         return
 
     kind, enc, seed, n_rays, rmax = CONFIGS[args.config]

@@ -38,7 +38,7 @@ typedef enum {
     RMPC_E_OUT_OF_BOUNDS = -3,  /* query position outside the map's grid */
     RMPC_E_NOMEM = -4,          /* the caller's device arena has no room */
     RMPC_E_HIP = -5,            /* a HIP runtime call failed */
-    RMPC_E_STOPPED = -6         /* reserved for the serving loop */
+    RMPC_E_STOPPED = -6         /* no serving loop is running, or it stopped after an error */
 } rmpc_status;
 
 /* Voxel storage (reading: a voxel is occupied when its TSDF value at the centre is <= 0;
@@ -248,6 +248,94 @@ rmpc_status rmpc_set_profiling(rmpc_ctx *ctx, int enable);
 /* rmpc_get_profile -- total kernel time in milliseconds and number of timed launches since
  * profiling was last enabled.  Errors: RMPC_E_INVALID. */
 rmpc_status rmpc_get_profile(rmpc_ctx *ctx, double *kernel_ms, int64_t *launches);
+
+/*
+ * Serving loop.  A library thread owns a pool of launch slots, each with its own stream and
+ * batch buffers.  Requests submitted from any thread wait in one FIFO queue; whenever a slot
+ * is free, the thread takes requests from the front of the queue (up to the slot's query and
+ * tile capacity, and while their scan points fit the staging memory) into one persistent
+ * launch (the same kernel as rmpc_query_batch), so launches on different slots overlap on
+ * the device and new requests join the next launch while earlier ones run (continuous
+ * batching).  Each result is the one rmpc_query_batch gives for the request with the same
+ * launch configuration.  While the server runs, maps cannot be uploaded or released.
+ */
+typedef struct {
+    rmpc_query_desc q;          /* the query (rmpc_query_batch's descriptor) */
+    const float *points_host;   /* scan queries: q.n x 3 float32 in host memory, copied to the
+                                   device by the server (q.points_dev is then ignored); NULL to
+                                   use q.points_dev.  Either buffer must stay valid and
+                                   unchanged until the request is done, and device points must
+                                   be complete when rmpc_submit is called.  Pinned host memory
+                                   is copied asynchronously, pageable memory synchronously. */
+} rmpc_request;
+
+typedef struct {
+    int32_t n_slots;            /* launches in flight at once, each on its own stream: 1..8 */
+    int32_t max_batch;          /* requests per launch: 1..4096 */
+    int32_t max_tiles;          /* 256-lane tiles per launch (0 = 262144); a request needing
+                                   more is refused.  Each slot holds 128 B per tile. */
+    int32_t max_pending;        /* queued requests before rmpc_submit refuses (0 = 65536) */
+    size_t staging_bytes;       /* device memory for host scan points (0 = none) */
+    rmpc_params map_params;     /* policy of map requests */
+    rmpc_params scan_params;    /* policy of scan requests */
+    rmpc_launch_config launch;  /* as for batches */
+} rmpc_server_config;
+
+typedef struct {
+    uint64_t submitted;         /* requests accepted */
+    uint64_t completed;         /* requests with a result (polled or not) */
+    uint64_t launches;          /* kernel launches */
+    uint64_t pending;           /* requests queued now */
+    uint64_t in_flight;         /* requests in running launches now */
+    uint64_t refused;           /* submits refused because the queue was full */
+    uint64_t staging_waits;     /* launches closed early because staging memory was full */
+    uint64_t staging_peak;      /* most staging bytes in use at once */
+    uint64_t batch_max;         /* most requests in one launch */
+} rmpc_server_counters;
+
+/*
+ * rmpc_server_start -- start the serving loop on this context.  Slots, their buffers and the
+ * staging memory come from the arena.  Errors: RMPC_E_INVALID (bad config, already running),
+ * RMPC_E_NOMEM (arena too small), RMPC_E_HIP.
+ */
+rmpc_status rmpc_server_start(rmpc_ctx *ctx, const rmpc_server_config *cfg);
+
+/*
+ * rmpc_submit -- validate a request and queue it; never waits for the device.  Thread-safe.
+ *   ticket: receives the request's ticket (increasing in submission order).
+ * The latency clock of the request starts here.  Errors: as rmpc_query_batch for an invalid
+ * query (nothing is queued), RMPC_E_NOMEM (queue full, or scan points larger than the
+ * staging memory), RMPC_E_STOPPED (no server, or it failed; rmpc_last_error says why).
+ */
+rmpc_status rmpc_submit(rmpc_ctx *ctx, const rmpc_request *req, uint64_t *ticket);
+
+/*
+ * rmpc_poll -- non-blocking check of one request.  Thread-safe.
+ *   done: 1 if the result is ready (out and latency_s are then written and the ticket is
+ *     retired), else 0.
+ *   latency_s: optional, seconds from rmpc_submit to the server seeing the result in host
+ *     memory.
+ * Errors: RMPC_E_INVALID (unknown or retired ticket), RMPC_E_STOPPED.
+ */
+rmpc_status rmpc_poll(rmpc_ctx *ctx, uint64_t ticket, rmpc_result *out, int32_t *done, double *latency_s);
+
+/*
+ * rmpc_poll_completed -- collect up to max ready results in completion order (tickets,
+ * out, latency_s: arrays of max entries; latency_s may be NULL) and retire their tickets.
+ * Thread-safe.  Errors: RMPC_E_INVALID, RMPC_E_STOPPED.
+ */
+rmpc_status rmpc_poll_completed(rmpc_ctx *ctx, int32_t max, uint64_t *tickets, rmpc_result *out,
+                                double *latency_s, int32_t *n_out);
+
+/* rmpc_server_stats -- the server's counters.  Thread-safe.  Errors: RMPC_E_STOPPED. */
+rmpc_status rmpc_server_stats(rmpc_ctx *ctx, rmpc_server_counters *out);
+
+/*
+ * rmpc_server_stop -- finish every queued and running request, then stop the thread and
+ * return the slots and staging memory to the arena.  Results not yet polled are discarded.
+ * Errors: RMPC_E_STOPPED (not running); a failure of the loop is reported as RMPC_E_HIP.
+ */
+rmpc_status rmpc_server_stop(rmpc_ctx *ctx);
 
 /* rmpc_last_error -- text of the calling thread's last error ("" if none). */
 const char *rmpc_last_error(void);

@@ -56,6 +56,21 @@ KIND_MAP, KIND_SCAN = 0, 1
 CONFIG_QUERY, CONFIG_BATCH = 0, 1
 
 
+class Request(C.Structure):
+    _fields_ = [("q", QueryDesc), ("points_host", C.c_void_p)]
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("n_slots", C.c_int32), ("max_batch", C.c_int32), ("max_tiles", C.c_int32),
+                ("max_pending", C.c_int32), ("staging_bytes", C.c_size_t), ("map_params", Params),
+                ("scan_params", Params), ("launch", LaunchConfig)]
+
+
+class ServerCounters(C.Structure):
+    _fields_ = [(k, C.c_uint64) for k in ("submitted", "completed", "launches", "pending", "in_flight",
+                                          "refused", "staging_waits", "staging_peak", "batch_max")]
+
+
 class Result(C.Structure):
     _fields_ = [("f", C.c_double * 3), ("A", C.c_double * 9), ("b", C.c_double * 3),
                 ("lam", C.c_double * 3), ("rank", C.c_int32), ("n_hit", C.c_int32),
@@ -89,6 +104,13 @@ _SIGS = {
                         C.c_char_p, _P(LaunchConfig)],
     "rmpc_set_profiling": [C.c_void_p, C.c_int],
     "rmpc_get_profile": [C.c_void_p, _P(C.c_double), _P(C.c_int64)],
+    "rmpc_server_start": [C.c_void_p, _P(ServerConfig)],
+    "rmpc_submit": [C.c_void_p, _P(Request), _P(C.c_uint64)],
+    "rmpc_poll": [C.c_void_p, C.c_uint64, _P(Result), _P(C.c_int32), _P(C.c_double)],
+    "rmpc_poll_completed": [C.c_void_p, C.c_int32, _P(C.c_uint64), _P(Result), _P(C.c_double),
+                            _P(C.c_int32)],
+    "rmpc_server_stats": [C.c_void_p, _P(ServerCounters)],
+    "rmpc_server_stop": [C.c_void_p],
 }
 for _name, _args in _SIGS.items():
     getattr(_lib, _name).argtypes = _args
@@ -255,6 +277,64 @@ def rmpc_get_profile(ctx: int) -> Tuple[float, int]:
     n = C.c_int64(0)
     _check(_lib.rmpc_get_profile(C.c_void_p(ctx), C.byref(ms), C.byref(n)), "rmpc_get_profile")
     return ms.value, n.value
+
+
+def request(q: Dict, points_host_ptr: Optional[int] = None) -> Request:
+    """A serving request from a query dict (see query_descs); scan points either on the device
+    ("points_ptr") or in host memory (points_host_ptr, pinned for asynchronous copies)."""
+    r = Request()
+    r.q = query_descs([q])[0]
+    r.points_host = C.c_void_p(int(points_host_ptr) if points_host_ptr else None)
+    return r
+
+
+def rmpc_server_start(ctx: int, n_slots: int, max_batch: int, map_params: Dict[str, float],
+                      scan_params: Dict[str, float], launch: Dict[str, int], staging_bytes: int = 0,
+                      max_tiles: int = 0, max_pending: int = 0) -> None:
+    cfg = ServerConfig(int(n_slots), int(max_batch), int(max_tiles), int(max_pending), int(staging_bytes),
+                       params_struct(map_params), params_struct(scan_params),
+                       LaunchConfig(launch["lookahead"], launch["lane_target_log2"], launch["blocks_per_cu"],
+                                    launch["use_graph"]))
+    _check(_lib.rmpc_server_start(C.c_void_p(ctx), C.byref(cfg)), "rmpc_server_start")
+
+
+def rmpc_submit(ctx: int, req: Request) -> int:
+    t = C.c_uint64(0)
+    _check(_lib.rmpc_submit(C.c_void_p(ctx), C.byref(req), C.byref(t)), "rmpc_submit")
+    return t.value
+
+
+def rmpc_poll(ctx: int, ticket: int) -> Tuple[Optional[Dict], float]:
+    r = Result()
+    done = C.c_int32(0)
+    lat = C.c_double(0.0)
+    _check(_lib.rmpc_poll(C.c_void_p(ctx), C.c_uint64(ticket), C.byref(r), C.byref(done), C.byref(lat)),
+           "rmpc_poll")
+    return (result_dict(r), lat.value) if done.value else (None, 0.0)
+
+
+def rmpc_poll_completed(ctx: int, max_n: int = 256, raw: bool = False):
+    """Ready results in completion order: a list of (ticket, result dict, latency_s); with
+    raw=True the tuple (tickets, latencies, Result array, count) without conversion."""
+    tickets = (C.c_uint64 * max_n)()
+    out = (Result * max_n)()
+    lat = (C.c_double * max_n)()
+    n = C.c_int32(0)
+    _check(_lib.rmpc_poll_completed(C.c_void_p(ctx), int(max_n), tickets, out, lat, C.byref(n)),
+           "rmpc_poll_completed")
+    if raw:
+        return tickets[:n.value], lat[:n.value], out, n.value
+    return [(tickets[i], result_dict(out[i]), lat[i]) for i in range(n.value)]
+
+
+def rmpc_server_stats(ctx: int) -> Dict[str, int]:
+    c = ServerCounters()
+    _check(_lib.rmpc_server_stats(C.c_void_p(ctx), C.byref(c)), "rmpc_server_stats")
+    return {k: getattr(c, k) for k, _ in ServerCounters._fields_}
+
+
+def rmpc_server_stop(ctx: int) -> None:
+    _check(_lib.rmpc_server_stop(C.c_void_p(ctx)), "rmpc_server_stop")
 
 
 # ----------------------------------------------------------------------------- convenience

@@ -16,10 +16,12 @@
 #include <utility>
 #include <vector>
 
-#include "rmpcast.h"
-#include "rmpc_kernels.h"
+#include "rmpc_host.h"
 
-namespace {
+namespace rmpc_host {
+
+constexpr size_t kMinArena = 2u << 20;
+constexpr int kMaxDim = 4096;
 
 thread_local std::string g_last_error;
 
@@ -29,122 +31,17 @@ rmpc_status fail(rmpc_status st, const std::string &msg)
     return st;
 }
 
-#define RMPC_HIP(call)                                                                    \
-    do {                                                                                  \
-        hipError_t e_ = (call);                                                           \
-        if (e_ != hipSuccess)                                                             \
-            return fail(RMPC_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_));   \
-    } while (0)
+DeviceGuard::DeviceGuard(int dev)
+{
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+}
 
-constexpr size_t kAlign = 256;
-constexpr size_t kMinArena = 2u << 20;
-constexpr int kMaxDim = 4096;
-
-// First-fit sub-allocator over the caller's arena (offsets only; never touches memory).
-class Arena {
-  public:
-    void init(size_t bytes) { free_.clear(); free_[0] = bytes; }
-    bool alloc(size_t bytes, size_t *off)
-    {
-        bytes = (bytes + kAlign - 1) / kAlign * kAlign;
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= bytes) {
-                *off = it->first;
-                const size_t rest = it->second - bytes;
-                const size_t noff = it->first + bytes;
-                free_.erase(it);
-                if (rest) free_[noff] = rest;
-                used_[*off] = bytes;
-                return true;
-            }
-        }
-        return false;
-    }
-    void release(size_t off)
-    {
-        auto u = used_.find(off);
-        if (u == used_.end()) return;
-        size_t start = off, len = u->second;
-        used_.erase(u);
-        auto nx = free_.lower_bound(start);
-        if (nx != free_.end() && start + len == nx->first) { len += nx->second; nx = free_.erase(nx); }
-        if (nx != free_.begin()) {
-            auto pv = std::prev(nx);
-            if (pv->first + pv->second == start) { start = pv->first; len += pv->second; free_.erase(pv); }
-        }
-        free_[start] = len;
-    }
-
-  private:
-    std::map<size_t, size_t> free_, used_;
-};
-
-struct MapEntry {
-    rmpc_map_desc desc;
-    rmpc::MapView view;
-    size_t off;
-};
-
-}  // namespace
-
-struct rmpc_ctx {
-    int device;
-    uint8_t *arena;
-    size_t arena_bytes;
-    Arena alloc;
-    float *dirs;            // structure of arrays, RMPC_MAX_RAYS per component
-    int32_t *order;         // all Halton indices in direction-coherent (Hilbert) order
-    int32_t *counts;        // compaction scratch
-    // ordered ray lists for a ladder of list sizes (all built at creation): a query with N
-    // rays walks the list of the smallest size >= N and skips entries >= N
-    std::vector<int32_t> ladder;            // ascending sizes, last = RMPC_MAX_RAYS
-    std::vector<const int32_t *> ladder_lists;
-    float *partials;
-    uint32_t *ticket;
-    rmpc_result *result_host;   // pinned, written by the kernels
-    uint64_t *done_host;        // pinned completion word (sequence number of the last result)
-    uint64_t seq;
-    std::map<int32_t, MapEntry> maps;
-    int32_t next_map_id;
-    rmpc_launch_config cfg[2];  // RMPC_CONFIG_QUERY, RMPC_CONFIG_BATCH
-    // batch state (allocated on first use)
-    bool batch_ready;
-    rmpc::BatchHeader *b_hdr;
-    rmpc::BatchQuery *b_q;
-    uint32_t *b_work;
-    uint32_t *b_tickets;
-    float *b_partials;
-    rmpc_result *b_results_host;
-    rmpc::BatchHeader *b_hdr_host;
-    rmpc::BatchQuery *b_q_host;
-    hipStream_t own_stream;
-    hipEvent_t ev_dep;
-    hipGraphExec_t graph_exec;
-    int graph_blocks, graph_lookahead;
-    int cu_count;
-    // kernel timing (rmpc_set_profiling)
-    bool profiling;
-    hipEvent_t ev0, ev1;
-    double prof_ms;
-    int64_t prof_n;
-};
-
-namespace {
-
-// Runs a call with the context's device current, restoring the caller's afterwards.
-struct DeviceGuard {
-    int prev = -1;
-    explicit DeviceGuard(int dev)
-    {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) (void)hipSetDevice(dev);
-    }
-    ~DeviceGuard()
-    {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-    }
-};
+DeviceGuard::~DeviceGuard()
+{
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+}
 
 bool finite3(const double *p) { return p && std::isfinite(p[0]) && std::isfinite(p[1]) && std::isfinite(p[2]); }
 
@@ -177,13 +74,6 @@ rmpc::PolicyF policy_f(const rmpc_params *p, const double v[3])
     P.inv_radius = (float)(1.0 / p->radius);
     P.eps = (float)p->eps;
     return P;
-}
-
-int ilog2(int v)
-{
-    int l = 0;
-    while ((1 << l) < v) ++l;
-    return l;
 }
 
 // Brick edge (log2) per axis for a storage type: about 128-256 bytes per brick.
@@ -278,8 +168,7 @@ int segments_for(int32_t n_rays, double span, int lane_target_log2)
 
 // Validates the query state and fills the geometry part of RayArgs.
 rmpc_status setup_query(rmpc_ctx *ctx, int32_t map_id, const double x[3], int32_t n_rays,
-                        const rmpc_params *params, const rmpc_launch_config &cfg, rmpc::RayArgs &A,
-                        const MapEntry **me_out)
+                        const rmpc_params *params, const rmpc_launch_config &cfg, rmpc::RayArgs &A)
 {
     if (!ctx) return fail(RMPC_E_INVALID, "ctx is NULL");
     if (!finite3(x)) return fail(RMPC_E_INVALID, "position is NULL or not finite");
@@ -324,24 +213,23 @@ rmpc_status setup_query(rmpc_ctx *ctx, int32_t map_id, const double x[3], int32_
     A.result = ctx->result_host;
     A.done = ctx->done_host;
     A.seq = 0;
-    *me_out = &me;
     return RMPC_OK;
 }
 
 // Wait for a query's result: spin on the completion word the kernel sets after writing the
 // result (a few microseconds sooner than a stream synchronisation), checking the stream for
 // errors now and then.
-rmpc_status wait_result(rmpc_ctx *ctx, hipStream_t s, uint64_t seq)
+rmpc_status wait_done(const uint64_t *done, hipStream_t s, uint64_t seq)
 {
     const auto t0 = std::chrono::steady_clock::now();
     for (uint64_t it = 1;; ++it) {
-        if (__atomic_load_n(ctx->done_host, __ATOMIC_ACQUIRE) == seq) return RMPC_OK;
+        if (__atomic_load_n(done, __ATOMIC_ACQUIRE) == seq) return RMPC_OK;
         if ((it & 1023) == 0) {
             if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(60))
                 return fail(RMPC_E_HIP, "query kernel did not finish within 60 s");
             const hipError_t e = hipStreamQuery(s);
             if (e == hipSuccess) {
-                if (__atomic_load_n(ctx->done_host, __ATOMIC_ACQUIRE) == seq) return RMPC_OK;
+                if (__atomic_load_n(done, __ATOMIC_ACQUIRE) == seq) return RMPC_OK;
                 return fail(RMPC_E_HIP, "kernel finished without publishing its result");
             }
             if (e != hipErrorNotReady) return fail(RMPC_E_HIP, std::string("query kernel: ") + hipGetErrorString(e));
@@ -362,258 +250,9 @@ rmpc_status account_profile(rmpc_ctx *ctx)
 }
 
 
-// ---------------------------------------------------------------------------------------
-// batches
-// ---------------------------------------------------------------------------------------
+}  // namespace rmpc_host
 
-rmpc_status check_config(const rmpc_launch_config *c)
-{
-    if (!c) return fail(RMPC_E_INVALID, "config is NULL");
-    if (c->lookahead != 4 && c->lookahead != 8 && c->lookahead != 16)
-        return fail(RMPC_E_INVALID, "lookahead must be 4, 8 or 16");
-    if (c->lane_target_log2 < 10 || c->lane_target_log2 > 22)
-        return fail(RMPC_E_INVALID, "lane_target_log2 out of [10, 22]");
-    if (c->blocks_per_cu < 0 || c->blocks_per_cu > 64) return fail(RMPC_E_INVALID, "blocks_per_cu out of [0, 64]");
-    if (c->use_graph != 0 && c->use_graph != 1) return fail(RMPC_E_INVALID, "use_graph must be 0 or 1");
-    return RMPC_OK;
-}
-
-// Device and pinned buffers of the batch path, allocated on first use.
-rmpc_status batch_prepare(rmpc_ctx *ctx)
-{
-    if (ctx->batch_ready) return RMPC_OK;
-    const size_t rows = (size_t)rmpc::kBatchMaxTiles + (size_t)rmpc::kGroups * rmpc::kBatchMaxQueries;
-    size_t o_hdr, o_q, o_work, o_tk, o_part;
-    if (!ctx->alloc.alloc(sizeof(rmpc::BatchHeader), &o_hdr) ||
-        !ctx->alloc.alloc(sizeof(rmpc::BatchQuery) * rmpc::kBatchMaxQueries, &o_q) ||
-        !ctx->alloc.alloc(256, &o_work) ||
-        !ctx->alloc.alloc(sizeof(uint32_t) * (rmpc::kGroups + 1) * rmpc::kBatchMaxQueries, &o_tk) ||
-        !ctx->alloc.alloc(sizeof(float) * 32 * rows, &o_part))
-        return fail(RMPC_E_NOMEM, "arena too small for the batch buffers");
-    ctx->b_hdr = reinterpret_cast<rmpc::BatchHeader *>(ctx->arena + o_hdr);
-    ctx->b_q = reinterpret_cast<rmpc::BatchQuery *>(ctx->arena + o_q);
-    ctx->b_work = reinterpret_cast<uint32_t *>(ctx->arena + o_work);
-    ctx->b_tickets = reinterpret_cast<uint32_t *>(ctx->arena + o_tk);
-    ctx->b_partials = reinterpret_cast<float *>(ctx->arena + o_part);
-    RMPC_HIP(hipMemset(ctx->b_work, 0, 256));
-    RMPC_HIP(hipMemset(ctx->b_tickets, 0, sizeof(uint32_t) * (rmpc::kGroups + 1) * rmpc::kBatchMaxQueries));
-    RMPC_HIP(hipHostMalloc(reinterpret_cast<void **>(&ctx->b_results_host),
-                           sizeof(rmpc_result) * rmpc::kBatchMaxQueries, hipHostMallocCoherent));
-    RMPC_HIP(hipHostMalloc(reinterpret_cast<void **>(&ctx->b_hdr_host), sizeof(rmpc::BatchHeader), 0));
-    RMPC_HIP(hipHostMalloc(reinterpret_cast<void **>(&ctx->b_q_host),
-                           sizeof(rmpc::BatchQuery) * rmpc::kBatchMaxQueries, 0));
-    RMPC_HIP(hipStreamCreateWithFlags(&ctx->own_stream, hipStreamNonBlocking));
-    RMPC_HIP(hipEventCreateWithFlags(&ctx->ev_dep, hipEventDisableTiming));
-    RMPC_HIP(hipDeviceGetAttribute(&ctx->cu_count, hipDeviceAttributeMultiprocessorCount, ctx->device));
-    ctx->batch_ready = true;
-    return RMPC_OK;
-}
-
-// Validate query k of a batch and fill its device descriptor (tiles not yet placed).
-rmpc_status batch_describe(rmpc_ctx *ctx, const rmpc_query_desc &d, int k, const rmpc_params *mp,
-                           const rmpc_params *sp, const rmpc_launch_config &cfg, rmpc::BatchQuery &Q)
-{
-    std::memset(&Q, 0, sizeof Q);
-    if (d.kind == RMPC_KIND_MAP) {
-        if (!finite3(d.v)) return fail(RMPC_E_INVALID, "query " + std::to_string(k) + ": velocity not finite");
-        const MapEntry *me = nullptr;
-        if (rmpc_status st = setup_query(ctx, d.map_id, d.x, d.n, mp, cfg, Q.ray, &me)) {
-            g_last_error = "query " + std::to_string(k) + ": " + g_last_error;
-            return st;
-        }
-        Q.kind = 0;
-        Q.ray.pol = policy_f(mp, d.v);
-        for (int a = 0; a < 3; ++a) Q.ray.vel64[a] = d.v[a];
-        Q.n_tiles = (Q.ray.n_list * Q.ray.segments + rmpc::kBlockThreads - 1) / rmpc::kBlockThreads;
-    } else if (d.kind == RMPC_KIND_SCAN) {
-        if (!finite3(d.v)) return fail(RMPC_E_INVALID, "query " + std::to_string(k) + ": velocity not finite");
-        if (d.n < 0 || d.n > (1 << 24)) return fail(RMPC_E_INVALID, "query " + std::to_string(k) + ": n_points out of [0, 2^24]");
-        if (d.n > 0 && !d.points_dev) return fail(RMPC_E_INVALID, "query " + std::to_string(k) + ": points_dev is NULL");
-        if (rmpc_status st = check_params(sp)) {
-            g_last_error = "query " + std::to_string(k) + ": " + g_last_error;
-            return st;
-        }
-        Q.kind = 1;
-        rmpc::ScanArgs &A = Q.scan;
-        A.points = d.points_dev;
-        A.n_points = d.n;
-        A.min_range2 = sp->min_range_m * sp->min_range_m;
-        for (int a = 0; a < 3; ++a) A.vel64[a] = d.v[a];
-        A.radius64 = sp->radius;
-        A.pol = policy_f(sp, d.v);
-        A.rank_tol = sp->rank_tol;
-        Q.n_tiles = rmpc::scan_grid_blocks(d.n);
-    } else {
-        return fail(RMPC_E_INVALID, "query " + std::to_string(k) + ": unknown kind");
-    }
-    return RMPC_OK;
-}
-
-// One launch over queries [k0, k1) whose descriptors are in ctx->b_q_host[0 ..).
-rmpc_status batch_launch(rmpc_ctx *ctx, int nq, int n_tiles, const rmpc_launch_config &cfg,
-                         hipStream_t user, rmpc_result *out)
-{
-    const uint64_t seq = ++ctx->seq;
-    ctx->b_hdr_host->n_queries = nq;
-    ctx->b_hdr_host->n_tiles = n_tiles;
-    ctx->b_hdr_host->seq = seq;
-    const int per_cu = cfg.blocks_per_cu > 0 ? cfg.blocks_per_cu : rmpc::batch_blocks_per_cu(cfg.lookahead);
-    const int blocks = std::max(1, std::min(per_cu * ctx->cu_count, n_tiles));
-    rmpc::BatchArgs B;
-    B.hdr = ctx->b_hdr;
-    B.q = ctx->b_q;
-    B.work = ctx->b_work;
-    B.tickets = ctx->b_tickets;
-    B.partials = ctx->b_partials;
-    B.group_row_base = rmpc::kBatchMaxTiles;
-    B.results = ctx->b_results_host;
-    B.done = ctx->done_host;
-    // the launch runs on the context's own stream, after the caller's stream's work
-    hipStream_t s = ctx->own_stream;
-    const int gblocks = per_cu * ctx->cu_count;
-    if (cfg.use_graph &&
-        (!ctx->graph_exec || ctx->graph_blocks != gblocks || ctx->graph_lookahead != cfg.lookahead)) {
-        // the grid is fixed (resident blocks) and the per-batch data sit in device memory, so
-        // one captured launch serves every batch
-        if (ctx->graph_exec) { RMPC_HIP(hipGraphExecDestroy(ctx->graph_exec)); ctx->graph_exec = nullptr; }
-        hipGraph_t g;
-        RMPC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        const hipError_t le = rmpc::launch_batch(B, gblocks, cfg.lookahead, s);
-        const hipError_t ce = hipStreamEndCapture(s, &g);
-        if (le != hipSuccess) return fail(RMPC_E_HIP, std::string("batch capture: ") + hipGetErrorString(le));
-        if (ce != hipSuccess) return fail(RMPC_E_HIP, std::string("batch capture: ") + hipGetErrorString(ce));
-        const hipError_t ie = hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (ie != hipSuccess) return fail(RMPC_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(ie));
-        ctx->graph_blocks = gblocks;
-        ctx->graph_lookahead = cfg.lookahead;
-    }
-    RMPC_HIP(hipEventRecord(ctx->ev_dep, user));
-    RMPC_HIP(hipStreamWaitEvent(s, ctx->ev_dep, 0));
-    RMPC_HIP(hipMemcpyAsync(ctx->b_hdr, ctx->b_hdr_host, sizeof(rmpc::BatchHeader), hipMemcpyHostToDevice, s));
-    RMPC_HIP(hipMemcpyAsync(ctx->b_q, ctx->b_q_host, sizeof(rmpc::BatchQuery) * (size_t)nq,
-                            hipMemcpyHostToDevice, s));
-    if (cfg.use_graph) {
-        RMPC_HIP(hipGraphLaunch(ctx->graph_exec, s));
-    } else {
-        RMPC_HIP(rmpc::launch_batch(B, blocks, cfg.lookahead, s));
-    }
-    if (rmpc_status st = wait_result(ctx, s, seq)) return st;
-    std::memcpy(out, ctx->b_results_host, sizeof(rmpc_result) * (size_t)nq);
-    // the caller's later work may reuse the point buffers: order it after this launch
-    RMPC_HIP(hipEventRecord(ctx->ev_dep, s));
-    RMPC_HIP(hipStreamWaitEvent(user, ctx->ev_dep, 0));
-    return RMPC_OK;
-}
-
-rmpc_status run_batch(rmpc_ctx *ctx, const rmpc_query_desc *q, int32_t n, const rmpc_params *mp,
-                      const rmpc_params *sp, hipStream_t user, const rmpc_launch_config &cfg,
-                      rmpc_result *out)
-{
-    if (rmpc_status st = batch_prepare(ctx)) return st;
-    // validate everything before launching anything
-    std::vector<rmpc::BatchQuery> all((size_t)n);
-    for (int k = 0; k < n; ++k)
-        if (rmpc_status st = batch_describe(ctx, q[k], k, mp, sp, cfg, all[(size_t)k])) return st;
-    int k0 = 0;
-    while (k0 < n) {
-        int nq = 0, tiles = 0;
-        while (k0 + nq < n && nq < rmpc::kBatchMaxQueries &&
-               tiles + all[(size_t)(k0 + nq)].n_tiles <= rmpc::kBatchMaxTiles) {
-            rmpc::BatchQuery &Q = ctx->b_q_host[nq];
-            Q = all[(size_t)(k0 + nq)];
-            Q.tile_begin = tiles;
-            tiles += Q.n_tiles;
-            ++nq;
-        }
-        if (nq == 0) return fail(RMPC_E_INVALID, "a query needs more tiles than one launch holds");
-        if (rmpc_status st = batch_launch(ctx, nq, tiles, cfg, user, out + k0)) return st;
-        k0 += nq;
-    }
-    return RMPC_OK;
-}
-
-// Cache key of a tuned configuration: architecture, storage types present, ray-count bucket.
-std::string tune_key(rmpc_ctx *ctx, const rmpc_query_desc *q, int32_t n)
-{
-    hipDeviceProp_t prop;
-    std::string arch = "gpu";
-    if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) arch = prop.gcnArchName;
-    arch = arch.substr(0, arch.find(':'));
-    bool dt[3] = {false, false, false};
-    bool scan = false;
-    double mean = 0.0;
-    for (int k = 0; k < n; ++k) {
-        if (q[k].kind == RMPC_KIND_SCAN) { scan = true; continue; }
-        auto it = ctx->maps.find(q[k].map_id);
-        if (it != ctx->maps.end()) dt[it->second.desc.dtype] = true;
-        mean += q[k].n;
-    }
-    mean /= std::max(1, n);
-    int bucket = 0;
-    while ((1 << (bucket + 1)) <= mean) ++bucket;
-    return arch + "|" + (dt[0] ? "f32" : "") + (dt[1] ? "f16" : "") + (dt[2] ? "u8" : "") +
-           (scan ? "+scan" : "") + "|n2^" + std::to_string(bucket) + "|q" + std::to_string(n >= 64 ? 64 : n);
-}
-
-// Tiny JSON cache: one object of "key": [lookahead, lane_target_log2, blocks_per_cu].
-bool cache_lookup(const char *path, const std::string &key, rmpc_launch_config *c)
-{
-    if (!path) return false;
-    FILE *f = std::fopen(path, "r");
-    if (!f) return false;
-    std::string text;
-    char buf[4096];
-    size_t got;
-    while ((got = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, got);
-    std::fclose(f);
-    const std::string pat = "\"" + key + "\": [";
-    const size_t at = text.find(pat);
-    if (at == std::string::npos) return false;
-    int a, b, d;
-    if (std::sscanf(text.c_str() + at + pat.size(), "%d, %d, %d", &a, &b, &d) != 3) return false;
-    c->lookahead = a;
-    c->lane_target_log2 = b;
-    c->blocks_per_cu = d;
-    return check_config(c) == RMPC_OK;
-}
-
-void cache_store(const char *path, const std::string &key, const rmpc_launch_config &c)
-{
-    if (!path) return;
-    std::vector<std::pair<std::string, std::string>> entries;
-    if (FILE *f = std::fopen(path, "r")) {
-        char line[512];
-        while (std::fgets(line, sizeof line, f)) {
-            const char *q1 = std::strchr(line, '"');
-            if (!q1) continue;
-            const char *q2 = std::strchr(q1 + 1, '"');
-            const char *lb = q2 ? std::strchr(q2, '[') : nullptr;
-            const char *rb = lb ? std::strchr(lb, ']') : nullptr;
-            if (!rb) continue;
-            entries.emplace_back(std::string(q1 + 1, q2), std::string(lb, rb + 1));
-        }
-        std::fclose(f);
-    }
-    const std::string val = "[" + std::to_string(c.lookahead) + ", " + std::to_string(c.lane_target_log2) +
-                            ", " + std::to_string(c.blocks_per_cu) + "]";
-    bool found = false;
-    for (auto &e : entries)
-        if (e.first == key) { e.second = val; found = true; }
-    if (!found) entries.emplace_back(key, val);
-    const std::string tmp = std::string(path) + ".tmp";
-    FILE *f = std::fopen(tmp.c_str(), "w");
-    if (!f) return;
-    std::fprintf(f, "{\n");
-    for (size_t i = 0; i < entries.size(); ++i)
-        std::fprintf(f, "  \"%s\": %s%s\n", entries[i].first.c_str(), entries[i].second.c_str(),
-                     i + 1 < entries.size() ? "," : "");
-    std::fprintf(f, "}\n");
-    std::fclose(f);
-    std::rename(tmp.c_str(), path);
-}
-
-}  // namespace
+using namespace rmpc_host;
 
 extern "C" {
 
@@ -639,12 +278,14 @@ rmpc_status rmpc_create(int device, void *arena_dev, size_t arena_bytes, rmpc_ct
     c->next_map_id = 0;
     c->cfg[RMPC_CONFIG_QUERY] = rmpc_launch_config{rmpc::kLookahead, 17, 0, 0};
     c->cfg[RMPC_CONFIG_BATCH] = rmpc_launch_config{8, 14, 0, 0};
-    c->batch_ready = false;
-    c->own_stream = nullptr;
     c->ev_dep = nullptr;
-    c->graph_exec = nullptr;
-    c->graph_blocks = c->graph_lookahead = 0;
+    c->server = nullptr;
     c->cu_count = 0;
+    if (hipDeviceGetAttribute(&c->cu_count, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+        c->cu_count < 1) {
+        delete c;
+        return fail(RMPC_E_HIP, "cannot read the device's compute-unit count");
+    }
     c->profiling = false;
     c->ev0 = c->ev1 = nullptr;
     c->prof_ms = 0.0;
@@ -720,17 +361,12 @@ rmpc_status rmpc_destroy(rmpc_ctx *ctx)
 {
     if (!ctx) return RMPC_OK;
     DeviceGuard dg(ctx->device);
+    server_destroy(ctx);
     (void)hipDeviceSynchronize();
+    slot_destroy(ctx, ctx->batch);
     (void)hipHostFree(ctx->result_host);
     (void)hipHostFree(ctx->done_host);
-    if (ctx->batch_ready) {
-        (void)hipHostFree(ctx->b_results_host);
-        (void)hipHostFree(ctx->b_hdr_host);
-        (void)hipHostFree(ctx->b_q_host);
-    }
-    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
     if (ctx->ev_dep) (void)hipEventDestroy(ctx->ev_dep);
-    if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     delete ctx;
@@ -741,6 +377,7 @@ rmpc_status rmpc_map_upload(rmpc_ctx *ctx, const rmpc_map_desc *desc, const void
                             int voxels_on_device, void *hip_stream, int32_t *map_id_out)
 {
     if (!ctx || !desc || !voxels || !map_id_out) return fail(RMPC_E_INVALID, "NULL argument");
+    if (ctx->server) return fail(RMPC_E_INVALID, "maps cannot change while the server runs");
     if (desc->nx < 1 || desc->ny < 1 || desc->nz < 1 || desc->nx > kMaxDim || desc->ny > kMaxDim ||
         desc->nz > kMaxDim)
         return fail(RMPC_E_INVALID, "grid dimensions out of [1, 4096]");
@@ -800,6 +437,7 @@ rmpc_status rmpc_map_upload(rmpc_ctx *ctx, const rmpc_map_desc *desc, const void
 rmpc_status rmpc_map_release(rmpc_ctx *ctx, int32_t map_id)
 {
     if (!ctx) return fail(RMPC_E_INVALID, "ctx is NULL");
+    if (ctx->server) return fail(RMPC_E_INVALID, "maps cannot change while the server runs");
     auto it = ctx->maps.find(map_id);
     if (it == ctx->maps.end()) return fail(RMPC_E_NOMAP, "unknown map id");
     DeviceGuard dg(ctx->device);
@@ -819,14 +457,13 @@ rmpc_status rmpc_query(rmpc_ctx *ctx, int32_t map_id, const double x[3], const d
     DeviceGuard dg(ctx->device);
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     rmpc::RayArgs A;
-    const MapEntry *me = nullptr;
-    if (rmpc_status st = setup_query(ctx, map_id, x, n_rays, params, ctx->cfg[RMPC_CONFIG_QUERY], A, &me))
+    if (rmpc_status st = setup_query(ctx, map_id, x, n_rays, params, ctx->cfg[RMPC_CONFIG_QUERY], A))
         return st;
     A.seq = ++ctx->seq;
     A.pol = policy_f(params, v);
     for (int a = 0; a < 3; ++a) A.vel64[a] = v[a];
     RMPC_HIP(rmpc::launch_raycast(A, s, false, ctx->profiling ? ctx->ev0 : nullptr, ctx->ev1));
-    if (rmpc_status st = wait_result(ctx, s, A.seq)) return st;
+    if (rmpc_status st = wait_done(ctx->done_host, s, A.seq)) return st;
     std::memcpy(out, ctx->result_host, sizeof(rmpc_result));
     if (ctx->profiling) RMPC_HIP(hipEventSynchronize(ctx->ev1));
     return account_profile(ctx);
@@ -841,8 +478,7 @@ rmpc_status rmpc_trace_debug(rmpc_ctx *ctx, int32_t map_id, const double x[3], i
     DeviceGuard dg(ctx->device);
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     rmpc::RayArgs A;
-    const MapEntry *me = nullptr;
-    if (rmpc_status st = setup_query(ctx, map_id, x, n_rays, params, ctx->cfg[RMPC_CONFIG_QUERY], A, &me))
+    if (rmpc_status st = setup_query(ctx, map_id, x, n_rays, params, ctx->cfg[RMPC_CONFIG_QUERY], A))
         return st;
     A.seq = ++ctx->seq;
     A.dbg_hit = hit_lin_dev;
@@ -880,7 +516,7 @@ rmpc_status rmpc_scan_query(rmpc_ctx *ctx, const float *points_dev, int32_t n_po
     A.done = ctx->done_host;
     A.seq = ++ctx->seq;
     RMPC_HIP(rmpc::launch_scan(A, s, ctx->profiling ? ctx->ev0 : nullptr, ctx->ev1));
-    if (rmpc_status st = wait_result(ctx, s, A.seq)) return st;
+    if (rmpc_status st = wait_done(ctx->done_host, s, A.seq)) return st;
     std::memcpy(out, ctx->result_host, sizeof(rmpc_result));
     if (ctx->profiling) RMPC_HIP(hipEventSynchronize(ctx->ev1));
     return account_profile(ctx);
@@ -901,53 +537,6 @@ rmpc_status rmpc_config_get(rmpc_ctx *ctx, int32_t which, rmpc_launch_config *cf
     if (!ctx || !cfg) return fail(RMPC_E_INVALID, "NULL argument");
     if (which != RMPC_CONFIG_QUERY && which != RMPC_CONFIG_BATCH) return fail(RMPC_E_INVALID, "unknown config");
     *cfg = ctx->cfg[which];
-    return RMPC_OK;
-}
-
-rmpc_status rmpc_query_batch(rmpc_ctx *ctx, const rmpc_query_desc *q, int32_t n,
-                             const rmpc_params *map_params, const rmpc_params *scan_params,
-                             void *hip_stream, rmpc_result *out)
-{
-    if (!ctx || !q || !out) return fail(RMPC_E_INVALID, "NULL argument");
-    if (n < 1) return fail(RMPC_E_INVALID, "n must be >= 1");
-    DeviceGuard dg(ctx->device);
-    return run_batch(ctx, q, n, map_params, scan_params, static_cast<hipStream_t>(hip_stream),
-                     ctx->cfg[RMPC_CONFIG_BATCH], out);
-}
-
-rmpc_status rmpc_tune_batch(rmpc_ctx *ctx, const rmpc_query_desc *q, int32_t n,
-                            const rmpc_params *map_params, const rmpc_params *scan_params,
-                            void *hip_stream, const char *cache_path, rmpc_launch_config *best)
-{
-    if (!ctx || !q) return fail(RMPC_E_INVALID, "NULL argument");
-    if (n < 1) return fail(RMPC_E_INVALID, "n must be >= 1");
-    DeviceGuard dg(ctx->device);
-    hipStream_t user = static_cast<hipStream_t>(hip_stream);
-    const std::string key = tune_key(ctx, q, n);
-    rmpc_launch_config chosen = ctx->cfg[RMPC_CONFIG_BATCH];
-    if (!cache_lookup(cache_path, key, &chosen)) {
-        std::vector<rmpc_result> res((size_t)n);
-        double best_ms = 1e30;
-        const int max_per_cu = std::max(1, rmpc::batch_blocks_per_cu(8));
-        for (int la : {4, 8, 16})
-            for (int lt : {12, 14, 16, 18})
-                for (int bpc : {0, std::max(1, max_per_cu / 2)}) {
-                    rmpc_launch_config c{la, lt, bpc, 0};
-                    if (rmpc_status st = run_batch(ctx, q, n, map_params, scan_params, user, c, res.data()))
-                        return st;                                   // warm-up (and validation)
-                    const auto t0 = std::chrono::steady_clock::now();
-                    for (int r = 0; r < 3; ++r)
-                        if (rmpc_status st = run_batch(ctx, q, n, map_params, scan_params, user, c, res.data()))
-                            return st;
-                    const double ms = std::chrono::duration<double, std::milli>(
-                                          std::chrono::steady_clock::now() - t0).count() / 3.0;
-                    if (ms < best_ms) { best_ms = ms; chosen = c; }
-                }
-        cache_store(cache_path, key, chosen);
-    }
-    chosen.use_graph = ctx->cfg[RMPC_CONFIG_BATCH].use_graph;
-    ctx->cfg[RMPC_CONFIG_BATCH] = chosen;
-    if (best) *best = chosen;
     return RMPC_OK;
 }
 

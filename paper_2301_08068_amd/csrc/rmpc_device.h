@@ -14,7 +14,6 @@ namespace rmpc {
 constexpr int kWave = 64;
 constexpr int kBlock = 256;                 // threads per block of the ray kernels
 constexpr int kWavesPerBlock = kBlock / kWave;
-constexpr int kPartialWords = 32;           // one block partial: 18 floats + 4 ints, padded
 constexpr int kMaxBlocks = kMaxPartialSlots;
 
 // Per-ray debug flags (same bit values as the public RMPC_RAY_*).

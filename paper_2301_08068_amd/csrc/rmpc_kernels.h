@@ -20,6 +20,9 @@ constexpr int kGroups = 8;
 // Block-partial slots of one reduction (one per block of a launch).
 constexpr int kMaxPartialSlots = 4096;
 
+// Words of one block partial in device memory: 18 floats + 4 integers, padded.
+constexpr int kPartialWords = 32;
+
 // A resident map in brick layout.  Voxel (x, y, z) lives in brick
 // (x >> lbx, y >> lby, z >> lbz); bricks are stored x-fastest and voxels inside a brick
 // too, so a voxel's element offset is X(x) + Y(y) + Z(z), each term a function of one
