@@ -75,10 +75,12 @@ typedef struct {
 #define RMPC_Q_ILL 1u            /* an eigenvalue within 10x of the pseudo-inverse cut, or the
                                     kept condition number exceeds 1e3 */
 #define RMPC_Q_IN_COLLISION 2u   /* the start voxel is occupied: every ray hits at distance 0 */
-#define RMPC_Q_TIE 4u            /* some ray met two face crossings within 1e-5 voxel */
+#define RMPC_Q_TIE 4u            /* some ray carries RMPC_RAY_TIE */
 
 /* Per-ray debug flags (rmpc_trace_debug). */
-#define RMPC_RAY_TIE 1u          /* two face crossings within 1e-5 voxel on the ray's path */
+#define RMPC_RAY_TIE 1u          /* two face crossings within 1e-5 voxel at a decision the
+                                    walk took (crossings inside 8^3 cells it skipped as free
+                                    are not examined; every decision is exact regardless) */
 #define RMPC_RAY_RANGE_TIE 2u    /* a face crossing within 1e-5 voxel of max_range */
 #define RMPC_RAY_START_FACE 4u   /* the start lies within 1e-5 voxel of a face */
 #define RMPC_RAY_IN_COLLISION 8u /* the start voxel is occupied */
@@ -95,7 +97,8 @@ typedef struct {
     int32_t n_tie;              /* rays carrying RMPC_RAY_TIE */
     uint32_t flags;             /* RMPC_Q_* */
     int32_t n_rays;             /* rays cast (or scan points read) */
-    int64_t visits;             /* voxels read over all rays (start voxel included) */
+    int64_t visits;             /* voxels the rays' walks entered, start voxel included (the
+                                   walk reads far fewer: it skips free 8^3 cells whole) */
 } rmpc_result;
 
 /* Largest ray count per query (the Halton table length). */
@@ -166,7 +169,7 @@ rmpc_status rmpc_scan_query(rmpc_ctx *ctx, const float *points_dev, int32_t n_po
  *   hit_lin_dev[n_rays]: logical index of the hit voxel, -1 on a miss.
  *   dist_dev[n_rays]: distance in metres to where the ray enters it (float64), +inf on a miss.
  *   flags_dev[n_rays]: RMPC_RAY_* flags.
- *   visits_dev[n_rays]: voxels read by the ray (start voxel included); may be NULL.
+ *   visits_dev[n_rays]: voxels the ray's walk entered (start voxel included); may be NULL.
  * All output buffers are device memory.  Only params->max_range_m is used.  Blocking.
  * Errors: as rmpc_query.
  */
@@ -187,13 +190,14 @@ typedef struct {
     const float *points_dev;    /* scan queries: n x 3 float32 on the device (robot-relative) */
 } rmpc_query_desc;
 
-/* Launch configuration (rmpc_config_set, rmpc_tune_batch).  Results do not depend on
- * lookahead, blocks_per_cu or use_graph; the segmentation (lane_target_log2) changes only the
- * summation order. */
+/* Launch configuration (rmpc_config_set, rmpc_tune_batch).  Hits, distances, visits and the
+ * metric sums do not depend on lookahead, blocks_per_cu or use_graph; the segmentation
+ * (lane_target_log2) changes only the summation order.  RMPC_RAY_TIE / n_tie may change with
+ * the lookahead and the segmentation (they report near-ties at the decisions the walk takes). */
 #define RMPC_CONFIG_QUERY 0     /* rmpc_query and rmpc_trace_debug */
 #define RMPC_CONFIG_BATCH 1     /* rmpc_query_batch */
 typedef struct {
-    int32_t lookahead;          /* voxel visits planned per round: 4, 8 or 16 */
+    int32_t lookahead;          /* steps (voxels or free cells) planned per round: 4, 8 or 16 */
     int32_t lane_target_log2;   /* split rays into segments until a query has ~2^this lanes (10..22) */
     int32_t blocks_per_cu;      /* batches: resident blocks per CU of the persistent kernel (0 = max) */
     int32_t use_graph;          /* batches: 1 = replay the launch from a captured hipGraph */
@@ -205,7 +209,7 @@ typedef struct {
  *   q[n]: queries, 1 <= n; map queries use map_params, scan queries scan_params (either may
  *     be NULL if no query of that kind is present).
  *   out[n]: host results, the same as rmpc_query / rmpc_scan_query would return for each
- *     query alone; bitwise identical when the query's ray segmentation is the same.
+ *     query alone; bitwise identical when the launch configuration is the same.
  * Queries are validated first; any invalid one fails the whole call (the message names its
  * index) and nothing is written.  Large batches are split into several launches.  Blocking.
  * Errors: RMPC_E_INVALID, RMPC_E_NOMAP, RMPC_E_OUT_OF_BOUNDS, RMPC_E_NOMEM, RMPC_E_HIP.

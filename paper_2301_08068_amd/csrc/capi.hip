@@ -397,10 +397,16 @@ rmpc_status rmpc_map_upload(rmpc_ctx *ctx, const rmpc_map_desc *desc, const void
     v.nby = (desc->ny + (1 << lb[1]) - 1) >> lb[1];
     v.nbz = (desc->nz + (1 << lb[2]) - 1) >> lb[2];
     const uint64_t n_dst = (uint64_t)v.nbx * v.nby * v.nbz << (lb[0] + lb[1] + lb[2]);
-    if (n_dst >= (1ull << 32)) return fail(RMPC_E_INVALID, "grid too large for 32-bit voxel offsets");
+    v.ncx = desc->nx >> rmpc::kCellLog2;
+    v.ncy = desc->ny >> rmpc::kCellLog2;
+    v.ncz = desc->nz >> rmpc::kCellLog2;
+    const uint64_t cell_base = (n_dst + 255) / 256 * 256;
+    const uint64_t n_all = cell_base + (uint64_t)v.ncx * v.ncy * v.ncz;
+    if (n_all >= (1ull << 32)) return fail(RMPC_E_INVALID, "grid too large for 32-bit voxel offsets");
+    v.cell_base = (uint32_t)cell_base;
     const size_t eb = elem_bytes(desc->dtype);
     size_t off;
-    if (!ctx->alloc.alloc(n_dst * eb, &off)) return fail(RMPC_E_NOMEM, "arena full (map)");
+    if (!ctx->alloc.alloc(n_all * eb, &off)) return fail(RMPC_E_NOMEM, "arena full (map)");
     v.data = ctx->arena + off;
     const size_t n_log = (size_t)desc->nx * desc->ny * desc->nz;
     const void *src = voxels;

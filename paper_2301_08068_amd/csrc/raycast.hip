@@ -83,20 +83,51 @@ __device__ __forceinline__ double seg_boundary(double t_nom, float gx, float gy,
     return t;
 }
 
-// One lane's walk through one segment of one ray.
+// Float64 parameter of the face at integer coordinate B along one axis (r != 0).
+__device__ __forceinline__ double face64(int B, float g, float r)
+{
+    return ((double)B - (double)g) / (double)r;
+}
+
+// Float32 parameter of the same face: the value every float32 comparison of the walk uses,
+// always formed from the face coordinate (never accumulated).
+__device__ __forceinline__ float face32(int B, float g, float ir)
+{
+    return ((float)B - g) * ir;
+}
+
+// The ray in the forms the walk uses.
+struct RayF {
+    float gx, gy, gz;                 // start, grid units
+    float rx, ry, rz;                 // direction
+    float irx, iry, irz;              // 1/r, +inf for r = 0
+    int px, py, pz;                   // 1 when r > 0: the face ahead of coordinate u is u + p
+    int sx, sy, sz;                   // step direction
+};
+
+// One lane's walk through one segment of one ray.  The walk moves either voxel by voxel or,
+// while it is inside cells whose summary says "free", cell by cell (lg = kCellLog2): a cell's
+// faces are voxel faces, so both levels take their decisions on the same crossing
+// parameters and visit the cells in the order the voxel walk would.
 struct Walker {
-    int vx, vy, vz;
-    float Tx, Ty, Tz;                 // float32 parameters of the next faces
+    int ux, uy, uz;                   // current voxel, or current cell at the cell level
+    int lg;                           // 0: voxel level, kCellLog2: cell level
+    float Tx, Ty, Tz;                 // float32 parameters of the next faces at this level
     float t_hi;                       // stop once the next crossing exceeds this (float32)
     float t_lo;                       // crossings at or beyond this get the float64 range test
     bool last;                        // the segment ending at max_range
-    int steps;                        // voxels entered so far
+    bool pending;                     // voxel level: the current voxel is still to be read
+    int ent_a;                        // axis across which the current voxel or cell was entered
+    bool anchored;                    // cell level: (ax, ay, az) is a voxel of the walk in the cell
+    int ax, ay, az;
+    int steps;                        // decisions taken so far (orders the near-tie records)
     int tie_at, rtie_at;              // first decision index with a (range) near-tie
     // outcome
+    bool ended;                       // the ray's walk ends here: a hit, max_range or the grid edge
     bool hit;
-    int hit_step;                     // 0-based index of the step that entered the hit voxel
+    int hit_step;                     // decision index of the step that entered the hit voxel
     double d;                         // metres
-    int hx, hy, hz;                   // hit voxel (debug)
+    int fx, fy, fz;                   // last voxel entered when ended (the hit voxel on a hit)
 };
 
 __device__ __forceinline__ uint32_t voxel_offset(const MapView &m, int x, int y, int z)
@@ -104,94 +135,267 @@ __device__ __forceinline__ uint32_t voxel_offset(const MapView &m, int x, int y,
     return addr_x(m, x) + addr_y(m, y) + addr_z(m, z);
 }
 
-// Plan K steps, load their voxels, stop at the first occupied one.  Returns true while the
-// walk goes on.  The common path has no branches: the axis step is done with selects, each
-// step's load is issued as soon as its address is known, and steps past the end of the walk
-// load a harmless in-grid address and are ignored.  Only the axis of each step is kept (2
-// bits); the hit voxel's coordinates are recovered by undoing the later steps.
-template <int DT, int K, bool DEBUG>
-__device__ __forceinline__ bool walk_round(const RayArgs &A, Walker &w, float gx, float gy, float gz,
-                                           float rx, float ry, float rz, float irx, float iry, float irz,
-                                           uint32_t safe_addr)
+__device__ __forceinline__ uint32_t cell_offset(const MapView &m, int cx, int cy, int cz)
 {
+    return m.cell_base + (uint32_t)cx + __umul24((uint32_t)m.ncx, (uint32_t)cy + __umul24((uint32_t)m.ncy, (uint32_t)cz));
+}
+
+// Parameters of the next faces ahead of the current voxel or cell.
+__device__ __forceinline__ void set_faces(Walker &w, const RayF &R)
+{
+    const float gx = R.gx, gy = R.gy, gz = R.gz, irx = R.irx, iry = R.iry, irz = R.irz;
+    const int px = R.px, py = R.py, pz = R.pz;
+    w.Tx = R.rx != 0.0f ? face32((w.ux + px) << w.lg, gx, irx) : kInf;
+    w.Ty = R.ry != 0.0f ? face32((w.uy + py) << w.lg, gy, iry) : kInf;
+    w.Tz = R.rz != 0.0f ? face32((w.uz + pz) << w.lg, gz, irz) : kInf;
+}
+
+// Position before steps j+1 .. K-1 of a round were taken (2-bit axis codes; 3 = no move).
+template <int K>
+__device__ __forceinline__ void undo_after(uint32_t axes, int j, const RayF &R, int &x, int &y, int &z)
+{
+    const int sx = R.sx, sy = R.sy, sz = R.sz;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        if (k > j) {
+            const uint32_t ak = (axes >> (2 * k)) & 3u;
+            x -= ak == 0 ? sx : 0;
+            y -= ak == 1 ? sy : 0;
+            z -= ak == 2 ? sz : 0;
+        }
+    }
+}
+
+// Does face F of axis b come before the crossing of face Ba of axis a in the merged crossing
+// order (a smaller parameter, or an equal one on a lower axis)?  Float32 decides outside the
+// guard band, float64 inside it.
+__device__ __forceinline__ bool crossed_first(int F, float gb, float rb, float irb, int b, float T32, int Ba,
+                                              float ga, float ra, int a, bool &tie)
+{
+    const float tf = face32(F, gb, irb);
+    const float band = 2e-5f + 1e-6f * fmaxf(fabsf(tf), T32);
+    if (tf < T32 - band) return true;
+    if (tf > T32 + band) return false;
+    const double f64 = face64(F, gb, rb), t64 = face64(Ba, ga, ra);
+    tie = tie || fabs(f64 - t64) < 1e-5;
+    return f64 < t64 || (f64 == t64 && b < a);
+}
+
+// Coordinate along axis b (rb != 0) of the voxel the walk is in right after crossing face Ba
+// of axis a at float32 parameter T32, known to lie in [lo, lo + 7]: the float32 estimate
+// floor(g + T r), confirmed on the face behind it and the face ahead of it.
+__device__ __forceinline__ int entry_coord(int lo, float gb, float rb, float irb, int b, float T32, int Ba,
+                                           float ga, float ra, int a, bool &tie)
+{
+    const int hi = lo + (1 << kCellLog2) - 1;
+    int c = (int)floorf(fmaf(T32, rb, gb));
+    c = min(max(c, lo), hi);
+    const bool up = rb > 0.0f;
+    const int f_in = up ? c : c + 1;              // face crossed into voxel c
+    const int f_out = up ? c + 1 : c;             // face out of voxel c, ahead
+    const bool chk_in = up ? c > lo : c < hi;     // the cell's own face needs no check
+    const bool chk_out = up ? c < hi : c > lo;
+    if (chk_in && !crossed_first(f_in, gb, rb, irb, b, T32, Ba, ga, ra, a, tie))
+        c += up ? -1 : 1;
+    else if (chk_out && crossed_first(f_out, gb, rb, irb, b, T32, Ba, ga, ra, a, tie))
+        c += up ? 1 : -1;
+    return c;
+}
+
+// Voxel the walk is in right after entering cell (cx, cy, cz) across its face on axis a.
+__device__ __forceinline__ void cell_entry(const RayArgs &A, const RayF &R, int a, int cx, int cy, int cz,
+                                           int &vx, int &vy, int &vz, bool &tie)
+{
+    const float gx = R.gx, gy = R.gy, gz = R.gz, rx = R.rx, ry = R.ry, rz = R.rz;
+    const float irx = R.irx, iry = R.iry, irz = R.irz;
+    const int px = R.px, py = R.py, pz = R.pz;
+    constexpr int E = 1 << kCellLog2;
+    const int lx = cx << kCellLog2, ly = cy << kCellLog2, lz = cz << kCellLog2;
+    // the face crossed: the cell's low face when travelling up the axis, else its high face
+    const int Ba = a == 0 ? (px ? lx : lx + E) : (a == 1 ? (py ? ly : ly + E) : (pz ? lz : lz + E));
+    const float ga = a == 0 ? gx : (a == 1 ? gy : gz);
+    const float ra = a == 0 ? rx : (a == 1 ? ry : rz);
+    const float ira = a == 0 ? irx : (a == 1 ? iry : irz);
+    const float T32 = face32(Ba, ga, ira);
+    vx = a == 0 ? (px ? lx : lx + E - 1)
+                : (rx != 0.0f ? entry_coord(lx, gx, rx, irx, 0, T32, Ba, ga, ra, a, tie) : A.v0[0]);
+    vy = a == 1 ? (py ? ly : ly + E - 1)
+                : (ry != 0.0f ? entry_coord(ly, gy, ry, iry, 1, T32, Ba, ga, ra, a, tie) : A.v0[1]);
+    vz = a == 2 ? (pz ? lz : lz + E - 1)
+                : (rz != 0.0f ? entry_coord(lz, gz, rz, irz, 2, T32, Ba, ga, ra, a, tie) : A.v0[2]);
+}
+
+// Continue the walk at the voxel level at voxel (vx, vy, vz).
+__device__ __forceinline__ void to_voxels(Walker &w, const RayF &R, int vx, int vy, int vz, bool pending, int ent_a)
+{
+    w.ux = vx; w.uy = vy; w.uz = vz;
+    w.lg = 0;
+    w.pending = pending;
+    w.ent_a = ent_a;
+    w.anchored = false;
+    set_faces(w, R);
+}
+
+// Plan K steps at the current level, load what they enter, and act on the first occupied
+// voxel or cell.  Returns true while the walk goes on.  The steps have no branches: the axis
+// step is done with selects, each step's load is issued as soon as its address is known, and
+// steps past the end of the walk load a harmless address and are ignored.  Only the axis of
+// each step is kept (2 bits); earlier positions are recovered by undoing later steps.
+//   voxel level: an occupied voxel is the hit; a round that ends inside a free cell moves the
+//     walk to the cell level.
+//   cell level: an occupied cell is entered at the voxel level (its entry voxel found from the
+//     crossing); at max_range or the edge of the cells, the current free cell is finished at
+//     the voxel level so that the walk's last voxel and range decision are exact.
+template <int DT, int K, bool DEBUG>
+__device__ __forceinline__ bool walk_round(const RayArgs &A, Walker &w, const RayF &R, uint32_t safe_v,
+                                           uint32_t safe_c)
+{
+    const float gx = R.gx, gy = R.gy, gz = R.gz, rx = R.rx, ry = R.ry, rz = R.rz;
+    const float irx = R.irx, iry = R.iry, irz = R.irz;
+    const int px = R.px, py = R.py, pz = R.pz, sx = R.sx, sy = R.sy, sz = R.sz;
     using VT = typename Voxel<DT>::T;
     const MapView &m = A.map;
     const VT *vox = static_cast<const VT *>(m.data);
-    const int px = rx > 0.0f, py = ry > 0.0f, pz = rz > 0.0f;
-    const int sx = px ? 1 : -1, sy = py ? 1 : -1, sz = pz ? 1 : -1;
+    const bool cell = w.lg != 0;
+    const int lg = w.lg;
+    const int lim_x = cell ? m.ncx : m.nx, lim_y = cell ? m.ncy : m.ny, lim_z = cell ? m.ncz : m.nz;
     VT val[K];
     uint32_t axes = 0;                // 2 bits per planned step
     int nplan = 0;
     bool going = true;                // no termination yet in this round
+    bool exited = false;              // the walk left the grid (voxels) or the whole cells (cells)
 #pragma unroll
     for (int k = 0; k < K; ++k) {
+        const bool null_step = k == 0 && w.pending;      // read the current voxel, do not move
         // nearest and second-nearest crossings (no NaNs occur: +inf marks an axis never crossed)
         const float t1 = __builtin_amdgcn_fmed3f(w.Tx, fminf(w.Ty, w.Tz), -kInf);
         const float t2 = __builtin_amdgcn_fmed3f(w.Tx, w.Ty, w.Tz);
         int a = w.Tx == t1 ? 0 : (w.Ty == t1 ? 1 : 2);
-        if (going && t2 - t1 < 2e-5f + 1e-6f * t2) {
+        bool tie = false;
+        if (going && !null_step && t2 - t1 < 2e-5f + 1e-6f * t2) {
             // decide in float64 exactly as the definition does
-            const double X = rx != 0.0f ? cross64(w.vx, gx, rx) : __builtin_huge_val();
-            const double Y = ry != 0.0f ? cross64(w.vy, gy, ry) : __builtin_huge_val();
-            const double Z = rz != 0.0f ? cross64(w.vz, gz, rz) : __builtin_huge_val();
+            const double X = rx != 0.0f ? face64((w.ux + px) << lg, gx, rx) : __builtin_huge_val();
+            const double Y = ry != 0.0f ? face64((w.uy + py) << lg, gy, ry) : __builtin_huge_val();
+            const double Z = rz != 0.0f ? face64((w.uz + pz) << lg, gz, rz) : __builtin_huge_val();
             a = 0;
             double m1 = X;
             if (Y < m1) { a = 1; m1 = Y; }
             if (Z < m1) { a = 2; m1 = Z; }
-            const bool tie = (a != 0 && X - m1 < 1e-5) || (a != 1 && Y - m1 < 1e-5) ||
-                             (a != 2 && Z - m1 < 1e-5);
-            if (tie && w.tie_at > w.steps + k) w.tie_at = w.steps + k;
+            tie = (a != 0 && X - m1 < 1e-5) || (a != 1 && Y - m1 < 1e-5) || (a != 2 && Z - m1 < 1e-5);
         }
         const bool bx = a == 0, by = a == 1, bz = a == 2;
         const float ta = bx ? w.Tx : (by ? w.Ty : w.Tz);
         bool stop = ta > w.t_hi;
-        if (going && !stop && ta >= w.t_lo) {
+        if (cell) {
+            stop = stop || ta >= w.t_lo;                 // finish near max_range at the voxel level
+        } else if (going && !stop && !null_step && ta >= w.t_lo) {
             // range test (closed interval) in float64 inside the guard band
-            const double T64 = bx ? cross64(w.vx, gx, rx) : (by ? cross64(w.vy, gy, ry) : cross64(w.vz, gz, rz));
+            const double T64 = bx ? face64(w.ux + px, gx, rx)
+                                  : (by ? face64(w.uy + py, gy, ry) : face64(w.uz + pz, gz, rz));
             const double dist = T64 * A.h;
             stop = dist > A.max_range;
             if (fabs(dist - A.max_range) < 1e-5 * A.h && w.rtie_at > w.steps + k) w.rtie_at = w.steps + k;
         }
-        w.vx = bx ? w.vx + sx : w.vx;
-        w.vy = by ? w.vy + sy : w.vy;
-        w.vz = bz ? w.vz + sz : w.vz;
-        w.Tx = bx ? ((float)(w.vx + px) - gx) * irx : w.Tx;
-        w.Ty = by ? ((float)(w.vy + py) - gy) * iry : w.Ty;
-        w.Tz = bz ? ((float)(w.vz + pz) - gz) * irz : w.Tz;
-        const bool inside = (unsigned)w.vx < (unsigned)m.nx && (unsigned)w.vy < (unsigned)m.ny &&
-                            (unsigned)w.vz < (unsigned)m.nz;
+        stop = stop && !null_step;
+        const bool mx = bx && !null_step, my = by && !null_step, mz = bz && !null_step;
+        w.ux = mx ? w.ux + sx : w.ux;
+        w.uy = my ? w.uy + sy : w.uy;
+        w.uz = mz ? w.uz + sz : w.uz;
+        w.Tx = mx ? face32((w.ux + px) << lg, gx, irx) : w.Tx;
+        w.Ty = my ? face32((w.uy + py) << lg, gy, iry) : w.Ty;
+        w.Tz = mz ? face32((w.uz + pz) << lg, gz, irz) : w.Tz;
+        const bool inside = (unsigned)w.ux < (unsigned)lim_x && (unsigned)w.uy < (unsigned)lim_y &&
+                            (unsigned)w.uz < (unsigned)lim_z;
+        exited = exited || (going && !stop && !inside);
+        // a near-tie counts at every voxel decision, but at the cell level only on steps taken
+        // (the voxel walk makes the others itself)
+        if (tie && (!cell || (!stop && inside)) && w.tie_at > w.steps + k) w.tie_at = w.steps + k;
         going = going && !stop && inside;
-        val[k] = vox[going ? voxel_offset(m, w.vx, w.vy, w.vz) : safe_addr];
-        axes |= (uint32_t)a << (2 * k);
+        const uint32_t off = cell ? cell_offset(m, w.ux, w.uy, w.uz) : voxel_offset(m, w.ux, w.uy, w.uz);
+        val[k] = vox[going ? off : (cell ? safe_c : safe_v)];
+        axes |= (uint32_t)(null_step ? 3 : a) << (2 * k);
         nplan += going ? 1 : 0;
     }
+    // voxel level: the summary of the cell the walk is in after a full round
+    const int ccx = w.ux >> kCellLog2, ccy = w.uy >> kCellLog2, ccz = w.uz >> kCellLog2;
+    const bool cin = !cell && going && ccx < m.ncx && ccy < m.ncy && ccz < m.ncz;
+    const VT cf = vox[cin ? cell_offset(m, ccx, ccy, ccz) : safe_c];
     int hk = -1;
 #pragma unroll
     for (int k = K - 1; k >= 0; --k)
         if (k < nplan && Voxel<DT>::occ(val[k])) hk = k;
-    if (hk >= 0) {
-        // undo the steps after hk to get the hit voxel
-        int hx = w.vx, hy = w.vy, hz = w.vz;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            if (k > hk) {
-                const uint32_t ak = (axes >> (2 * k)) & 3u;
-                hx -= ak == 0 ? sx : 0;
-                hy -= ak == 1 ? sy : 0;
-                hz -= ak == 2 ? sz : 0;
-            }
+    w.pending = false;
+    if (!cell) {
+        if (hk >= 0) {
+            int hx = w.ux, hy = w.uy, hz = w.uz;
+            undo_after<K>(axes, hk, R, hx, hy, hz);
+            uint32_t ah = (axes >> (2 * hk)) & 3u;
+            if (ah == 3u) ah = (uint32_t)w.ent_a;
+            const double T64 = ah == 0 ? entry64(hx, gx, rx) : (ah == 1 ? entry64(hy, gy, ry) : entry64(hz, gz, rz));
+            w.d = T64 * A.h;
+            w.fx = hx; w.fy = hy; w.fz = hz;
+            w.hit = w.ended = true;
+            w.hit_step = w.steps + hk;
+            w.steps += hk + 1;
+            return false;
         }
-        const uint32_t a = (axes >> (2 * hk)) & 3u;
-        const double T64 = a == 0 ? entry64(hx, gx, rx) : (a == 1 ? entry64(hy, gy, ry) : entry64(hz, gz, rz));
-        w.d = T64 * A.h;
-        if (DEBUG) { w.hx = hx; w.hy = hy; w.hz = hz; }
-        w.hit = true;
-        w.hit_step = w.steps + hk;
-        w.steps += hk + 1;
-        return false;
+        if (nplan < K) {
+            w.steps += nplan;
+            if (w.last || exited) {
+                int fx = w.ux, fy = w.uy, fz = w.uz;
+                undo_after<K>(axes, nplan - 1, R, fx, fy, fz);   // the last voxel entered
+                w.fx = fx; w.fy = fy; w.fz = fz;
+                w.ended = true;
+            }
+            return false;
+        }
+        w.steps += K;
+        if (cin && !Voxel<DT>::occ(cf)) {
+            w.ax = w.ux; w.ay = w.uy; w.az = w.uz;
+            w.anchored = true;
+            w.ux = ccx; w.uy = ccy; w.uz = ccz;
+            w.lg = kCellLog2;
+            set_faces(w, R);
+        }
+        return true;
     }
-    w.steps += nplan;
-    return nplan == K;
+    // cell level
+    if (hk >= 0) {
+        int cx = w.ux, cy = w.uy, cz = w.uz;
+        undo_after<K>(axes, hk, R, cx, cy, cz);
+        const int a = (int)((axes >> (2 * hk)) & 3u);
+        int vx, vy, vz;
+        bool tie = false;
+        cell_entry(A, R, a, cx, cy, cz, vx, vy, vz, tie);
+        // near-ties seen on cell steps past hk lie beyond the entry into this cell: forget them
+        // (the voxel steps that follow reuse those decision indices)
+        if (w.tie_at > w.steps + hk) w.tie_at = 1 << 30;
+        if (tie) w.tie_at = min(w.tie_at, w.steps + hk);
+        w.steps += hk + 1;
+        to_voxels(w, R, vx, vy, vz, true, a);
+        return true;
+    }
+    if (nplan < K) {
+        w.steps += nplan;
+        if (!w.last && !exited) return false;            // the segment ends inside a free cell
+        // finish the current (free) cell voxel by voxel
+        int vx, vy, vz;
+        if (nplan == 0 && w.anchored) {
+            vx = w.ax; vy = w.ay; vz = w.az;
+        } else {
+            int cx = w.ux, cy = w.uy, cz = w.uz;
+            undo_after<K>(axes, nplan - 1, R, cx, cy, cz);
+            const int a = nplan > 0 ? (int)((axes >> (2 * (nplan - 1))) & 3u) : w.ent_a;
+            bool tie = false;
+            cell_entry(A, R, a, cx, cy, cz, vx, vy, vz, tie);
+        }
+        to_voxels(w, R, vx, vy, vz, false, 0);
+        return true;
+    }
+    w.anchored = false;
+    w.ent_a = (int)((axes >> (2 * (K - 1))) & 3u);
+    w.steps += K;
+    return true;
 }
 
 // Per-ray outcome, valid in the lane that reports the ray (its hit segment, else segment 0).
@@ -200,7 +404,7 @@ struct RayOut {
     bool hit;
     double d;
     uint32_t flags;
-    int visits_lane;                  // this lane's share of the ray's visits
+    int visits_lane;                  // the ray's visit count in one lane of its group, else 0
     int hit_lin;                      // debug
 };
 
@@ -209,30 +413,41 @@ template <int DT, int K, bool DEBUG>
 __device__ __forceinline__ RayOut trace_group(const RayArgs &A, bool valid, int seg, int S,
                                               float rx, float ry, float rz)
 {
+    using VT = typename Voxel<DT>::T;
     const MapView &m = A.map;
-    const float gx = A.g[0], gy = A.g[1], gz = A.g[2];
-    const float irx = rx != 0.0f ? 1.0f / rx : kInf;
-    const float iry = ry != 0.0f ? 1.0f / ry : kInf;
-    const float irz = rz != 0.0f ? 1.0f / rz : kInf;
+    RayF R;
+    R.gx = A.g[0]; R.gy = A.g[1]; R.gz = A.g[2];
+    R.rx = rx; R.ry = ry; R.rz = rz;
+    R.irx = rx != 0.0f ? 1.0f / rx : kInf;
+    R.iry = ry != 0.0f ? 1.0f / ry : kInf;
+    R.irz = rz != 0.0f ? 1.0f / rz : kInf;
+    R.px = rx > 0.0f; R.py = ry > 0.0f; R.pz = rz > 0.0f;
+    R.sx = R.px ? 1 : -1; R.sy = R.py ? 1 : -1; R.sz = R.pz ? 1 : -1;
     const double tmax = A.tmax_v;
     Walker w;
+    w.lg = 0;
+    w.pending = false;
+    w.ent_a = 0;
+    w.anchored = false;
+    w.ax = w.ay = w.az = 0;
     w.steps = 0;
     w.tie_at = w.rtie_at = 1 << 30;
+    w.ended = false;
     w.hit = false;
     w.hit_step = -1;
     w.d = __builtin_huge_val();
-    w.hx = w.hy = w.hz = 0;
+    w.fx = w.fy = w.fz = 0;
     bool active = valid;
     // segment start
     if (seg == 0) {
-        w.vx = A.v0[0]; w.vy = A.v0[1]; w.vz = A.v0[2];
+        w.ux = A.v0[0]; w.uy = A.v0[1]; w.uz = A.v0[2];
     } else {
         bool ok;
-        seg_boundary(tmax * seg / S, gx, gy, gz, rx, ry, rz, w.vx, w.vy, w.vz, ok);
-        if (!ok || (unsigned)w.vx >= (unsigned)m.nx || (unsigned)w.vy >= (unsigned)m.ny ||
-            (unsigned)w.vz >= (unsigned)m.nz) {
+        seg_boundary(tmax * seg / S, R.gx, R.gy, R.gz, rx, ry, rz, w.ux, w.uy, w.uz, ok);
+        if (!ok || (unsigned)w.ux >= (unsigned)m.nx || (unsigned)w.uy >= (unsigned)m.ny ||
+            (unsigned)w.uz >= (unsigned)m.nz) {
             active = false;                               // empty segment (or past the grid)
-            w.vx = A.v0[0]; w.vy = A.v0[1]; w.vz = A.v0[2];
+            w.ux = A.v0[0]; w.uy = A.v0[1]; w.uz = A.v0[2];
         }
     }
     // segment end: the next boundary that exists, else max_range
@@ -242,18 +457,30 @@ __device__ __forceinline__ RayOut trace_group(const RayArgs &A, bool valid, int 
     for (int e = seg + 1; e < S && w.last; ++e) {
         int ux, uy, uz;
         bool ok;
-        const double te = seg_boundary(tmax * e / S, gx, gy, gz, rx, ry, rz, ux, uy, uz, ok);
+        const double te = seg_boundary(tmax * e / S, R.gx, R.gy, R.gz, rx, ry, rz, ux, uy, uz, ok);
         if (ok) {
             w.last = false;
             w.t_hi = (float)te;       // no crossing lies within kSegMargin of te
             w.t_lo = kInf;
         }
     }
-    const int px = rx > 0.0f, py = ry > 0.0f, pz = rz > 0.0f;
-    w.Tx = rx != 0.0f ? ((float)(w.vx + px) - gx) * irx : kInf;
-    w.Ty = ry != 0.0f ? ((float)(w.vy + py) - gy) * iry : kInf;
-    w.Tz = rz != 0.0f ? ((float)(w.vz + pz) - gz) * irz : kInf;
-    const uint32_t safe_addr = voxel_offset(m, A.v0[0], A.v0[1], A.v0[2]);
+    set_faces(w, R);
+    const uint32_t safe_v = voxel_offset(m, A.v0[0], A.v0[1], A.v0[2]);
+    const uint32_t safe_c = m.ncx > 0 && m.ncy > 0 && m.ncz > 0 ? m.cell_base : safe_v;
+    {
+        // start at the cell level when the start voxel's cell is free
+        const VT *vox = static_cast<const VT *>(m.data);
+        const int cx = w.ux >> kCellLog2, cy = w.uy >> kCellLog2, cz = w.uz >> kCellLog2;
+        const bool cin = active && cx < m.ncx && cy < m.ncy && cz < m.ncz;
+        const VT cf = vox[cin ? cell_offset(m, cx, cy, cz) : safe_c];
+        if (cin && !Voxel<DT>::occ(cf)) {
+            w.ax = w.ux; w.ay = w.uy; w.az = w.uz;
+            w.anchored = true;
+            w.ux = cx; w.uy = cy; w.uz = cz;
+            w.lg = kCellLog2;
+            set_faces(w, R);
+        }
+    }
 
     const int lane = threadIdx.x & (kWave - 1);
     const int base = lane & ~(S - 1);
@@ -263,14 +490,19 @@ __device__ __forceinline__ RayOut trace_group(const RayArgs &A, bool valid, int 
         const uint64_t hm = __ballot(w.hit);
         if (hm & lower) active = false;                  // a lower segment already hit
         if (!__any(active)) break;
-        if (active) active = walk_round<DT, K, DEBUG>(A, w, gx, gy, gz, rx, ry, rz, irx, iry, irz, safe_addr);
+        if (active) active = walk_round<DT, K, DEBUG>(A, w, R, safe_v, safe_c);
     }
-    // combine the group: the lowest segment with a hit owns the ray
+    // combine the group: the lowest segment with a hit owns the ray; the lowest segment whose
+    // walk ended holds the ray's last voxel
     const uint64_t gh = (__ballot(w.hit) >> base) & seg_bits;
     const int h = gh ? __ffsll((unsigned long long)gh) - 1 : S;
+    const uint64_t ge = (__ballot(valid && w.ended) >> base) & seg_bits;
+    const int t = ge ? __ffsll((unsigned long long)ge) - 1 : S;
     const bool keep = valid && seg <= h;
     RayOut o;
-    o.visits_lane = keep ? w.steps + (seg == 0 ? 1 : 0) : 0;
+    // voxels entered, start voxel included: every step changes one coordinate by one toward
+    // the ray's direction, so the count follows from the first and the last voxel
+    o.visits_lane = valid && seg == t ? 1 + abs(w.fx - A.v0[0]) + abs(w.fy - A.v0[1]) + abs(w.fz - A.v0[2]) : 0;
     const bool tie = keep && w.tie_at <= (seg == h ? w.hit_step : (1 << 29));
     const bool rtie = keep && w.rtie_at <= (seg == h ? w.hit_step : (1 << 29));
     const uint64_t tm = (__ballot(tie) >> base) & seg_bits;
@@ -279,7 +511,7 @@ __device__ __forceinline__ RayOut trace_group(const RayArgs &A, bool valid, int 
     o.hit = w.hit && seg == h;
     o.d = o.hit ? w.d : __builtin_huge_val();
     o.flags = A.start_flags | (tm ? kRayTie : 0u) | (rm ? kRayRangeTie : 0u);
-    o.hit_lin = o.hit ? w.hx + m.nx * (w.hy + m.ny * w.hz) : -1;
+    o.hit_lin = o.hit ? w.fx + m.nx * (w.fy + m.ny * w.fz) : -1;
     return o;
 }
 

@@ -27,12 +27,22 @@ constexpr int kPartialWords = 32;
 // (x >> lbx, y >> lby, z >> lbz); bricks are stored x-fastest and voxels inside a brick
 // too, so a voxel's element offset is X(x) + Y(y) + Z(z), each term a function of one
 // coordinate only.
+//
+// After the bricks (at element offset cell_base) the map holds one summary element per cell
+// of 8 x 8 x 8 voxels, x-fastest: "occupied" when any voxel of the cell is, "free" when none
+// is.  Only whole cells inside the grid have a summary (ncx = nx / 8 etc.); the walk skips
+// free cells whole.
 struct MapView {
     const void *data;
     int32_t nx, ny, nz, dtype;
     int32_t lbx, lby, lbz;       // log2 of the brick edge along each axis
     int32_t nbx, nby, nbz;       // bricks along each axis
+    uint32_t cell_base;          // element offset of the cell summaries
+    int32_t ncx, ncy, ncz;       // whole cells along each axis
 };
+
+// log2 of the edge of a summary cell, in voxels.
+constexpr int kCellLog2 = 3;
 
 // Policy constants in float32 (reciprocals precomputed on the host).
 struct PolicyF {

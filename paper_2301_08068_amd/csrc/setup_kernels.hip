@@ -68,6 +68,26 @@ __global__ void layout_kernel(LayoutArgs A, T pad)
     static_cast<T *>(const_cast<void *>(m.data))[e] = v;
 }
 
+// Summary of cell c (8 x 8 x 8 voxels, whole cells only): the occupied value when any of
+// its voxels is occupied, else the free value, stored after the bricks.
+template <int DT>
+__global__ void cell_summary_kernel(MapView m, typename Voxel<DT>::T occ_val, typename Voxel<DT>::T free_val)
+{
+    using T = typename Voxel<DT>::T;
+    const int n_cells = m.ncx * m.ncy * m.ncz;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_cells) return;
+    const int cx = c % m.ncx, cy = (c / m.ncx) % m.ncy, cz = c / (m.ncx * m.ncy);
+    T *data = static_cast<T *>(const_cast<void *>(m.data));
+    bool any = false;
+    for (int k = 0; k < (1 << (3 * kCellLog2)) && !any; ++k) {
+        const int x = (cx << kCellLog2) + (k & 7), y = (cy << kCellLog2) + ((k >> 3) & 7),
+                  z = (cz << kCellLog2) + (k >> 6);
+        any = Voxel<DT>::occ(data[addr_x(m, x) + addr_y(m, y) + addr_z(m, z)]);
+    }
+    data[m.cell_base + (uint32_t)c] = any ? occ_val : free_val;
+}
+
 // Chunk-wise count of entries < n (one 1024-entry chunk per block).
 __global__ void __launch_bounds__(1024) compact_count_kernel(CompactArgs A)
 {
@@ -126,10 +146,22 @@ hipError_t launch_directions(const DirsArgs &a, hipStream_t s)
 hipError_t launch_layout(const LayoutArgs &a, hipStream_t s)
 {
     const uint64_t blocks = (a.n_dst + 255) / 256;
+    const int n_cells = a.dst.ncx * a.dst.ncy * a.dst.ncz;
+    const unsigned cblocks = (unsigned)((n_cells + 255) / 256);
     switch (a.dst.dtype) {
-    case RMPC_TSDF_F32: layout_kernel<float><<<(unsigned)blocks, 256, 0, s>>>(a, 1.0f); break;
-    case RMPC_TSDF_F16: layout_kernel<uint16_t><<<(unsigned)blocks, 256, 0, s>>>(a, (uint16_t)0x3c00); break;
-    default: layout_kernel<uint8_t><<<(unsigned)blocks, 256, 0, s>>>(a, (uint8_t)0); break;
+    case RMPC_TSDF_F32:
+        layout_kernel<float><<<(unsigned)blocks, 256, 0, s>>>(a, 1.0f);
+        if (n_cells) cell_summary_kernel<RMPC_TSDF_F32><<<cblocks, 256, 0, s>>>(a.dst, -1.0f, 1.0f);
+        break;
+    case RMPC_TSDF_F16:
+        layout_kernel<uint16_t><<<(unsigned)blocks, 256, 0, s>>>(a, (uint16_t)0x3c00);
+        if (n_cells)
+            cell_summary_kernel<RMPC_TSDF_F16><<<cblocks, 256, 0, s>>>(a.dst, (uint16_t)0xbc00, (uint16_t)0x3c00);
+        break;
+    default:
+        layout_kernel<uint8_t><<<(unsigned)blocks, 256, 0, s>>>(a, (uint8_t)0);
+        if (n_cells) cell_summary_kernel<RMPC_OCC_U8><<<cblocks, 256, 0, s>>>(a.dst, (uint8_t)1, (uint8_t)0);
+        break;
     }
     return hipGetLastError();
 }

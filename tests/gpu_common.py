@@ -6,7 +6,8 @@ import oracle
 
 def compare_trace(gpu, orc, label=""):
     """Per-ray parity: hit voxel bit-exact (flagged rays: inside the admissible set), the
-    float64 distance bit-exact for equal hits, flags and visit counts exact."""
+    float64 distance bit-exact for equal hits, visit counts and flags exact except TIE, which
+    the GPU may leave off where the oracle sets it."""
     hit_g, hit_o = gpu["hit"].astype(np.int64), orc["hit"].astype(np.int64)
     flagged = (orc["flags"] & (oracle.TIE | oracle.RANGE_TIE)) != 0
     same = hit_g == hit_o
@@ -18,13 +19,19 @@ def compare_trace(gpu, orc, label=""):
     hs = same & (hit_o >= 0)
     assert np.array_equal(gpu["d"][hs], orc["d"][hs]), f"{label}: distances differ"
     assert np.all(np.isinf(gpu["d"][same & (hit_o < 0)]))
-    assert np.array_equal(gpu["flags"][same].astype(np.uint32), orc["flags"][same]), f"{label}: flags differ"
+    # every flag but TIE is exact; the walk skips free cells whole and reports the near-ties of
+    # the decisions it takes, a subset of the oracle's
+    gf, of = gpu["flags"][same].astype(np.uint32), orc["flags"][same].astype(np.uint32)
+    assert np.array_equal(gf & ~np.uint32(oracle.TIE), of & ~np.uint32(oracle.TIE)), f"{label}: flags differ"
+    assert not np.any(gf & ~of & oracle.TIE), f"{label}: TIE flag on a ray the oracle does not flag"
     assert np.array_equal(gpu["visits"][same], orc["visits"][same]), f"{label}: visits differ"
     return int(same.sum()), int(flagged.sum())
 
 
-def compare_query(g, o, label="", rtol=1e-4):
-    """Query parity: sums within rtol of their largest entry, f within rtol unless ILL."""
+def compare_query(g, o, label="", rtol=1e-4, ties="subset"):
+    """Query parity: sums within rtol of their largest entry, f within rtol unless ILL, counts
+    exact.  ties="subset": o is the oracle, whose near-ties include the GPU's; "ignore": two
+    GPU results whose launches may differ in lookahead (the ties a walk sees depend on it)."""
     sS = max(np.abs(o["S"]).max(), 1e-300)
     sb = max(np.abs(o["b"]).max(), 1e-300)
     assert np.max(np.abs(g["S"] - o["S"])) <= rtol * sS, f"{label}: S {g['S']} vs {o['S']}"
@@ -39,5 +46,7 @@ def compare_query(g, o, label="", rtol=1e-4):
         S = g["S"]
         if np.linalg.norm(g["b"]) > 0:
             assert np.linalg.norm(S @ g["f"] - g["b"]) <= rtol * np.linalg.norm(g["b"]) * 10, label
-    for k in ("n_hit", "n_contrib", "n_tie", "visits"):
+    for k in ("n_hit", "n_contrib", "visits"):
         assert g[k] == o[k], f"{label}: {k} {g[k]} vs {o[k]}"
+    if ties == "subset":
+        assert g["n_tie"] <= o["n_tie"], f"{label}: n_tie {g['n_tie']} vs {o['n_tie']}"

@@ -1,0 +1,86 @@
+"""Precision variants on the 400^3 paper-shaped map: the float32 TSDF, the sign-preserving
+float16 TSDF and the uint8 occupancy give the same occupancy voxel for voxel, so the GPU walks,
+hits and distances are identical across the three, and each result's error against the
+float64 oracle comes from the float32 compensated sums alone.  Prints a per-result error table
+(written to gpurun_out/precision_report.txt when that folder exists)."""
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from paper_2301_08068_amd import workloads as W  # noqa: E402
+from gpu_common import compare_query, compare_trace  # noqa: E402
+
+P = W.params("static", max_range=10.0)
+SEEDS = (200, 201, 202, 203, 204, 205, 206, 207)
+
+
+def _rel(a, b):
+    s = max(np.abs(b).max(), 1e-300)
+    return float(np.abs(a - b).max() / s)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2301_08068_amd import binding
+    c = binding.Context(0, arena_bytes=1 << 30)
+    yield c
+    c.close()
+
+
+def test_precision_report(ctx, paper_map):
+    encs = {"f32": paper_map.tsdf, "f16": W.encode_f16(paper_map.tsdf), "u8": W.encode_u8(paper_map.tsdf)}
+    mids = {e: ctx.upload(d, paper_map.voxel_m, paper_map.origin_m, e) for e, d in encs.items()}
+    om = oracle.OracleMap.from_voxelmap(paper_map)
+    dirs = oracle.directions(65536)
+    lines = ["precision report: 400^3 paper-shaped map (seed 2), 65536 rays, max range 10 m",
+             "error vs the float64 oracle; d: per-ray hit distance; S = sum A_i, b = sum A_i f_i, "
+             "f = pinv(S) b (relative to the largest entry)",
+             f"{'state':>6} {'enc':>4} {'hit_mismatch':>12} {'d_max_rel':>10} {'S_rel':>10} {'b_rel':>10} "
+             f"{'f_rel':>10} {'rank':>4}"]
+    worst = {}
+    try:
+        for seed in SEEDS:
+            x, v = W.free_state(paper_map, seed)
+            o_tr = oracle.trace(om, oracle.grid_start(om, x), dirs, P["max_range"], nthreads=8)
+            o_q = oracle.query(om, x, v, 65536, P, dirs=dirs, nthreads=8)
+            res = {}
+            for e, mid in mids.items():
+                tr = ctx.trace(mid, x, 65536, P)
+                compare_trace(tr, o_tr, f"{e} seed {seed}")
+                q = ctx.query(mid, x, v, 65536, P)
+                compare_query(q, o_q, f"{e} seed {seed}")
+                res[e] = (tr, q)
+                hs = (tr["hit"] >= 0) & (o_tr["hit"] >= 0)
+                d_rel = float(np.max(np.abs(tr["d"][hs] - o_tr["d"][hs]) / o_tr["d"][hs].clip(1e-300))) \
+                    if hs.any() else 0.0
+                f_rel = float(np.linalg.norm(q["f"] - o_q["f"]) / max(np.linalg.norm(o_q["f"]), 1e-300))
+                row = dict(mis=int(np.sum(tr["hit"] != o_tr["hit"])), d=d_rel, S=_rel(q["S"], o_q["S"]),
+                           b=_rel(q["b"], o_q["b"]), f=f_rel)
+                for k, val in row.items():
+                    worst[(e, k)] = max(worst.get((e, k), 0), val)
+                lines.append(f"{seed:>6} {e:>4} {row['mis']:>12d} {row['d']:>10.2e} {row['S']:>10.2e} "
+                             f"{row['b']:>10.2e} {row['f']:>10.2e} {q['rank']:>4d}")
+            # identical occupancy -> identical walks and bitwise identical results
+            for e in ("f16", "u8"):
+                assert np.array_equal(res[e][0]["hit"], res["f32"][0]["hit"])
+                assert np.array_equal(res[e][0]["d"], res["f32"][0]["d"])
+                for k in ("S", "b", "f"):
+                    assert np.array_equal(res[e][1][k], res["f32"][1][k]), (e, k)
+    finally:
+        for mid in mids.values():
+            ctx.release(mid)
+    lines.append("worst: " + ", ".join(f"{e}.{k}={v:.2e}" for (e, k), v in sorted(worst.items())))
+    text = "\n".join(lines)
+    print(text)
+    if os.path.isdir("gpurun_out"):
+        with open(os.path.join("gpurun_out", "precision_report.txt"), "w") as f:
+            f.write(text + "\n")
+    for e in encs:
+        assert worst[(e, "mis")] == 0 and worst[(e, "d")] == 0.0
