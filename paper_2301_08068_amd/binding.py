@@ -194,6 +194,24 @@ def rmpc_query(ctx: int, map_id: int, x, v, n_rays: int, params: Dict[str, float
     return result_dict(r)
 
 
+class PreparedQuery:
+    """rmpc_query with its arguments marshalled once: each call passes the same C arguments
+    and returns the Result struct it filled (for loops that repeat one query)."""
+
+    def __init__(self, ctx: int, map_id: int, x, v, n_rays: int, params: Dict[str, float], stream=None):
+        self._args = (C.c_void_p(ctx), int(map_id), _d3(x), _d3(v), int(n_rays), C.byref(params_struct(params)),
+                      C.c_void_p(_stream_ptr(stream)))
+        self.result = Result()
+        self._out = C.byref(self.result)
+        self._fn = _lib.rmpc_query
+
+    def __call__(self) -> Result:
+        st = self._fn(*self._args, self._out)
+        if st != RMPC_OK:
+            _check(st, "rmpc_query")
+        return self.result
+
+
 def rmpc_scan_query(ctx: int, points_ptr: int, n_points: int, v, params: Dict[str, float],
                     stream=None) -> Dict:
     r = Result()

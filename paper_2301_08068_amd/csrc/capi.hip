@@ -76,20 +76,6 @@ rmpc::PolicyF policy_f(const rmpc_params *p, const double v[3])
     return P;
 }
 
-// Brick edge (log2) per axis for a storage type: about 128-256 bytes per brick.
-void brick_shape(int dtype, int lb[3])
-{
-    lb[0] = lb[1] = lb[2] = 2;                      // 4 x 4 x 4
-    if (dtype == RMPC_OCC_U8) lb[0] = 3;             // 8 x 4 x 4 bytes
-    if (const char *e = std::getenv("RMPC_BRICK_LOG2")) {
-        int a, b, c;
-        if (std::sscanf(e, "%d,%d,%d", &a, &b, &c) == 3 && a >= 0 && b >= 0 && c >= 0 &&
-            a <= 4 && b <= 4 && c <= 4) {
-            lb[0] = a; lb[1] = b; lb[2] = c;
-        }
-    }
-}
-
 size_t elem_bytes(int dtype) { return dtype == RMPC_TSDF_F32 ? 4 : (dtype == RMPC_TSDF_F16 ? 2 : 1); }
 
 // Index of cell (x, y) along a Hilbert curve filling an n x n grid (n a power of two).
@@ -387,20 +373,14 @@ rmpc_status rmpc_map_upload(rmpc_ctx *ctx, const rmpc_map_desc *desc, const void
         return fail(RMPC_E_INVALID, "voxel size or origin invalid");
     DeviceGuard dg(ctx->device);
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    int lb[3];
-    brick_shape(desc->dtype, lb);
     rmpc::MapView v;
     std::memset(&v, 0, sizeof v);
     v.nx = desc->nx; v.ny = desc->ny; v.nz = desc->nz; v.dtype = desc->dtype;
-    v.lbx = lb[0]; v.lby = lb[1]; v.lbz = lb[2];
-    v.nbx = (desc->nx + (1 << lb[0]) - 1) >> lb[0];
-    v.nby = (desc->ny + (1 << lb[1]) - 1) >> lb[1];
-    v.nbz = (desc->nz + (1 << lb[2]) - 1) >> lb[2];
-    const uint64_t n_dst = (uint64_t)v.nbx * v.nby * v.nbz << (lb[0] + lb[1] + lb[2]);
+    const uint64_t n_log = (uint64_t)desc->nx * desc->ny * desc->nz;
     v.ncx = desc->nx >> rmpc::kCellLog2;
     v.ncy = desc->ny >> rmpc::kCellLog2;
     v.ncz = desc->nz >> rmpc::kCellLog2;
-    const uint64_t cell_base = (n_dst + 255) / 256 * 256;
+    const uint64_t cell_base = (n_log + 255) / 256 * 256;
     const uint64_t n_all = cell_base + (uint64_t)v.ncx * v.ncy * v.ncz;
     if (n_all >= (1ull << 32)) return fail(RMPC_E_INVALID, "grid too large for 32-bit voxel offsets");
     v.cell_base = (uint32_t)cell_base;
@@ -408,31 +388,14 @@ rmpc_status rmpc_map_upload(rmpc_ctx *ctx, const rmpc_map_desc *desc, const void
     size_t off;
     if (!ctx->alloc.alloc(n_all * eb, &off)) return fail(RMPC_E_NOMEM, "arena full (map)");
     v.data = ctx->arena + off;
-    const size_t n_log = (size_t)desc->nx * desc->ny * desc->nz;
-    const void *src = voxels;
-    size_t tmp_off = 0;
-    bool tmp = false;
-    if (!voxels_on_device) {
-        if (!ctx->alloc.alloc(n_log * eb, &tmp_off)) {
-            ctx->alloc.release(off);
-            return fail(RMPC_E_NOMEM, "arena full (upload staging)");
-        }
-        tmp = true;
-        hipError_t e = hipMemcpyAsync(ctx->arena + tmp_off, voxels, n_log * eb, hipMemcpyHostToDevice, s);
-        if (e != hipSuccess) {
-            ctx->alloc.release(off);
-            ctx->alloc.release(tmp_off);
-            return fail(RMPC_E_HIP, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
-        }
-        src = ctx->arena + tmp_off;
-    }
-    rmpc::LayoutArgs la{src, v, (int32_t)eb, n_dst};
-    hipError_t e = rmpc::launch_layout(la, s);
+    // the grid is stored as given (x-fastest); the cell summaries follow it
+    hipError_t e = hipMemcpyAsync(ctx->arena + off, voxels, n_log * eb,
+                                  voxels_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = rmpc::launch_cell_summary(rmpc::SummaryArgs{v}, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (tmp) ctx->alloc.release(tmp_off);
     if (e != hipSuccess) {
         ctx->alloc.release(off);
-        return fail(RMPC_E_HIP, std::string("map layout: ") + hipGetErrorString(e));
+        return fail(RMPC_E_HIP, std::string("map upload: ") + hipGetErrorString(e));
     }
     const int32_t id = ctx->next_map_id++;
     ctx->maps[id] = MapEntry{*desc, v, off};

@@ -56,8 +56,7 @@ __device__ __forceinline__ bool start_occupied(const RayArgs &A)
 {
     using VT = typename Voxel<DT>::T;
     const VT *vox = static_cast<const VT *>(A.map.data);
-    const uint32_t a = addr_x(A.map, A.v0[0]) + addr_y(A.map, A.v0[1]) + addr_z(A.map, A.v0[2]);
-    return Voxel<DT>::occ(vox[a]);
+    return Voxel<DT>::occ(vox[(uint32_t)A.lin0]);
 }
 
 // Segment boundary of a ray near t_nom: the first of 16 candidates t = t_nom + 0.05 c (voxel
@@ -89,30 +88,41 @@ __device__ __forceinline__ double face64(int B, float g, float r)
     return ((double)B - (double)g) / (double)r;
 }
 
-// Float32 parameter of the same face: the value every float32 comparison of the walk uses,
-// always formed from the face coordinate (never accumulated).
-__device__ __forceinline__ float face32(int B, float g, float ir)
-{
-    return ((float)B - g) * ir;
-}
-
-// The ray in the forms the walk uses.
+// The ray in the forms the walk uses.  Along each axis the walk only moves toward larger
+// s*coordinate (s = sign of r), so faces are kept as s*B: a step adds the level's edge, and
+// the float32 crossing parameter (s*B - s*g) * |1/r| has the same bits as (B - g) * (1/r).
 struct RayF {
     float gx, gy, gz;                 // start, grid units
     float rx, ry, rz;                 // direction
-    float irx, iry, irz;              // 1/r, +inf for r = 0
-    int px, py, pz;                   // 1 when r > 0: the face ahead of coordinate u is u + p
-    int sx, sy, sz;                   // step direction
+    float gsx, gsy, gsz;              // s*g
+    float arx, ary, arz;              // |1/r|, +inf for r = 0
 };
+
+__device__ __forceinline__ RayF make_ray(const RayArgs &A, float rx, float ry, float rz)
+{
+    RayF R;
+    R.gx = A.g[0]; R.gy = A.g[1]; R.gz = A.g[2];
+    R.rx = rx; R.ry = ry; R.rz = rz;
+    R.gsx = rx > 0.0f ? R.gx : -R.gx;
+    R.gsy = ry > 0.0f ? R.gy : -R.gy;
+    R.gsz = rz > 0.0f ? R.gz : -R.gz;
+    R.arx = rx != 0.0f ? fabsf(1.0f / rx) : kInf;
+    R.ary = ry != 0.0f ? fabsf(1.0f / ry) : kInf;
+    R.arz = rz != 0.0f ? fabsf(1.0f / rz) : kInf;
+    return R;
+}
 
 // One lane's walk through one segment of one ray.  The walk moves either voxel by voxel or,
 // while it is inside cells whose summary says "free", cell by cell (lg = kCellLog2): a cell's
 // faces are voxel faces, so both levels take their decisions on the same crossing
 // parameters and visit the cells in the order the voxel walk would.
 struct Walker {
-    int ux, uy, uz;                   // current voxel, or current cell at the cell level
     int lg;                           // 0: voxel level, kCellLog2: cell level
-    float Tx, Ty, Tz;                 // float32 parameters of the next faces at this level
+    float Bx, By, Bz;                 // s * coordinate of the face ahead (exact integers)
+    float Tx, Ty, Tz;                 // float32 parameters of those faces
+    float Lx, Ly, Lz;                 // past these s*B the walk has left the grid (or the whole cells)
+    uint32_t off;                     // element offset of the current voxel or cell
+    int dx, dy, dz;                   // offset change of one step along each axis
     float t_hi;                       // stop once the next crossing exceeds this (float32)
     float t_lo;                       // crossings at or beyond this get the float64 range test
     bool last;                        // the segment ending at max_range
@@ -130,38 +140,53 @@ struct Walker {
     int fx, fy, fz;                   // last voxel entered when ended (the hit voxel on a hit)
 };
 
-__device__ __forceinline__ uint32_t voxel_offset(const MapView &m, int x, int y, int z)
+// Start walking at voxel (lg = 0) or cell (lg = kCellLog2) (ux, uy, uz).
+__device__ __forceinline__ void enter_level(Walker &w, const RayF &R, const MapView &m, int lg, int ux, int uy,
+                                            int uz)
 {
-    return addr_x(m, x) + addr_y(m, y) + addr_z(m, z);
+    const float rx = R.rx, ry = R.ry, rz = R.rz;
+    const int px = rx > 0.0f, py = ry > 0.0f, pz = rz > 0.0f;
+    const bool cell = lg != 0;
+    w.lg = lg;
+    const int bx = (ux + px) << lg, by = (uy + py) << lg, bz = (uz + pz) << lg;
+    w.Bx = (float)(px ? bx : -bx);
+    w.By = (float)(py ? by : -by);
+    w.Bz = (float)(pz ? bz : -bz);
+    w.Tx = rx != 0.0f ? (w.Bx - R.gsx) * R.arx : kInf;
+    w.Ty = ry != 0.0f ? (w.By - R.gsy) * R.ary : kInf;
+    w.Tz = rz != 0.0f ? (w.Bz - R.gsz) * R.arz : kInf;
+    const int vnx = m.nx, vny = m.ny, vnz = m.nz, cnx = m.ncx, cny = m.ncy, cnz = m.ncz;
+    const uint32_t cell_base = m.cell_base;
+    const int nx = cell ? cnx : vnx, ny = cell ? cny : vny, nz = cell ? cnz : vnz;
+    w.Lx = px ? (float)(nx << lg) : 0.0f;
+    w.Ly = py ? (float)(ny << lg) : 0.0f;
+    w.Lz = pz ? (float)(nz << lg) : 0.0f;
+    w.off = (cell ? cell_base : 0u) + (uint32_t)ux + (uint32_t)nx * ((uint32_t)uy + (uint32_t)ny * (uint32_t)uz);
+    w.dx = px ? 1 : -1;
+    w.dy = py ? nx : -nx;
+    w.dz = pz ? nx * ny : -(nx * ny);
 }
 
-__device__ __forceinline__ uint32_t cell_offset(const MapView &m, int cx, int cy, int cz)
+// Integer coordinates (at the walk's level) of the position whose faces ahead are s*B.
+__device__ __forceinline__ void coords_of(const RayF &R, int lg, float Bx, float By, float Bz, int &x, int &y, int &z)
 {
-    return m.cell_base + (uint32_t)cx + __umul24((uint32_t)m.ncx, (uint32_t)cy + __umul24((uint32_t)m.ncy, (uint32_t)cz));
+    const int px = R.rx > 0.0f, py = R.ry > 0.0f, pz = R.rz > 0.0f;
+    x = ((int)fabsf(Bx) >> lg) - px;
+    y = ((int)fabsf(By) >> lg) - py;
+    z = ((int)fabsf(Bz) >> lg) - pz;
 }
 
-// Parameters of the next faces ahead of the current voxel or cell.
-__device__ __forceinline__ void set_faces(Walker &w, const RayF &R)
-{
-    const float gx = R.gx, gy = R.gy, gz = R.gz, irx = R.irx, iry = R.iry, irz = R.irz;
-    const int px = R.px, py = R.py, pz = R.pz;
-    w.Tx = R.rx != 0.0f ? face32((w.ux + px) << w.lg, gx, irx) : kInf;
-    w.Ty = R.ry != 0.0f ? face32((w.uy + py) << w.lg, gy, iry) : kInf;
-    w.Tz = R.rz != 0.0f ? face32((w.uz + pz) << w.lg, gz, irz) : kInf;
-}
-
-// Position before steps j+1 .. K-1 of a round were taken (2-bit axis codes; 3 = no move).
+// Faces ahead before steps j+1 .. K-1 of a round were taken (2-bit axis codes).
 template <int K>
-__device__ __forceinline__ void undo_after(uint32_t axes, int j, const RayF &R, int &x, int &y, int &z)
+__device__ __forceinline__ void undo_after(uint32_t axes, int j, float L, float &Bx, float &By, float &Bz)
 {
-    const int sx = R.sx, sy = R.sy, sz = R.sz;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         if (k > j) {
             const uint32_t ak = (axes >> (2 * k)) & 3u;
-            x -= ak == 0 ? sx : 0;
-            y -= ak == 1 ? sy : 0;
-            z -= ak == 2 ? sz : 0;
+            Bx -= ak == 0 ? L : 0.0f;
+            By -= ak == 1 ? L : 0.0f;
+            Bz -= ak == 2 ? L : 0.0f;
         }
     }
 }
@@ -169,10 +194,10 @@ __device__ __forceinline__ void undo_after(uint32_t axes, int j, const RayF &R, 
 // Does face F of axis b come before the crossing of face Ba of axis a in the merged crossing
 // order (a smaller parameter, or an equal one on a lower axis)?  Float32 decides outside the
 // guard band, float64 inside it.
-__device__ __forceinline__ bool crossed_first(int F, float gb, float rb, float irb, int b, float T32, int Ba,
-                                              float ga, float ra, int a, bool &tie)
+__device__ __forceinline__ bool crossed_first(int F, float gb, float rb, int b, float T32, int Ba, float ga,
+                                              float ra, int a, bool &tie)
 {
-    const float tf = face32(F, gb, irb);
+    const float tf = ((float)F - gb) * (1.0f / rb);
     const float band = 2e-5f + 1e-6f * fmaxf(fabsf(tf), T32);
     if (tf < T32 - band) return true;
     if (tf > T32 + band) return false;
@@ -184,8 +209,8 @@ __device__ __forceinline__ bool crossed_first(int F, float gb, float rb, float i
 // Coordinate along axis b (rb != 0) of the voxel the walk is in right after crossing face Ba
 // of axis a at float32 parameter T32, known to lie in [lo, lo + 7]: the float32 estimate
 // floor(g + T r), confirmed on the face behind it and the face ahead of it.
-__device__ __forceinline__ int entry_coord(int lo, float gb, float rb, float irb, int b, float T32, int Ba,
-                                           float ga, float ra, int a, bool &tie)
+__device__ __forceinline__ int entry_coord(int lo, float gb, float rb, int b, float T32, int Ba, float ga, float ra,
+                                           int a, bool &tie)
 {
     const int hi = lo + (1 << kCellLog2) - 1;
     int c = (int)floorf(fmaf(T32, rb, gb));
@@ -195,9 +220,9 @@ __device__ __forceinline__ int entry_coord(int lo, float gb, float rb, float irb
     const int f_out = up ? c + 1 : c;             // face out of voxel c, ahead
     const bool chk_in = up ? c > lo : c < hi;     // the cell's own face needs no check
     const bool chk_out = up ? c < hi : c > lo;
-    if (chk_in && !crossed_first(f_in, gb, rb, irb, b, T32, Ba, ga, ra, a, tie))
+    if (chk_in && !crossed_first(f_in, gb, rb, b, T32, Ba, ga, ra, a, tie))
         c += up ? -1 : 1;
-    else if (chk_out && crossed_first(f_out, gb, rb, irb, b, T32, Ba, ga, ra, a, tie))
+    else if (chk_out && crossed_first(f_out, gb, rb, b, T32, Ba, ga, ra, a, tie))
         c += up ? 1 : -1;
     return c;
 }
@@ -206,41 +231,38 @@ __device__ __forceinline__ int entry_coord(int lo, float gb, float rb, float irb
 __device__ __forceinline__ void cell_entry(const RayArgs &A, const RayF &R, int a, int cx, int cy, int cz,
                                            int &vx, int &vy, int &vz, bool &tie)
 {
-    const float gx = R.gx, gy = R.gy, gz = R.gz, rx = R.rx, ry = R.ry, rz = R.rz;
-    const float irx = R.irx, iry = R.iry, irz = R.irz;
-    const int px = R.px, py = R.py, pz = R.pz;
     constexpr int E = 1 << kCellLog2;
+    const float gx = R.gx, gy = R.gy, gz = R.gz, rx = R.rx, ry = R.ry, rz = R.rz;
+    const int px = rx > 0.0f, py = ry > 0.0f, pz = rz > 0.0f;
     const int lx = cx << kCellLog2, ly = cy << kCellLog2, lz = cz << kCellLog2;
     // the face crossed: the cell's low face when travelling up the axis, else its high face
     const int Ba = a == 0 ? (px ? lx : lx + E) : (a == 1 ? (py ? ly : ly + E) : (pz ? lz : lz + E));
     const float ga = a == 0 ? gx : (a == 1 ? gy : gz);
     const float ra = a == 0 ? rx : (a == 1 ? ry : rz);
-    const float ira = a == 0 ? irx : (a == 1 ? iry : irz);
-    const float T32 = face32(Ba, ga, ira);
-    vx = a == 0 ? (px ? lx : lx + E - 1)
-                : (rx != 0.0f ? entry_coord(lx, gx, rx, irx, 0, T32, Ba, ga, ra, a, tie) : A.v0[0]);
-    vy = a == 1 ? (py ? ly : ly + E - 1)
-                : (ry != 0.0f ? entry_coord(ly, gy, ry, iry, 1, T32, Ba, ga, ra, a, tie) : A.v0[1]);
-    vz = a == 2 ? (pz ? lz : lz + E - 1)
-                : (rz != 0.0f ? entry_coord(lz, gz, rz, irz, 2, T32, Ba, ga, ra, a, tie) : A.v0[2]);
+    const float T32 = ((float)Ba - ga) * (1.0f / ra);
+    vx = a == 0 ? (px ? lx : lx + E - 1) : (rx != 0.0f ? entry_coord(lx, gx, rx, 0, T32, Ba, ga, ra, a, tie) : A.v0[0]);
+    vy = a == 1 ? (py ? ly : ly + E - 1) : (ry != 0.0f ? entry_coord(ly, gy, ry, 1, T32, Ba, ga, ra, a, tie) : A.v0[1]);
+    vz = a == 2 ? (pz ? lz : lz + E - 1) : (rz != 0.0f ? entry_coord(lz, gz, rz, 2, T32, Ba, ga, ra, a, tie) : A.v0[2]);
 }
 
 // Continue the walk at the voxel level at voxel (vx, vy, vz).
-__device__ __forceinline__ void to_voxels(Walker &w, const RayF &R, int vx, int vy, int vz, bool pending, int ent_a)
+__device__ __forceinline__ void to_voxels(Walker &w, const RayF &R, const MapView &m, int vx, int vy, int vz,
+                                          bool pending, int ent_a)
 {
-    w.ux = vx; w.uy = vy; w.uz = vz;
-    w.lg = 0;
+    enter_level(w, R, m, 0, vx, vy, vz);
     w.pending = pending;
     w.ent_a = ent_a;
     w.anchored = false;
-    set_faces(w, R);
 }
 
 // Plan K steps at the current level, load what they enter, and act on the first occupied
-// voxel or cell.  Returns true while the walk goes on.  The steps have no branches: the axis
-// step is done with selects, each step's load is issued as soon as its address is known, and
-// steps past the end of the walk load a harmless address and are ignored.  Only the axis of
-// each step is kept (2 bits); earlier positions are recovered by undoing later steps.
+// voxel or cell.  Returns true while the walk goes on.  The planned steps have no branches:
+// the axis step is done with selects, each step's load is issued as soon as its offset is
+// known, and steps past the end of the plan load a harmless offset and are ignored.  A step
+// whose decision needs float64 (two crossings inside the guard band, or a crossing near
+// max_range) ends the plan; once the round's loads are checked, that step is taken exactly
+// and what it enters is read at the start of the next round.  Only the axis of each planned
+// step is kept (2 bits); earlier positions are recovered by undoing later steps.
 //   voxel level: an occupied voxel is the hit; a round that ends inside a free cell moves the
 //     walk to the cell level.
 //   cell level: an occupied cell is entered at the voxel level (its entry voxel found from the
@@ -250,151 +272,218 @@ template <int DT, int K, bool DEBUG>
 __device__ __forceinline__ bool walk_round(const RayArgs &A, Walker &w, const RayF &R, uint32_t safe_v,
                                            uint32_t safe_c)
 {
-    const float gx = R.gx, gy = R.gy, gz = R.gz, rx = R.rx, ry = R.ry, rz = R.rz;
-    const float irx = R.irx, iry = R.iry, irz = R.irz;
-    const int px = R.px, py = R.py, pz = R.pz, sx = R.sx, sy = R.sy, sz = R.sz;
     using VT = typename Voxel<DT>::T;
     const MapView &m = A.map;
     const VT *vox = static_cast<const VT *>(m.data);
+    const float gx = R.gx, gy = R.gy, gz = R.gz, rx = R.rx, ry = R.ry, rz = R.rz;
+    const float gsx = R.gsx, gsy = R.gsy, gsz = R.gsz, arx = R.arx, ary = R.ary, arz = R.arz;
     const bool cell = w.lg != 0;
-    const int lg = w.lg;
-    const int lim_x = cell ? m.ncx : m.nx, lim_y = cell ? m.ncy : m.ny, lim_z = cell ? m.ncz : m.nz;
+    const float L = cell ? (float)(1 << kCellLog2) : 1.0f;
+    const uint32_t safe = cell ? safe_c : safe_v;
+    // the round works on copies (selects between registers, never between fields)
+    float Bx = w.Bx, By = w.By, Bz = w.Bz, Tx = w.Tx, Ty = w.Ty, Tz = w.Tz;
+    uint32_t off = w.off;
+    const int dx = w.dx, dy = w.dy, dz = w.dz;
+    const float Lx = w.Lx, Ly = w.Ly, Lz = w.Lz, t_hi = w.t_hi, t_lo = w.t_lo;
+    // what the previous round's exact step entered is read first
+    const VT pv = vox[w.pending ? off : safe];
     VT val[K];
     uint32_t axes = 0;                // 2 bits per planned step
     int nplan = 0;
-    bool going = true;                // no termination yet in this round
+    bool going = true;                // the plan goes on
     bool exited = false;              // the walk left the grid (voxels) or the whole cells (cells)
+    bool hard = false;                // the plan ended at a step that needs float64
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        const bool null_step = k == 0 && w.pending;      // read the current voxel, do not move
         // nearest and second-nearest crossings (no NaNs occur: +inf marks an axis never crossed)
-        const float t1 = __builtin_amdgcn_fmed3f(w.Tx, fminf(w.Ty, w.Tz), -kInf);
-        const float t2 = __builtin_amdgcn_fmed3f(w.Tx, w.Ty, w.Tz);
-        int a = w.Tx == t1 ? 0 : (w.Ty == t1 ? 1 : 2);
+        const float t1 = __builtin_amdgcn_fmed3f(Tx, fminf(Ty, Tz), -kInf);
+        const float t2 = __builtin_amdgcn_fmed3f(Tx, Ty, Tz);
+        // (bitwise operators: no short-circuit branches in the plan)
+        const bool bx = Tx == t1, by = !bx & (Ty == t1), bz = !bx & !by;
+        const bool near_end = t1 >= t_lo;
+        const bool stop = (t1 > t_hi) | (cell & near_end);    // cells: finish near max_range at the voxel level
+        const bool need64 = (t2 - t1 < 2e-5f + 1e-6f * t2) | (!cell & near_end);
+        Bx = bx ? Bx + L : Bx;
+        By = by ? By + L : By;
+        Bz = bz ? Bz + L : Bz;
+        Tx = bx ? (Bx - gsx) * arx : Tx;
+        Ty = by ? (By - gsy) * ary : Ty;
+        Tz = bz ? (Bz - gsz) * arz : Tz;
+        off += (uint32_t)(bx ? dx : (by ? dy : dz));
+        const bool inside = (Bx <= Lx) & (By <= Ly) & (Bz <= Lz);
+        const bool live = going & !stop;
+        hard = hard | (live & need64);
+        exited = exited | (live & !need64 & !inside);
+        going = live & !need64 & inside;
+        val[k] = vox[going ? off : safe];
+        axes |= (uint32_t)(bx ? 0 : (by ? 1 : 2)) << (2 * k);
+        nplan += going ? 1 : 0;
+    }
+    int hk = -1;
+#pragma unroll
+    for (int k = K - 1; k >= 0; --k)
+        if (k < nplan && Voxel<DT>::occ(val[k])) hk = k;
+    const int steps = w.steps;
+
+    // (a) the voxel or cell entered by the previous round's exact step
+    if (w.pending && Voxel<DT>::occ(pv)) {
+        int ux, uy, uz;
+        coords_of(R, w.lg, w.Bx, w.By, w.Bz, ux, uy, uz);
+        const int a = w.ent_a;
+        if (!cell) {
+            const double T64 = a == 0 ? entry64(ux, gx, rx) : (a == 1 ? entry64(uy, gy, ry) : entry64(uz, gz, rz));
+            w.d = T64 * A.h;
+            w.fx = ux; w.fy = uy; w.fz = uz;
+            w.hit = w.ended = true;
+            w.hit_step = steps - 1;
+            return false;
+        }
+        int vx, vy, vz;
         bool tie = false;
-        if (going && !null_step && t2 - t1 < 2e-5f + 1e-6f * t2) {
-            // decide in float64 exactly as the definition does
-            const double X = rx != 0.0f ? face64((w.ux + px) << lg, gx, rx) : __builtin_huge_val();
-            const double Y = ry != 0.0f ? face64((w.uy + py) << lg, gy, ry) : __builtin_huge_val();
-            const double Z = rz != 0.0f ? face64((w.uz + pz) << lg, gz, rz) : __builtin_huge_val();
+        cell_entry(A, R, a, ux, uy, uz, vx, vy, vz, tie);
+        if (tie) w.tie_at = min(w.tie_at, steps - 1);
+        to_voxels(w, R, m, vx, vy, vz, true, a);
+        return true;
+    }
+    w.pending = false;
+
+    // (b) the first occupied voxel or cell among the planned steps
+    if (hk >= 0) {
+        float hBx = Bx, hBy = By, hBz = Bz;
+        undo_after<K>(axes, hk, L, hBx, hBy, hBz);
+        int ux, uy, uz;
+        coords_of(R, w.lg, hBx, hBy, hBz, ux, uy, uz);
+        const int a = (int)((axes >> (2 * hk)) & 3u);
+        if (!cell) {
+            const double T64 = a == 0 ? entry64(ux, gx, rx) : (a == 1 ? entry64(uy, gy, ry) : entry64(uz, gz, rz));
+            w.d = T64 * A.h;
+            w.fx = ux; w.fy = uy; w.fz = uz;
+            w.hit = w.ended = true;
+            w.hit_step = steps + hk;
+            w.steps = steps + hk + 1;
+            return false;
+        }
+        int vx, vy, vz;
+        bool tie = false;
+        cell_entry(A, R, a, ux, uy, uz, vx, vy, vz, tie);
+        if (tie) w.tie_at = min(w.tie_at, steps + hk);
+        w.steps = steps + hk + 1;
+        to_voxels(w, R, m, vx, vy, vz, true, a);
+        return true;
+    }
+
+    // (c) a full round: continue, at the cell level if the walk is inside a free cell
+    if (nplan == K) {
+        w.Bx = Bx; w.By = By; w.Bz = Bz; w.Tx = Tx; w.Ty = Ty; w.Tz = Tz;
+        w.off = off;
+        w.steps = steps + K;
+        if (cell) {
+            w.anchored = false;
+            w.ent_a = (int)((axes >> (2 * (K - 1))) & 3u);
+            return true;
+        }
+        int ux, uy, uz;
+        coords_of(R, 0, Bx, By, Bz, ux, uy, uz);
+        const int ccx = ux >> kCellLog2, ccy = uy >> kCellLog2, ccz = uz >> kCellLog2;
+        if (ccx < m.ncx && ccy < m.ncy && ccz < m.ncz &&
+            !Voxel<DT>::occ(vox[m.cell_base + (uint32_t)ccx + (uint32_t)m.ncx * ((uint32_t)ccy + (uint32_t)m.ncy * (uint32_t)ccz)])) {
+            enter_level(w, R, m, kCellLog2, ccx, ccy, ccz);
+            w.ax = ux; w.ay = uy; w.az = uz;
+            w.anchored = true;
+        }
+        return true;
+    }
+
+    // (d) the plan ended at step nplan: go back to the position after step nplan - 1
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        if (k >= nplan) {
+            const uint32_t ak = (axes >> (2 * k)) & 3u;
+            Bx -= ak == 0 ? L : 0.0f;
+            By -= ak == 1 ? L : 0.0f;
+            Bz -= ak == 2 ? L : 0.0f;
+            off -= (uint32_t)(ak == 0 ? dx : (ak == 1 ? dy : dz));
+        }
+    }
+    Tx = rx != 0.0f ? (Bx - gsx) * arx : kInf;
+    Ty = ry != 0.0f ? (By - gsy) * ary : kInf;
+    Tz = rz != 0.0f ? (Bz - gsz) * arz : kInf;
+    int tie_at = w.tie_at, rtie_at = w.rtie_at;
+    if (hard) {
+        // the step the plan stopped at, decided in float64 exactly as the definition does
+        const int at = steps + nplan;
+        const float t1 = __builtin_amdgcn_fmed3f(Tx, fminf(Ty, Tz), -kInf);
+        const float t2 = __builtin_amdgcn_fmed3f(Tx, Ty, Tz);
+        int a = Tx == t1 ? 0 : (Ty == t1 ? 1 : 2);
+        bool tie = false;
+        if (t2 - t1 < 2e-5f + 1e-6f * t2) {
+            const double X = rx != 0.0f ? face64((int)fabsf(Bx), gx, rx) : __builtin_huge_val();
+            const double Y = ry != 0.0f ? face64((int)fabsf(By), gy, ry) : __builtin_huge_val();
+            const double Z = rz != 0.0f ? face64((int)fabsf(Bz), gz, rz) : __builtin_huge_val();
             a = 0;
             double m1 = X;
             if (Y < m1) { a = 1; m1 = Y; }
             if (Z < m1) { a = 2; m1 = Z; }
             tie = (a != 0 && X - m1 < 1e-5) || (a != 1 && Y - m1 < 1e-5) || (a != 2 && Z - m1 < 1e-5);
         }
-        const bool bx = a == 0, by = a == 1, bz = a == 2;
-        const float ta = bx ? w.Tx : (by ? w.Ty : w.Tz);
-        bool stop = ta > w.t_hi;
-        if (cell) {
-            stop = stop || ta >= w.t_lo;                 // finish near max_range at the voxel level
-        } else if (going && !stop && !null_step && ta >= w.t_lo) {
+        // near-ties count at every voxel decision, at the cell level only on steps taken
+        if (tie && !cell) tie_at = min(tie_at, at);
+        const float ta = a == 0 ? Tx : (a == 1 ? Ty : Tz);
+        bool stop = ta > t_hi || (cell && ta >= t_lo);
+        if (!cell && !stop && ta >= t_lo) {
             // range test (closed interval) in float64 inside the guard band
-            const double T64 = bx ? face64(w.ux + px, gx, rx)
-                                  : (by ? face64(w.uy + py, gy, ry) : face64(w.uz + pz, gz, rz));
+            const double T64 = a == 0 ? face64((int)fabsf(Bx), gx, rx)
+                                      : (a == 1 ? face64((int)fabsf(By), gy, ry) : face64((int)fabsf(Bz), gz, rz));
             const double dist = T64 * A.h;
             stop = dist > A.max_range;
-            if (fabs(dist - A.max_range) < 1e-5 * A.h && w.rtie_at > w.steps + k) w.rtie_at = w.steps + k;
+            if (fabs(dist - A.max_range) < 1e-5 * A.h) rtie_at = min(rtie_at, at);
         }
-        stop = stop && !null_step;
-        const bool mx = bx && !null_step, my = by && !null_step, mz = bz && !null_step;
-        w.ux = mx ? w.ux + sx : w.ux;
-        w.uy = my ? w.uy + sy : w.uy;
-        w.uz = mz ? w.uz + sz : w.uz;
-        w.Tx = mx ? face32((w.ux + px) << lg, gx, irx) : w.Tx;
-        w.Ty = my ? face32((w.uy + py) << lg, gy, iry) : w.Ty;
-        w.Tz = mz ? face32((w.uz + pz) << lg, gz, irz) : w.Tz;
-        const bool inside = (unsigned)w.ux < (unsigned)lim_x && (unsigned)w.uy < (unsigned)lim_y &&
-                            (unsigned)w.uz < (unsigned)lim_z;
-        exited = exited || (going && !stop && !inside);
-        // a near-tie counts at every voxel decision, but at the cell level only on steps taken
-        // (the voxel walk makes the others itself)
-        if (tie && (!cell || (!stop && inside)) && w.tie_at > w.steps + k) w.tie_at = w.steps + k;
-        going = going && !stop && inside;
-        const uint32_t off = cell ? cell_offset(m, w.ux, w.uy, w.uz) : voxel_offset(m, w.ux, w.uy, w.uz);
-        val[k] = vox[going ? off : (cell ? safe_c : safe_v)];
-        axes |= (uint32_t)(null_step ? 3 : a) << (2 * k);
-        nplan += going ? 1 : 0;
-    }
-    // voxel level: the summary of the cell the walk is in after a full round
-    const int ccx = w.ux >> kCellLog2, ccy = w.uy >> kCellLog2, ccz = w.uz >> kCellLog2;
-    const bool cin = !cell && going && ccx < m.ncx && ccy < m.ncy && ccz < m.ncz;
-    const VT cf = vox[cin ? cell_offset(m, ccx, ccy, ccz) : safe_c];
-    int hk = -1;
-#pragma unroll
-    for (int k = K - 1; k >= 0; --k)
-        if (k < nplan && Voxel<DT>::occ(val[k])) hk = k;
-    w.pending = false;
-    if (!cell) {
-        if (hk >= 0) {
-            int hx = w.ux, hy = w.uy, hz = w.uz;
-            undo_after<K>(axes, hk, R, hx, hy, hz);
-            uint32_t ah = (axes >> (2 * hk)) & 3u;
-            if (ah == 3u) ah = (uint32_t)w.ent_a;
-            const double T64 = ah == 0 ? entry64(hx, gx, rx) : (ah == 1 ? entry64(hy, gy, ry) : entry64(hz, gz, rz));
-            w.d = T64 * A.h;
-            w.fx = hx; w.fy = hy; w.fz = hz;
-            w.hit = w.ended = true;
-            w.hit_step = w.steps + hk;
-            w.steps += hk + 1;
-            return false;
-        }
-        if (nplan < K) {
-            w.steps += nplan;
-            if (w.last || exited) {
-                int fx = w.ux, fy = w.uy, fz = w.uz;
-                undo_after<K>(axes, nplan - 1, R, fx, fy, fz);   // the last voxel entered
-                w.fx = fx; w.fy = fy; w.fz = fz;
-                w.ended = true;
+        if (!stop) {
+            const float nBx = a == 0 ? Bx + L : Bx, nBy = a == 1 ? By + L : By, nBz = a == 2 ? Bz + L : Bz;
+            if (nBx <= Lx && nBy <= Ly && nBz <= Lz) {
+                // take it; the next round reads what it enters
+                if (tie && cell) tie_at = min(tie_at, at);
+                w.Bx = nBx; w.By = nBy; w.Bz = nBz;
+                w.Tx = a == 0 && rx != 0.0f ? (nBx - gsx) * arx : Tx;
+                w.Ty = a == 1 && ry != 0.0f ? (nBy - gsy) * ary : Ty;
+                w.Tz = a == 2 && rz != 0.0f ? (nBz - gsz) * arz : Tz;
+                w.off = off + (uint32_t)(a == 0 ? dx : (a == 1 ? dy : dz));
+                w.tie_at = tie_at;
+                w.rtie_at = rtie_at;
+                w.pending = true;
+                w.ent_a = a;
+                w.anchored = false;
+                w.steps = at + 1;
+                return true;
             }
-            return false;
+            exited = true;
         }
-        w.steps += K;
-        if (cin && !Voxel<DT>::occ(cf)) {
-            w.ax = w.ux; w.ay = w.uy; w.az = w.uz;
-            w.anchored = true;
-            w.ux = ccx; w.uy = ccy; w.uz = ccz;
-            w.lg = kCellLog2;
-            set_faces(w, R);
-        }
-        return true;
     }
-    // cell level
-    if (hk >= 0) {
-        int cx = w.ux, cy = w.uy, cz = w.uz;
-        undo_after<K>(axes, hk, R, cx, cy, cz);
-        const int a = (int)((axes >> (2 * hk)) & 3u);
-        int vx, vy, vz;
+    // (e) the walk stops in this segment after step nplan - 1 (max_range, segment end, or the
+    // edge of the grid or of the whole cells)
+    w.tie_at = tie_at;
+    w.rtie_at = rtie_at;
+    w.steps = steps + nplan;
+    if (!cell) {
+        if (w.last || exited) {
+            coords_of(R, 0, Bx, By, Bz, w.fx, w.fy, w.fz);        // the last voxel entered
+            w.ended = true;
+        }
+        return false;
+    }
+    if (!w.last && !exited) return false;                // the segment ends inside a free cell
+    // finish the current (free) cell voxel by voxel
+    int vx, vy, vz;
+    if (nplan == 0 && w.anchored) {
+        vx = w.ax; vy = w.ay; vz = w.az;
+    } else {
+        int cx, cy, cz;
+        coords_of(R, kCellLog2, Bx, By, Bz, cx, cy, cz);
+        const int a = nplan > 0 ? (int)((axes >> (2 * (nplan - 1))) & 3u) : w.ent_a;
         bool tie = false;
         cell_entry(A, R, a, cx, cy, cz, vx, vy, vz, tie);
-        // near-ties seen on cell steps past hk lie beyond the entry into this cell: forget them
-        // (the voxel steps that follow reuse those decision indices)
-        if (w.tie_at > w.steps + hk) w.tie_at = 1 << 30;
-        if (tie) w.tie_at = min(w.tie_at, w.steps + hk);
-        w.steps += hk + 1;
-        to_voxels(w, R, vx, vy, vz, true, a);
-        return true;
     }
-    if (nplan < K) {
-        w.steps += nplan;
-        if (!w.last && !exited) return false;            // the segment ends inside a free cell
-        // finish the current (free) cell voxel by voxel
-        int vx, vy, vz;
-        if (nplan == 0 && w.anchored) {
-            vx = w.ax; vy = w.ay; vz = w.az;
-        } else {
-            int cx = w.ux, cy = w.uy, cz = w.uz;
-            undo_after<K>(axes, nplan - 1, R, cx, cy, cz);
-            const int a = nplan > 0 ? (int)((axes >> (2 * (nplan - 1))) & 3u) : w.ent_a;
-            bool tie = false;
-            cell_entry(A, R, a, cx, cy, cz, vx, vy, vz, tie);
-        }
-        to_voxels(w, R, vx, vy, vz, false, 0);
-        return true;
-    }
-    w.anchored = false;
-    w.ent_a = (int)((axes >> (2 * (K - 1))) & 3u);
-    w.steps += K;
+    to_voxels(w, R, m, vx, vy, vz, false, 0);
     return true;
 }
 
@@ -415,17 +504,9 @@ __device__ __forceinline__ RayOut trace_group(const RayArgs &A, bool valid, int 
 {
     using VT = typename Voxel<DT>::T;
     const MapView &m = A.map;
-    RayF R;
-    R.gx = A.g[0]; R.gy = A.g[1]; R.gz = A.g[2];
-    R.rx = rx; R.ry = ry; R.rz = rz;
-    R.irx = rx != 0.0f ? 1.0f / rx : kInf;
-    R.iry = ry != 0.0f ? 1.0f / ry : kInf;
-    R.irz = rz != 0.0f ? 1.0f / rz : kInf;
-    R.px = rx > 0.0f; R.py = ry > 0.0f; R.pz = rz > 0.0f;
-    R.sx = R.px ? 1 : -1; R.sy = R.py ? 1 : -1; R.sz = R.pz ? 1 : -1;
+    const RayF R = make_ray(A, rx, ry, rz);
     const double tmax = A.tmax_v;
     Walker w;
-    w.lg = 0;
     w.pending = false;
     w.ent_a = 0;
     w.anchored = false;
@@ -439,15 +520,13 @@ __device__ __forceinline__ RayOut trace_group(const RayArgs &A, bool valid, int 
     w.fx = w.fy = w.fz = 0;
     bool active = valid;
     // segment start
-    if (seg == 0) {
-        w.ux = A.v0[0]; w.uy = A.v0[1]; w.uz = A.v0[2];
-    } else {
+    int ux = A.v0[0], uy = A.v0[1], uz = A.v0[2];
+    if (seg != 0) {
         bool ok;
-        seg_boundary(tmax * seg / S, R.gx, R.gy, R.gz, rx, ry, rz, w.ux, w.uy, w.uz, ok);
-        if (!ok || (unsigned)w.ux >= (unsigned)m.nx || (unsigned)w.uy >= (unsigned)m.ny ||
-            (unsigned)w.uz >= (unsigned)m.nz) {
+        seg_boundary(tmax * seg / S, R.gx, R.gy, R.gz, rx, ry, rz, ux, uy, uz, ok);
+        if (!ok || (unsigned)ux >= (unsigned)m.nx || (unsigned)uy >= (unsigned)m.ny || (unsigned)uz >= (unsigned)m.nz) {
             active = false;                               // empty segment (or past the grid)
-            w.ux = A.v0[0]; w.uy = A.v0[1]; w.uz = A.v0[2];
+            ux = A.v0[0]; uy = A.v0[1]; uz = A.v0[2];
         }
     }
     // segment end: the next boundary that exists, else max_range
@@ -455,30 +534,30 @@ __device__ __forceinline__ RayOut trace_group(const RayArgs &A, bool valid, int 
     w.t_hi = A.tmax_hi;
     w.t_lo = A.tmax_lo;
     for (int e = seg + 1; e < S && w.last; ++e) {
-        int ux, uy, uz;
+        int bx, by, bz;
         bool ok;
-        const double te = seg_boundary(tmax * e / S, R.gx, R.gy, R.gz, rx, ry, rz, ux, uy, uz, ok);
+        const double te = seg_boundary(tmax * e / S, R.gx, R.gy, R.gz, rx, ry, rz, bx, by, bz, ok);
         if (ok) {
             w.last = false;
             w.t_hi = (float)te;       // no crossing lies within kSegMargin of te
             w.t_lo = kInf;
         }
     }
-    set_faces(w, R);
-    const uint32_t safe_v = voxel_offset(m, A.v0[0], A.v0[1], A.v0[2]);
+    const uint32_t safe_v = A.lin0;
     const uint32_t safe_c = m.ncx > 0 && m.ncy > 0 && m.ncz > 0 ? m.cell_base : safe_v;
     {
         // start at the cell level when the start voxel's cell is free
         const VT *vox = static_cast<const VT *>(m.data);
-        const int cx = w.ux >> kCellLog2, cy = w.uy >> kCellLog2, cz = w.uz >> kCellLog2;
+        const int cx = ux >> kCellLog2, cy = uy >> kCellLog2, cz = uz >> kCellLog2;
         const bool cin = active && cx < m.ncx && cy < m.ncy && cz < m.ncz;
-        const VT cf = vox[cin ? cell_offset(m, cx, cy, cz) : safe_c];
+        const VT cf = vox[cin ? m.cell_base + (uint32_t)cx + (uint32_t)m.ncx * ((uint32_t)cy + (uint32_t)m.ncy * (uint32_t)cz)
+                              : safe_c];
         if (cin && !Voxel<DT>::occ(cf)) {
-            w.ax = w.ux; w.ay = w.uy; w.az = w.uz;
+            enter_level(w, R, m, kCellLog2, cx, cy, cz);
+            w.ax = ux; w.ay = uy; w.az = uz;
             w.anchored = true;
-            w.ux = cx; w.uy = cy; w.uz = cz;
-            w.lg = kCellLog2;
-            set_faces(w, R);
+        } else {
+            enter_level(w, R, m, 0, ux, uy, uz);
         }
     }
 

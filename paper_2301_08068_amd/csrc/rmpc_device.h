@@ -22,24 +22,6 @@ constexpr uint32_t kRayRangeTie = RMPC_RAY_RANGE_TIE;
 constexpr uint32_t kRayStartFace = RMPC_RAY_START_FACE;
 constexpr uint32_t kRayInCollision = RMPC_RAY_IN_COLLISION;
 
-// Per-axis parts of a voxel's element offset.  Brick counts per row and per plane are below
-// 2^24 for every grid the library accepts, so 24-bit multiplies (full rate) are exact; the
-// host guarantees the total offset fits 32 bits.
-__device__ __forceinline__ uint32_t addr_x(const MapView &m, int x)
-{
-    return ((uint32_t)(x >> m.lbx) << (m.lbx + m.lby + m.lbz)) + (uint32_t)(x & ((1 << m.lbx) - 1));
-}
-__device__ __forceinline__ uint32_t addr_y(const MapView &m, int y)
-{
-    return (__umul24((uint32_t)(y >> m.lby), (uint32_t)m.nbx) << (m.lbx + m.lby + m.lbz)) +
-           ((uint32_t)(y & ((1 << m.lby) - 1)) << m.lbx);
-}
-__device__ __forceinline__ uint32_t addr_z(const MapView &m, int z)
-{
-    return (__umul24((uint32_t)(z >> m.lbz), (uint32_t)(m.nbx * m.nby)) << (m.lbx + m.lby + m.lbz)) +
-           ((uint32_t)(z & ((1 << m.lbz) - 1)) << (m.lbx + m.lby));
-}
-
 // Occupancy of a stored value: TSDF <= 0 (NaN is free), occupancy byte != 0.
 template <int DT> struct Voxel;
 template <> struct Voxel<RMPC_TSDF_F32> {

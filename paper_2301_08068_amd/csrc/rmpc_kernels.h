@@ -23,20 +23,13 @@ constexpr int kMaxPartialSlots = 4096;
 // Words of one block partial in device memory: 18 floats + 4 integers, padded.
 constexpr int kPartialWords = 32;
 
-// A resident map in brick layout.  Voxel (x, y, z) lives in brick
-// (x >> lbx, y >> lby, z >> lbz); bricks are stored x-fastest and voxels inside a brick
-// too, so a voxel's element offset is X(x) + Y(y) + Z(z), each term a function of one
-// coordinate only.
-//
-// After the bricks (at element offset cell_base) the map holds one summary element per cell
-// of 8 x 8 x 8 voxels, x-fastest: "occupied" when any voxel of the cell is, "free" when none
-// is.  Only whole cells inside the grid have a summary (ncx = nx / 8 etc.); the walk skips
-// free cells whole.
+// A resident map: the voxel grid x-fastest (element offset x + nx (y + ny z)), then, at
+// element offset cell_base, one summary element per cell of 8 x 8 x 8 voxels, also x-fastest:
+// "occupied" when any voxel of the cell is, "free" when none is.  Only whole cells inside the
+// grid have a summary (ncx = nx / 8 etc.); the walk skips free cells whole.
 struct MapView {
     const void *data;
     int32_t nx, ny, nz, dtype;
-    int32_t lbx, lby, lbz;       // log2 of the brick edge along each axis
-    int32_t nbx, nby, nbz;       // bricks along each axis
     uint32_t cell_base;          // element offset of the cell summaries
     int32_t ncx, ncy, ncz;       // whole cells along each axis
 };
@@ -147,11 +140,8 @@ struct CompactArgs {
     int32_t *out;                // n entries
 };
 
-struct LayoutArgs {
-    const void *src;             // logical x-fastest grid
-    MapView dst;                 // brick layout (data is the destination)
-    int32_t elem_bytes;
-    uint64_t n_dst;              // elements in the padded brick array
+struct SummaryArgs {
+    MapView map;                 // grid in place; summaries are written at cell_base
 };
 
 int ray_grid_blocks(int n_rays);
@@ -163,7 +153,7 @@ hipError_t launch_raycast(const RayArgs &a, hipStream_t s, bool debug, hipEvent_
 hipError_t launch_scan(const ScanArgs &a, hipStream_t s, hipEvent_t ev0 = nullptr,
                        hipEvent_t ev1 = nullptr);
 hipError_t launch_directions(const DirsArgs &a, hipStream_t s);
-hipError_t launch_layout(const LayoutArgs &a, hipStream_t s);
+hipError_t launch_cell_summary(const SummaryArgs &a, hipStream_t s);
 hipError_t launch_compact(const CompactArgs &a, hipStream_t s);
 // Persistent fused batch: `blocks` resident blocks pull tiles from a counter.
 hipError_t launch_batch(const BatchArgs &a, int blocks, int lookahead, hipStream_t s);

@@ -1,5 +1,5 @@
-// setup_kernels.hip -- one-time device work: the Halton ray-direction table and the
-// re-layout of an uploaded voxel grid into bricks.
+// setup_kernels.hip -- one-time device work: the Halton ray-direction table, the ordered ray
+// lists and the free-cell summaries of an uploaded voxel grid.
 
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -43,33 +43,8 @@ __global__ void directions_kernel(DirsArgs A)
     A.out[i + 2 * A.n] = (float)z;
 }
 
-// Fill the padded brick array from the logical x-fastest grid; padding holds a free value.
-template <typename T>
-__global__ void layout_kernel(LayoutArgs A, T pad)
-{
-    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= A.n_dst) return;
-    const MapView &m = A.dst;
-    const int lbv = m.lbx + m.lby + m.lbz;
-    const uint64_t brick = e >> lbv;
-    const uint32_t off = (uint32_t)(e & ((1u << lbv) - 1));
-    const int lx = off & ((1 << m.lbx) - 1);
-    const int ly = (off >> m.lbx) & ((1 << m.lby) - 1);
-    const int lz = off >> (m.lbx + m.lby);
-    const uint64_t bx = brick % (uint64_t)m.nbx;
-    const uint64_t by = (brick / (uint64_t)m.nbx) % (uint64_t)m.nby;
-    const uint64_t bz = brick / ((uint64_t)m.nbx * (uint64_t)m.nby);
-    const int64_t x = (int64_t)(bx << m.lbx) + lx;
-    const int64_t y = (int64_t)(by << m.lby) + ly;
-    const int64_t z = (int64_t)(bz << m.lbz) + lz;
-    T v = pad;
-    if (x < m.nx && y < m.ny && z < m.nz)
-        v = static_cast<const T *>(A.src)[x + (int64_t)m.nx * (y + (int64_t)m.ny * z)];
-    static_cast<T *>(const_cast<void *>(m.data))[e] = v;
-}
-
 // Summary of cell c (8 x 8 x 8 voxels, whole cells only): the occupied value when any of
-// its voxels is occupied, else the free value, stored after the bricks.
+// its voxels is occupied, else the free value, stored after the grid.
 template <int DT>
 __global__ void cell_summary_kernel(MapView m, typename Voxel<DT>::T occ_val, typename Voxel<DT>::T free_val)
 {
@@ -83,7 +58,7 @@ __global__ void cell_summary_kernel(MapView m, typename Voxel<DT>::T occ_val, ty
     for (int k = 0; k < (1 << (3 * kCellLog2)) && !any; ++k) {
         const int x = (cx << kCellLog2) + (k & 7), y = (cy << kCellLog2) + ((k >> 3) & 7),
                   z = (cz << kCellLog2) + (k >> 6);
-        any = Voxel<DT>::occ(data[addr_x(m, x) + addr_y(m, y) + addr_z(m, z)]);
+        any = Voxel<DT>::occ(data[(uint32_t)x + (uint32_t)m.nx * ((uint32_t)y + (uint32_t)m.ny * (uint32_t)z)]);
     }
     data[m.cell_base + (uint32_t)c] = any ? occ_val : free_val;
 }
@@ -143,25 +118,17 @@ hipError_t launch_directions(const DirsArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_layout(const LayoutArgs &a, hipStream_t s)
+hipError_t launch_cell_summary(const SummaryArgs &a, hipStream_t s)
 {
-    const uint64_t blocks = (a.n_dst + 255) / 256;
-    const int n_cells = a.dst.ncx * a.dst.ncy * a.dst.ncz;
-    const unsigned cblocks = (unsigned)((n_cells + 255) / 256);
-    switch (a.dst.dtype) {
-    case RMPC_TSDF_F32:
-        layout_kernel<float><<<(unsigned)blocks, 256, 0, s>>>(a, 1.0f);
-        if (n_cells) cell_summary_kernel<RMPC_TSDF_F32><<<cblocks, 256, 0, s>>>(a.dst, -1.0f, 1.0f);
-        break;
+    const int n_cells = a.map.ncx * a.map.ncy * a.map.ncz;
+    if (n_cells == 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((n_cells + 255) / 256);
+    switch (a.map.dtype) {
+    case RMPC_TSDF_F32: cell_summary_kernel<RMPC_TSDF_F32><<<blocks, 256, 0, s>>>(a.map, -1.0f, 1.0f); break;
     case RMPC_TSDF_F16:
-        layout_kernel<uint16_t><<<(unsigned)blocks, 256, 0, s>>>(a, (uint16_t)0x3c00);
-        if (n_cells)
-            cell_summary_kernel<RMPC_TSDF_F16><<<cblocks, 256, 0, s>>>(a.dst, (uint16_t)0xbc00, (uint16_t)0x3c00);
+        cell_summary_kernel<RMPC_TSDF_F16><<<blocks, 256, 0, s>>>(a.map, (uint16_t)0xbc00, (uint16_t)0x3c00);
         break;
-    default:
-        layout_kernel<uint8_t><<<(unsigned)blocks, 256, 0, s>>>(a, (uint8_t)0);
-        if (n_cells) cell_summary_kernel<RMPC_OCC_U8><<<cblocks, 256, 0, s>>>(a.dst, (uint8_t)1, (uint8_t)0);
-        break;
+    default: cell_summary_kernel<RMPC_OCC_U8><<<blocks, 256, 0, s>>>(a.map, (uint8_t)1, (uint8_t)0); break;
     }
     return hipGetLastError();
 }
