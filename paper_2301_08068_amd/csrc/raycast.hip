@@ -129,6 +129,7 @@ struct Walker {
     bool pending;                     // voxel level: the current voxel is still to be read
     int ent_a;                        // axis across which the current voxel or cell was entered
     bool anchored;                    // cell level: (ax, ay, az) is a voxel of the walk in the cell
+    bool settled;                     // finishing the last cell voxel by voxel: no return to cells
     int ax, ay, az;
     int steps;                        // decisions taken so far (orders the near-tie records)
     int tie_at, rtie_at;              // first decision index with a (range) near-tie
@@ -319,6 +320,14 @@ __device__ __forceinline__ bool walk_round(const RayArgs &A, Walker &w, const Ra
         axes |= (uint32_t)(bx ? 0 : (by ? 1 : 2)) << (2 * k);
         nplan += going ? 1 : 0;
     }
+    // voxel level: the summary of the cell the walk is in after a full round (for the move to
+    // the cell level), loaded before the plan's values are examined
+    int ux, uy, uz;
+    coords_of(R, 0, Bx, By, Bz, ux, uy, uz);
+    const int ccx = ux >> kCellLog2, ccy = uy >> kCellLog2, ccz = uz >> kCellLog2;
+    const bool cin = !cell && going && ccx < m.ncx && ccy < m.ncy && ccz < m.ncz;
+    const VT cf = vox[cin ? m.cell_base + (uint32_t)ccx + (uint32_t)m.ncx * ((uint32_t)ccy + (uint32_t)m.ncy * (uint32_t)ccz)
+                          : safe_c];
     int hk = -1;
 #pragma unroll
     for (int k = K - 1; k >= 0; --k)
@@ -327,20 +336,20 @@ __device__ __forceinline__ bool walk_round(const RayArgs &A, Walker &w, const Ra
 
     // (a) the voxel or cell entered by the previous round's exact step
     if (w.pending && Voxel<DT>::occ(pv)) {
-        int ux, uy, uz;
-        coords_of(R, w.lg, w.Bx, w.By, w.Bz, ux, uy, uz);
+        int px_, py_, pz_;
+        coords_of(R, w.lg, w.Bx, w.By, w.Bz, px_, py_, pz_);
         const int a = w.ent_a;
         if (!cell) {
-            const double T64 = a == 0 ? entry64(ux, gx, rx) : (a == 1 ? entry64(uy, gy, ry) : entry64(uz, gz, rz));
+            const double T64 = a == 0 ? entry64(px_, gx, rx) : (a == 1 ? entry64(py_, gy, ry) : entry64(pz_, gz, rz));
             w.d = T64 * A.h;
-            w.fx = ux; w.fy = uy; w.fz = uz;
+            w.fx = px_; w.fy = py_; w.fz = pz_;
             w.hit = w.ended = true;
             w.hit_step = steps - 1;
             return false;
         }
         int vx, vy, vz;
         bool tie = false;
-        cell_entry(A, R, a, ux, uy, uz, vx, vy, vz, tie);
+        cell_entry(A, R, a, px_, py_, pz_, vx, vy, vz, tie);
         if (tie) w.tie_at = min(w.tie_at, steps - 1);
         to_voxels(w, R, m, vx, vy, vz, true, a);
         return true;
@@ -351,13 +360,13 @@ __device__ __forceinline__ bool walk_round(const RayArgs &A, Walker &w, const Ra
     if (hk >= 0) {
         float hBx = Bx, hBy = By, hBz = Bz;
         undo_after<K>(axes, hk, L, hBx, hBy, hBz);
-        int ux, uy, uz;
-        coords_of(R, w.lg, hBx, hBy, hBz, ux, uy, uz);
+        int hx, hy, hz;
+        coords_of(R, w.lg, hBx, hBy, hBz, hx, hy, hz);
         const int a = (int)((axes >> (2 * hk)) & 3u);
         if (!cell) {
-            const double T64 = a == 0 ? entry64(ux, gx, rx) : (a == 1 ? entry64(uy, gy, ry) : entry64(uz, gz, rz));
+            const double T64 = a == 0 ? entry64(hx, gx, rx) : (a == 1 ? entry64(hy, gy, ry) : entry64(hz, gz, rz));
             w.d = T64 * A.h;
-            w.fx = ux; w.fy = uy; w.fz = uz;
+            w.fx = hx; w.fy = hy; w.fz = hz;
             w.hit = w.ended = true;
             w.hit_step = steps + hk;
             w.steps = steps + hk + 1;
@@ -365,7 +374,7 @@ __device__ __forceinline__ bool walk_round(const RayArgs &A, Walker &w, const Ra
         }
         int vx, vy, vz;
         bool tie = false;
-        cell_entry(A, R, a, ux, uy, uz, vx, vy, vz, tie);
+        cell_entry(A, R, a, hx, hy, hz, vx, vy, vz, tie);
         if (tie) w.tie_at = min(w.tie_at, steps + hk);
         w.steps = steps + hk + 1;
         to_voxels(w, R, m, vx, vy, vz, true, a);
@@ -382,11 +391,7 @@ __device__ __forceinline__ bool walk_round(const RayArgs &A, Walker &w, const Ra
             w.ent_a = (int)((axes >> (2 * (K - 1))) & 3u);
             return true;
         }
-        int ux, uy, uz;
-        coords_of(R, 0, Bx, By, Bz, ux, uy, uz);
-        const int ccx = ux >> kCellLog2, ccy = uy >> kCellLog2, ccz = uz >> kCellLog2;
-        if (ccx < m.ncx && ccy < m.ncy && ccz < m.ncz &&
-            !Voxel<DT>::occ(vox[m.cell_base + (uint32_t)ccx + (uint32_t)m.ncx * ((uint32_t)ccy + (uint32_t)m.ncy * (uint32_t)ccz)])) {
+        if (cin && !w.settled && !Voxel<DT>::occ(cf)) {
             enter_level(w, R, m, kCellLog2, ccx, ccy, ccz);
             w.ax = ux; w.ay = uy; w.az = uz;
             w.anchored = true;
@@ -472,7 +477,9 @@ __device__ __forceinline__ bool walk_round(const RayArgs &A, Walker &w, const Ra
         return false;
     }
     if (!w.last && !exited) return false;                // the segment ends inside a free cell
-    // finish the current (free) cell voxel by voxel
+    // finish the current (free) cell voxel by voxel: the walk ends in it or just past it (max
+    // range, or the grid edge beyond the whole cells), so it stays at the voxel level
+    w.settled = true;
     int vx, vy, vz;
     if (nplan == 0 && w.anchored) {
         vx = w.ax; vy = w.ay; vz = w.az;
@@ -510,6 +517,7 @@ __device__ __forceinline__ RayOut trace_group(const RayArgs &A, bool valid, int 
     w.pending = false;
     w.ent_a = 0;
     w.anchored = false;
+    w.settled = false;
     w.ax = w.ay = w.az = 0;
     w.steps = 0;
     w.tie_at = w.rtie_at = 1 << 30;
@@ -519,6 +527,15 @@ __device__ __forceinline__ RayOut trace_group(const RayArgs &A, bool valid, int 
     w.d = __builtin_huge_val();
     w.fx = w.fy = w.fz = 0;
     bool active = valid;
+    const VT *vox = static_cast<const VT *>(m.data);
+    const uint32_t safe_v = A.lin0;
+    const uint32_t safe_c = m.ncx > 0 && m.ncy > 0 && m.ncz > 0 ? m.cell_base : safe_v;
+    // the summary of the start voxel's cell: the same for every segment-0 lane (issued now,
+    // while the segment bounds are computed); other segments load theirs below
+    const int c0x = A.v0[0] >> kCellLog2, c0y = A.v0[1] >> kCellLog2, c0z = A.v0[2] >> kCellLog2;
+    const bool c0in = c0x < m.ncx && c0y < m.ncy && c0z < m.ncz;
+    const VT cf0 = vox[c0in ? m.cell_base + (uint32_t)c0x + (uint32_t)m.ncx * ((uint32_t)c0y + (uint32_t)m.ncy * (uint32_t)c0z)
+                            : safe_c];
     // segment start
     int ux = A.v0[0], uy = A.v0[1], uz = A.v0[2];
     if (seg != 0) {
@@ -543,15 +560,15 @@ __device__ __forceinline__ RayOut trace_group(const RayArgs &A, bool valid, int 
             w.t_lo = kInf;
         }
     }
-    const uint32_t safe_v = A.lin0;
-    const uint32_t safe_c = m.ncx > 0 && m.ncy > 0 && m.ncz > 0 ? m.cell_base : safe_v;
     {
         // start at the cell level when the start voxel's cell is free
-        const VT *vox = static_cast<const VT *>(m.data);
         const int cx = ux >> kCellLog2, cy = uy >> kCellLog2, cz = uz >> kCellLog2;
         const bool cin = active && cx < m.ncx && cy < m.ncy && cz < m.ncz;
-        const VT cf = vox[cin ? m.cell_base + (uint32_t)cx + (uint32_t)m.ncx * ((uint32_t)cy + (uint32_t)m.ncy * (uint32_t)cz)
-                              : safe_c];
+        VT cf = cf0;
+        if (S > 1)
+            cf = vox[cin && seg != 0 ? m.cell_base + (uint32_t)cx + (uint32_t)m.ncx * ((uint32_t)cy + (uint32_t)m.ncy * (uint32_t)cz)
+                                     : safe_c];
+        if (seg == 0) cf = cf0;
         if (cin && !Voxel<DT>::occ(cf)) {
             enter_level(w, R, m, kCellLog2, cx, cy, cz);
             w.ax = ux; w.ay = uy; w.az = uz;
@@ -726,7 +743,8 @@ __device__ __forceinline__ FinishSlots single_slots(float *partials, uint32_t *t
 
 // One map query per launch; block b takes tile xcd_tile(b).
 template <int DT, int K>
-__global__ void __launch_bounds__(kBlock) raycast_rmp_kernel(RayArgs A)
+// 4 waves per SIMD keep every block of a 2^18-lane query resident at once
+__global__ void __launch_bounds__(kBlock, 4) raycast_rmp_kernel(RayArgs A)
 {
     __shared__ float lds[kReduceLdsWords];
     ray_tile<DT, K>(A, xcd_tile(blockIdx.x, gridDim.x), gridDim.x,
@@ -749,13 +767,16 @@ __global__ void __launch_bounds__(kBlock) batch_kernel(BatchArgs B)
         if (threadIdx.x == 0)
             s_tile = (int)__hip_atomic_fetch_add(B.work, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __syncthreads();
-        const int tile = s_tile;
+        // the tile and its query are the same for the whole block: keep them (and the query's
+        // descriptor loads) in scalar registers
+        const int tile = __builtin_amdgcn_readfirstlane(s_tile);
         if (tile >= n_tiles) break;
         int lo = 0, hi = n_queries - 1;      // last query with tile_begin <= tile
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
             if (B.q[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
         }
+        lo = __builtin_amdgcn_readfirstlane(lo);
         const BatchQuery &Q = B.q[lo];
         FinishSlots F;
         F.tile_rows = B.partials + (size_t)Q.tile_begin * kPartialWords;
@@ -787,7 +808,7 @@ __global__ void __launch_bounds__(kBlock) batch_kernel(BatchArgs B)
 }
 
 template <int DT, int K>
-__global__ void __launch_bounds__(kBlock) trace_debug_kernel(RayArgs A)
+__global__ void __launch_bounds__(kBlock, 4) trace_debug_kernel(RayArgs A)
 {
     const int S = A.segments;
     const int p = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
