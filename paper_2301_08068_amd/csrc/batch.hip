@@ -31,8 +31,8 @@ rmpc_status check_config(const rmpc_launch_config *c)
 rmpc_status slot_create(rmpc_ctx *ctx, LaunchSlot &slot, int max_queries, int max_tiles)
 {
     slot = LaunchSlot();
-    const size_t rows = (size_t)max_tiles + (size_t)rmpc::kGroups * max_queries;
-    const size_t tk_bytes = sizeof(uint32_t) * (rmpc::kGroups + 1) * (size_t)max_queries;
+    const size_t rows = (size_t)max_tiles;
+    const size_t tk_bytes = sizeof(uint32_t) * (size_t)max_queries;
     const size_t sizes[5] = {sizeof(rmpc::BatchHeader), sizeof(rmpc::BatchQuery) * (size_t)max_queries, 256,
                              tk_bytes, sizeof(float) * rmpc::kPartialWords * rows};
     size_t off[5];
@@ -133,7 +133,6 @@ rmpc_status slot_launch(rmpc_ctx *ctx, LaunchSlot &slot, int nq, int n_tiles,
     B.work = slot.work;
     B.tickets = slot.tickets;
     B.partials = slot.partials;
-    B.group_row_base = slot.max_tiles;
     B.results = slot.results_host;
     B.done = slot.done_host;
     hipStream_t s = slot.stream;

@@ -280,7 +280,7 @@ rmpc_status rmpc_create(int device, void *arena_dev, size_t arena_bytes, rmpc_ct
     if (!c->alloc.alloc(sizeof(float) * 3 * RMPC_MAX_RAYS, &o_dirs) ||
         !c->alloc.alloc(sizeof(int32_t) * RMPC_MAX_RAYS, &o_order) ||
         !c->alloc.alloc(sizeof(int32_t) * 1024, &o_counts) ||
-        !c->alloc.alloc(sizeof(float) * (rmpc::kMaxPartialSlots + 8) * 32, &o_part) ||
+        !c->alloc.alloc(sizeof(float) * rmpc::kMaxPartialSlots * rmpc::kPartialWords, &o_part) ||
         !c->alloc.alloc(256, &o_ticket)) {
         delete c;
         return fail(RMPC_E_NOMEM, "arena too small for the context tables");

@@ -195,10 +195,10 @@ __device__ __forceinline__ void undo_after(uint32_t axes, int j, float L, float 
 // Does face F of axis b come before the crossing of face Ba of axis a in the merged crossing
 // order (a smaller parameter, or an equal one on a lower axis)?  Float32 decides outside the
 // guard band, float64 inside it.
-__device__ __forceinline__ bool crossed_first(int F, float gb, float rb, int b, float T32, int Ba, float ga,
-                                              float ra, int a, bool &tie)
+__device__ __forceinline__ bool crossed_first(int F, float gb, float rb, float irb, int b, float T32, int Ba,
+                                              float ga, float ra, int a, bool &tie)
 {
-    const float tf = ((float)F - gb) * (1.0f / rb);
+    const float tf = ((float)F - gb) * irb;
     const float band = 2e-5f + 1e-6f * fmaxf(fabsf(tf), T32);
     if (tf < T32 - band) return true;
     if (tf > T32 + band) return false;
@@ -210,8 +210,8 @@ __device__ __forceinline__ bool crossed_first(int F, float gb, float rb, int b, 
 // Coordinate along axis b (rb != 0) of the voxel the walk is in right after crossing face Ba
 // of axis a at float32 parameter T32, known to lie in [lo, lo + 7]: the float32 estimate
 // floor(g + T r), confirmed on the face behind it and the face ahead of it.
-__device__ __forceinline__ int entry_coord(int lo, float gb, float rb, int b, float T32, int Ba, float ga, float ra,
-                                           int a, bool &tie)
+__device__ __forceinline__ int entry_coord(int lo, float gb, float rb, float irb, int b, float T32, int Ba, float ga,
+                                           float ra, int a, bool &tie)
 {
     const int hi = lo + (1 << kCellLog2) - 1;
     int c = (int)floorf(fmaf(T32, rb, gb));
@@ -221,9 +221,9 @@ __device__ __forceinline__ int entry_coord(int lo, float gb, float rb, int b, fl
     const int f_out = up ? c + 1 : c;             // face out of voxel c, ahead
     const bool chk_in = up ? c > lo : c < hi;     // the cell's own face needs no check
     const bool chk_out = up ? c < hi : c > lo;
-    if (chk_in && !crossed_first(f_in, gb, rb, b, T32, Ba, ga, ra, a, tie))
+    if (chk_in && !crossed_first(f_in, gb, rb, irb, b, T32, Ba, ga, ra, a, tie))
         c += up ? -1 : 1;
-    else if (chk_out && crossed_first(f_out, gb, rb, b, T32, Ba, ga, ra, a, tie))
+    else if (chk_out && crossed_first(f_out, gb, rb, irb, b, T32, Ba, ga, ra, a, tie))
         c += up ? 1 : -1;
     return c;
 }
@@ -235,15 +235,18 @@ __device__ __forceinline__ void cell_entry(const RayArgs &A, const RayF &R, int 
     constexpr int E = 1 << kCellLog2;
     const float gx = R.gx, gy = R.gy, gz = R.gz, rx = R.rx, ry = R.ry, rz = R.rz;
     const int px = rx > 0.0f, py = ry > 0.0f, pz = rz > 0.0f;
+    // 1/r with the bits of the walk's own reciprocal
+    const float irx = px ? R.arx : -R.arx, iry = py ? R.ary : -R.ary, irz = pz ? R.arz : -R.arz;
     const int lx = cx << kCellLog2, ly = cy << kCellLog2, lz = cz << kCellLog2;
     // the face crossed: the cell's low face when travelling up the axis, else its high face
     const int Ba = a == 0 ? (px ? lx : lx + E) : (a == 1 ? (py ? ly : ly + E) : (pz ? lz : lz + E));
     const float ga = a == 0 ? gx : (a == 1 ? gy : gz);
     const float ra = a == 0 ? rx : (a == 1 ? ry : rz);
-    const float T32 = ((float)Ba - ga) * (1.0f / ra);
-    vx = a == 0 ? (px ? lx : lx + E - 1) : (rx != 0.0f ? entry_coord(lx, gx, rx, 0, T32, Ba, ga, ra, a, tie) : A.v0[0]);
-    vy = a == 1 ? (py ? ly : ly + E - 1) : (ry != 0.0f ? entry_coord(ly, gy, ry, 1, T32, Ba, ga, ra, a, tie) : A.v0[1]);
-    vz = a == 2 ? (pz ? lz : lz + E - 1) : (rz != 0.0f ? entry_coord(lz, gz, rz, 2, T32, Ba, ga, ra, a, tie) : A.v0[2]);
+    const float ira = a == 0 ? irx : (a == 1 ? iry : irz);
+    const float T32 = ((float)Ba - ga) * ira;
+    vx = a == 0 ? (px ? lx : lx + E - 1) : (rx != 0.0f ? entry_coord(lx, gx, rx, irx, 0, T32, Ba, ga, ra, a, tie) : A.v0[0]);
+    vy = a == 1 ? (py ? ly : ly + E - 1) : (ry != 0.0f ? entry_coord(ly, gy, ry, iry, 1, T32, Ba, ga, ra, a, tie) : A.v0[1]);
+    vz = a == 2 ? (pz ? lz : lz + E - 1) : (rz != 0.0f ? entry_coord(lz, gz, rz, irz, 2, T32, Ba, ga, ra, a, tie) : A.v0[2]);
 }
 
 // Continue the walk at the voxel level at voxel (vx, vy, vz).
@@ -731,7 +734,6 @@ __device__ __forceinline__ FinishSlots single_slots(float *partials, uint32_t *t
 {
     FinishSlots F;
     F.tile_rows = partials;
-    F.group_rows = partials + (size_t)kMaxBlocks * kPartialWords;
     F.tickets = ticket;
     F.out = out;
     F.finished = nullptr;
@@ -780,8 +782,7 @@ __global__ void __launch_bounds__(kBlock) batch_kernel(BatchArgs B)
         const BatchQuery &Q = B.q[lo];
         FinishSlots F;
         F.tile_rows = B.partials + (size_t)Q.tile_begin * kPartialWords;
-        F.group_rows = B.partials + (size_t)(B.group_row_base + lo * kGroups) * kPartialWords;
-        F.tickets = B.tickets + lo * (kGroups + 1);
+        F.tickets = B.tickets + lo;
         F.out = B.results + lo;
         F.finished = B.work + 2;
         F.n_queries = n_queries;

@@ -338,12 +338,11 @@ __device__ __forceinline__ void acc_from_partial(const float *p, Acc &a)
     a.n_hit = q[0]; a.n_contrib = q[1]; a.n_tie = q[2]; a.visits = q[3];
 }
 
-// Where one reduction keeps its state: tile rows (one per tile), kGroups group rows, kGroups+1
-// tickets, the result slot, and the completion publication.  A batch shares `finished`
-// (queries done so far) among its queries and publishes once, when the last one is done.
+// Where one reduction keeps its state: tile rows (one per tile), a ticket, the result slot,
+// and the completion publication.  A batch shares `finished` (queries done so far) among its
+// queries and publishes once, when the last one is done.
 struct FinishSlots {
     float *tile_rows;
-    float *group_rows;
     uint32_t *tickets;
     rmpc_result *out;
     uint32_t *finished;          // null for a single query
@@ -352,55 +351,47 @@ struct FinishSlots {
     uint64_t seq;
 };
 
-// Finish tile b of nb.  Every tile stores its partial in row b; tiles form kGroups groups
-// (b % 8); the last tile of a group to arrive merges the group's rows into a group row, and
-// the last group merger merges the group rows and resolves.  Tickets are reset for the next
-// launch by the final merger.  Deterministic for a fixed tiling: every merge has a fixed
-// order.  All threads of the block call this and return together (except the final merger's
-// thread 0, which finishes alone).
+// Grid reduction: every block stores its total in its row and takes a ticket; the last block
+// merges all rows -- thread t takes rows t, t + 256, ... in that order, then the block tree
+// merges the threads -- so the result depends on the rows and their count only, never on the
+// order in which blocks finish.  It resolves, writes the result and publishes.
 __device__ inline void grid_finish(const Acc &a, int b, int nb, const FinishSlots &F,
                                    double rank_tol, int32_t n_rays, uint32_t extra_flags, float *lds)
 {
-    __shared__ int stage;                    // 0 done, 1 group merger, 2 final merger
+    __shared__ int last;
     __shared__ float tot[kPartialWords];
-    const int g = b % kGroups;
-    const int ngroups = nb < kGroups ? nb : kGroups;
-    const int in_group = (nb - g + kGroups - 1) / kGroups;
     block_reduce_store(a, lds, tot);
     __syncthreads();
-    if (threadIdx.x < kWave) {               // wave 0 stores the tile row, then takes a ticket
+    if (threadIdx.x < kWave) {               // wave 0 stores the row, then takes the ticket
         if (threadIdx.x < 22) F.tile_rows[(size_t)b * kPartialWords + threadIdx.x] = tot[threadIdx.x];
         __threadfence();
         if (threadIdx.x == 0) {
-            const uint32_t prev = __hip_atomic_fetch_add(F.tickets + g, 1u, __ATOMIC_ACQ_REL,
-                                                         __HIP_MEMORY_SCOPE_AGENT);
-            stage = prev == (uint32_t)(in_group - 1) ? 1 : 0;
+            const uint32_t prev = __hip_atomic_fetch_add(F.tickets, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            last = prev == (uint32_t)(nb - 1);
         }
     }
     __syncthreads();
-    if (stage == 0) return;
+    if (!last) return;
     __threadfence();
-    merge_partials(F.tile_rows + (size_t)g * kPartialWords, kGroups * kPartialWords, in_group, tot);
-    __syncthreads();
-    if (threadIdx.x < kWave) {
-        if (threadIdx.x < 22) F.group_rows[(size_t)g * kPartialWords + threadIdx.x] = tot[threadIdx.x];
-        __threadfence();
-        if (threadIdx.x == 0) {
-            const uint32_t prev = __hip_atomic_fetch_add(F.tickets + kGroups, 1u, __ATOMIC_ACQ_REL,
-                                                         __HIP_MEMORY_SCOPE_AGENT);
-            stage = prev == (uint32_t)(ngroups - 1) ? 2 : 0;
-        }
+    Acc m;
+    m.zero();
+    for (int r0 = threadIdx.x; r0 < nb; r0 += 2 * kBlock) {
+        // two rows per pass, both loaded before either is merged
+        Acc r1, r2;
+        acc_from_partial(F.tile_rows + (size_t)r0 * kPartialWords, r1);
+        const int s2 = r0 + kBlock;
+        if (s2 < nb) acc_from_partial(F.tile_rows + (size_t)s2 * kPartialWords, r2);
+        else r2.zero();
+        m.merge(r1);
+        if (s2 < nb) m.merge(r2);
     }
-    __syncthreads();
-    if (stage != 2) return;
-    __threadfence();
-    merge_partials(F.group_rows, kPartialWords, ngroups, tot);
+    __syncthreads();                         // lds and tot are reused
+    block_reduce_store(m, lds, tot);
     __syncthreads();
     if (threadIdx.x == 0) {
         Acc t;
         acc_from_partial(tot, t);
-        for (int k = 0; k <= kGroups; ++k)
-            __hip_atomic_store(F.tickets + k, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(F.tickets, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         finalize_result(t, rank_tol, n_rays, extra_flags, F.out);
         bool publish = true;
         if (F.finished) {

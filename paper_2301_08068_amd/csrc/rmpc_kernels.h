@@ -15,9 +15,6 @@ constexpr int kLookahead = 4;
 // Threads per block of the query kernels (one tile = this many lanes).
 constexpr int kBlockThreads = 256;
 
-// Reductions merge tile partials in this many groups (tiles t with t % 8 == g).
-constexpr int kGroups = 8;
-
 // Block-partial slots of one reduction (one per block of a launch).
 constexpr int kMaxPartialSlots = 4096;
 
@@ -117,9 +114,8 @@ struct BatchArgs {
     const BatchHeader *hdr;
     const BatchQuery *__restrict__ q;
     uint32_t *work;              // [0] next tile, [1] blocks exited, [2] queries finished
-    uint32_t *tickets;           // kGroups + 1 per query
-    float *partials;             // tile rows of all queries, then kGroups group rows per query
-    int32_t group_row_base;      // row index of the first group row
+    uint32_t *tickets;           // one per query
+    float *partials;             // tile rows of all queries
     rmpc_result *results;        // one per query (pinned host memory)
     uint64_t *done;              // completion word, set to hdr->seq when all queries are done
 };
