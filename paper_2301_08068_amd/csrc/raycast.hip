@@ -753,12 +753,27 @@ __global__ void __launch_bounds__(kBlock, 4) raycast_rmp_kernel(RayArgs A)
                     single_slots(A.partials, A.ticket, A.result, A.done, A.seq), lds);
 }
 
+// A copy of *p made of wave-uniform words (readfirstlane), so that the compiler keeps it in
+// scalar registers; p must be the same for every lane.
+template <typename T>
+__device__ __forceinline__ T load_uniform(const T *p)
+{
+    static_assert(sizeof(T) % 4 == 0, "whole words");
+    uint32_t w[sizeof(T) / 4];
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(p);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) w[i] = __builtin_amdgcn_readfirstlane(src[i]);
+    T out;
+    __builtin_memcpy(&out, w, sizeof(T));
+    return out;
+}
+
 // Many map and scan queries in one persistent launch: resident blocks take tiles from a
 // counter (work[0]) until none are left; tile rows, tickets and results are per query, so a
 // query's result does not depend on which block ran which tile.  The last block to leave
 // resets the counters for the next launch.
 template <int K>
-__global__ void __launch_bounds__(kBlock) batch_kernel(BatchArgs B)
+__global__ void __launch_bounds__(kBlock, 3) batch_kernel(BatchArgs B)
 {
     __shared__ float lds[kReduceLdsWords];
     __shared__ int s_tile;
@@ -779,24 +794,28 @@ __global__ void __launch_bounds__(kBlock) batch_kernel(BatchArgs B)
             if (B.q[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
         }
         lo = __builtin_amdgcn_readfirstlane(lo);
-        const BatchQuery &Q = B.q[lo];
+        const BatchQuery &Qm = B.q[lo];
+        const int q_tile_begin = Qm.tile_begin, q_n_tiles = Qm.n_tiles, q_kind = Qm.kind;
         FinishSlots F;
-        F.tile_rows = B.partials + (size_t)Q.tile_begin * kPartialWords;
+        F.tile_rows = B.partials + (size_t)q_tile_begin * kPartialWords;
         F.tickets = B.tickets + lo;
         F.out = B.results + lo;
         F.finished = B.work + 2;
         F.n_queries = n_queries;
         F.done = B.done;
         F.seq = B.hdr->seq;
-        const int t = tile - Q.tile_begin;
-        if (Q.kind == 0) {
-            switch (Q.ray.map.dtype) {
-            case RMPC_TSDF_F32: ray_tile<RMPC_TSDF_F32, K>(Q.ray, t, Q.n_tiles, F, lds); break;
-            case RMPC_TSDF_F16: ray_tile<RMPC_TSDF_F16, K>(Q.ray, t, Q.n_tiles, F, lds); break;
-            default: ray_tile<RMPC_OCC_U8, K>(Q.ray, t, Q.n_tiles, F, lds); break;
+        const int t = tile - q_tile_begin;
+        // the descriptor is the same for the whole block: copy it into scalar registers
+        if (q_kind == 0) {
+            const RayArgs A = load_uniform(&Qm.ray);
+            switch (A.map.dtype) {
+            case RMPC_TSDF_F32: ray_tile<RMPC_TSDF_F32, K>(A, t, q_n_tiles, F, lds); break;
+            case RMPC_TSDF_F16: ray_tile<RMPC_TSDF_F16, K>(A, t, q_n_tiles, F, lds); break;
+            default: ray_tile<RMPC_OCC_U8, K>(A, t, q_n_tiles, F, lds); break;
             }
         } else {
-            scan_tile(Q.scan, t, Q.n_tiles, F, lds);
+            const ScanArgs A = load_uniform(&Qm.scan);
+            scan_tile(A, t, q_n_tiles, F, lds);
         }
     }
     if (threadIdx.x == 0) {
