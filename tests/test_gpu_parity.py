@@ -210,3 +210,46 @@ def test_errors_are_reported(ctx, tiny, tiny_map):
     with pytest.raises(B.RmpcError) as e:
         ctx.upload(np.zeros((4, 4, 4), np.float32), 0.0, (0, 0, 0))
     assert e.value.status == B.RMPC_E_INVALID
+
+
+@pytest.mark.parametrize("crop", [(0, 61, 3, 70, 1, 64), (5, 64, 0, 63, 0, 57), (0, 13, 0, 64, 0, 6)])
+def test_partial_cells_parity(ctx, tiny_map, crop):
+    """Grids whose sides are not multiples of 8 (partial cells are walked voxel by voxel) and a
+    grid thinner than one cell (no cell summaries at all): every ray as the oracle's."""
+    x0, x1, y0, y1, z0, z1 = crop
+    t = np.ascontiguousarray(tiny_map.tsdf[z0:z1, y0:y1, x0:x1])
+    org = tiny_map.origin_m + np.array([x0, y0, z0]) * tiny_map.voxel_m
+    mid = ctx.upload(t, tiny_map.voxel_m, org, "f32")
+    om = oracle.OracleMap(t, tiny_map.voxel_m, org, "f32")
+    try:
+        rng = np.random.default_rng(sum(crop))
+        done = 0
+        while done < 6:
+            x = org + rng.uniform(0.0, 1.0, 3) * np.array(t.shape[::-1]) * tiny_map.voxel_m
+            gi = np.floor((x - org) / tiny_map.voxel_m).astype(int)
+            if t[gi[2], gi[1], gi[0]] <= 0:
+                continue
+            v = rng.normal(size=3)
+            g = ctx.trace(mid, x, 4096, P_TINY)
+            o = oracle.trace(om, oracle.grid_start(om, x), oracle.directions(4096), P_TINY["max_range"])
+            compare_trace(g, o, f"crop {t.shape} state {done}")
+            compare_query(ctx.query(mid, x, v, 4096, P_TINY), oracle.query(om, x, v, 4096, P_TINY),
+                          f"crop {t.shape} state {done}")
+            done += 1
+    finally:
+        ctx.release(mid)
+
+
+def test_corner_starts_and_cell_face_ranges(ctx, tiny, tiny_map):
+    """Starts on voxel and cell corners and ranges that end exactly on cell faces."""
+    mid, om = tiny
+    for g in ((16.0, 16.0, 16.0), (8.0, 24.0, 40.0), (17.0, 33.0, 9.5), (31.5, 32.0, 32.0)):
+        x = tiny_map.origin_m + np.array(g) * tiny_map.voxel_m
+        gi = np.floor(g).astype(int)
+        if tiny_map.tsdf[gi[2], gi[1], gi[0]] <= 0:
+            continue
+        for rmax in (0.8, 1.6):
+            P = dict(P_TINY, max_range=rmax)
+            gt = ctx.trace(mid, x, 4096, P)
+            o = oracle.trace(om, oracle.grid_start(om, x), oracle.directions(4096), rmax)
+            compare_trace(gt, o, f"corner {g} range {rmax}")
