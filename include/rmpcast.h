@@ -120,14 +120,15 @@ rmpc_status rmpc_create(int device, void *arena_dev, size_t arena_bytes, rmpc_ct
 rmpc_status rmpc_destroy(rmpc_ctx *ctx);
 
 /*
- * rmpc_map_upload -- make a voxel map resident on the GPU ("the map is kept in GPU memory and
- * shared between all kernels", Sec. III-F).
+ * rmpc_map_upload -- make a voxel map resident on the GPU, where every later query reads it
+ * (Sec. III-F keeps the map in device memory for all kernels).
  *   desc: grid geometry and storage type; 1 <= nx, ny, nz <= 4096, voxel_m > 0.
  *   voxels: nx*ny*nz elements of the dtype in logical x-fastest order; host memory when
  *     voxels_on_device == 0, device memory of the context's GPU otherwise.  Only read during
  *     the call.
  *   map_id_out: receives an id >= 0.
- * The library re-lays the grid into cache-line bricks inside the arena.  Blocking.
+ * The library keeps the grid as given (x-fastest) in the arena and adds one summary element
+ * per whole 8 x 8 x 8 cell (occupied when any of its voxels is).  Blocking.
  * Errors: RMPC_E_INVALID, RMPC_E_NOMEM (arena full), RMPC_E_HIP.
  */
 rmpc_status rmpc_map_upload(rmpc_ctx *ctx, const rmpc_map_desc *desc, const void *voxels,

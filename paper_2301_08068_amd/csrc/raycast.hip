@@ -5,21 +5,23 @@
 // lanes walk at the same time (S = 1, 2, 4, 8 or 16): the first hit along a ray is the hit of
 // the lowest segment that finds one, so a query's critical path is one segment long instead of
 // one ray.  Inside a segment a lane runs a 3-D DDA (Amanatides & Woo) on the float32 start g
-// and the float32 Halton direction r, planning K voxel visits ahead (the visited addresses do
-// not depend on the loaded values, so K loads are in flight), and stops at the first occupied
-// voxel, at its segment's end, at max_range or at the grid's edge.  A wave ballot after every
-// round stops lanes whose ray already has a hit in a lower segment.  The lane holding the
-// ray's hit evaluates the obstacle policy of Sec. III-C in registers and adds it to
-// compensated float32 sums; the last block to finish resolves in float64.
+// and the float32 Halton direction r, in rounds that plan K steps ahead (the visited offsets
+// do not depend on the loaded values, so K loads are in flight), and stops at the first
+// occupied voxel, at its segment's end, at max_range or at the grid's edge.  Inside cells of
+// 8 x 8 x 8 voxels that the map's summaries mark free the walk steps cell by cell.  A wave
+// ballot after every round stops lanes whose ray already has a hit in a lower segment.  The
+// lane holding the ray's hit evaluates the obstacle policy of Sec. III-C in registers and adds
+// it to compensated float32 sums; the last block to finish resolves in float64.
 //
 // Exactness: face crossings are compared in float32 as T = (B - g) / r with B the integer
-// boundary (never accumulated).  When the two nearest crossings, or a crossing and max_range,
-// lie within a guard band that bounds the float32 error, the decision is redone in float64
-// from the same formula, so every traversal decision -- including which axis steps at an
-// exact tie (the lowest index) -- and the hit distance d = T h are the float64 values of the
-// definition.  A segment starts at a float64-located voxel on the ray's walk, at a parameter
-// chosen at least kSegMargin away from every face crossing, so the float32 end test of the
-// previous segment and the start of the next agree exactly.
+// face coordinate (never accumulated).  When the two nearest crossings, or a crossing and
+// max_range, lie within a guard band that bounds the float32 error, the decision is redone in
+// float64 from the same formula, so every traversal decision -- including which axis steps at
+// an exact tie (the lowest index) -- and the hit distance d = T h are the float64 values of
+// the definition.  Cell faces are voxel faces, so the cell-level walk takes the voxel walk's
+// decisions restricted to them.  A segment starts at a float64-located voxel on the ray's
+// walk, at a parameter chosen at least kSegMargin away from every face crossing, so the
+// float32 end test of the previous segment and the start of the next agree exactly.
 
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>

@@ -56,7 +56,7 @@ struct RayArgs {
     float tmax_lo, tmax_hi;      // float32 guard band around max_range / h
     double tmax_v;               // parameter span split into segments: min(max_range / h, grid diagonal)
     int32_t segments;            // lanes per ray (1, 2, 4, 8 or 16)
-    int32_t lookahead;           // voxel visits planned per round (4, 8 or 16)
+    int32_t lookahead;           // steps planned per round (4, 8 or 16)
     double max_range, h;
     double vel64[3];             // velocity, float64 (for the exact contribution count)
     double radius64;
