@@ -139,7 +139,7 @@ struct Walker {
     bool ended;                       // the ray's walk ends here: a hit, max_range or the grid edge
     bool hit;
     int hit_step;                     // decision index of the step that entered the hit voxel
-    double d;                         // metres
+    int hit_a;                        // axis across which the hit voxel was entered
     int fx, fy, fz;                   // last voxel entered when ended (the hit voxel on a hit)
 };
 
@@ -251,16 +251,6 @@ __device__ __forceinline__ void cell_entry(const RayArgs &A, const RayF &R, int 
     vz = a == 2 ? (pz ? lz : lz + E - 1) : (rz != 0.0f ? entry_coord(lz, gz, rz, irz, 2, T32, Ba, ga, ra, a, tie) : A.v0[2]);
 }
 
-// Continue the walk at the voxel level at voxel (vx, vy, vz).
-__device__ __forceinline__ void to_voxels(Walker &w, const RayF &R, const MapView &m, int vx, int vy, int vz,
-                                          bool pending, int ent_a)
-{
-    enter_level(w, R, m, 0, vx, vy, vz);
-    w.pending = pending;
-    w.ent_a = ent_a;
-    w.anchored = false;
-}
-
 // Plan K steps at the current level, load what they enter, and act on the first occupied
 // voxel or cell.  Returns true while the walk goes on.  The planned steps have no branches:
 // the axis step is done with selects, each step's load is issued as soon as its offset is
@@ -339,164 +329,182 @@ __device__ __forceinline__ bool walk_round(const RayArgs &A, Walker &w, const Ra
         if (k < nplan && Voxel<DT>::occ(val[k])) hk = k;
     const int steps = w.steps;
 
-    // (a) the voxel or cell entered by the previous round's exact step
-    if (w.pending && Voxel<DT>::occ(pv)) {
+    // Each case below only records what happens; the shared tail then computes a cell's entry
+    // voxel and moves the walk to its new level once, whatever mix of cases a wave's lanes take.
+    bool go_on = false;               // the walk continues next round
+    bool hit_now = false;             // the hit voxel (hx, hy, hz), entered across axis ha
+    int hx = 0, hy = 0, hz = 0, ha = 0;
+    int to_level = -1;                // >= 0: continue at this level
+    bool need_entry = false;          // the target voxel is the entry voxel of cell (tx, ty, tz) across axis ta_
+    int tx = 0, ty = 0, tz = 0, ta_ = 0;
+    int entry_tie_at = -1;            // decision index of that entry, for its near-tie record (-1: none)
+    bool to_pending = false;          // the target voxel is still to be read
+
+    const bool pending_hit = w.pending && Voxel<DT>::occ(pv);
+    w.pending = false;
+    if (pending_hit) {
+        // (a) the voxel or cell entered by the previous round's exact step
         int px_, py_, pz_;
         coords_of(R, w.lg, w.Bx, w.By, w.Bz, px_, py_, pz_);
-        const int a = w.ent_a;
         if (!cell) {
-            const double T64 = a == 0 ? entry64(px_, gx, rx) : (a == 1 ? entry64(py_, gy, ry) : entry64(pz_, gz, rz));
-            w.d = T64 * A.h;
-            w.fx = px_; w.fy = py_; w.fz = pz_;
-            w.hit = w.ended = true;
+            hit_now = true;
+            hx = px_; hy = py_; hz = pz_; ha = w.ent_a;
             w.hit_step = steps - 1;
-            return false;
+        } else {
+            to_level = 0; need_entry = true; to_pending = true;
+            tx = px_; ty = py_; tz = pz_; ta_ = w.ent_a;
+            entry_tie_at = steps - 1;
+            go_on = true;
         }
-        int vx, vy, vz;
-        bool tie = false;
-        cell_entry(A, R, a, px_, py_, pz_, vx, vy, vz, tie);
-        if (tie) w.tie_at = min(w.tie_at, steps - 1);
-        to_voxels(w, R, m, vx, vy, vz, true, a);
-        return true;
-    }
-    w.pending = false;
-
-    // (b) the first occupied voxel or cell among the planned steps
-    if (hk >= 0) {
+    } else if (hk >= 0) {
+        // (b) the first occupied voxel or cell among the planned steps
         float hBx = Bx, hBy = By, hBz = Bz;
         undo_after<K>(axes, hk, L, hBx, hBy, hBz);
-        int hx, hy, hz;
-        coords_of(R, w.lg, hBx, hBy, hBz, hx, hy, hz);
+        int cx, cy, cz;
+        coords_of(R, w.lg, hBx, hBy, hBz, cx, cy, cz);
         const int a = (int)((axes >> (2 * hk)) & 3u);
-        if (!cell) {
-            const double T64 = a == 0 ? entry64(hx, gx, rx) : (a == 1 ? entry64(hy, gy, ry) : entry64(hz, gz, rz));
-            w.d = T64 * A.h;
-            w.fx = hx; w.fy = hy; w.fz = hz;
-            w.hit = w.ended = true;
-            w.hit_step = steps + hk;
-            w.steps = steps + hk + 1;
-            return false;
-        }
-        int vx, vy, vz;
-        bool tie = false;
-        cell_entry(A, R, a, hx, hy, hz, vx, vy, vz, tie);
-        if (tie) w.tie_at = min(w.tie_at, steps + hk);
         w.steps = steps + hk + 1;
-        to_voxels(w, R, m, vx, vy, vz, true, a);
-        return true;
-    }
-
-    // (c) a full round: continue, at the cell level if the walk is inside a free cell
-    if (nplan == K) {
+        if (!cell) {
+            hit_now = true;
+            hx = cx; hy = cy; hz = cz; ha = a;
+            w.hit_step = steps + hk;
+        } else {
+            to_level = 0; need_entry = true; to_pending = true;
+            tx = cx; ty = cy; tz = cz; ta_ = a;
+            entry_tie_at = steps + hk;
+            go_on = true;
+        }
+    } else if (nplan == K) {
+        // (c) a full round: continue, at the cell level if the walk is inside a free cell
         w.Bx = Bx; w.By = By; w.Bz = Bz; w.Tx = Tx; w.Ty = Ty; w.Tz = Tz;
         w.off = off;
         w.steps = steps + K;
+        go_on = true;
         if (cell) {
             w.anchored = false;
             w.ent_a = (int)((axes >> (2 * (K - 1))) & 3u);
-            return true;
+        } else if (cin && !w.settled && !Voxel<DT>::occ(cf)) {
+            to_level = kCellLog2;
+            tx = ccx; ty = ccy; tz = ccz;
         }
-        if (cin && !w.settled && !Voxel<DT>::occ(cf)) {
-            enter_level(w, R, m, kCellLog2, ccx, ccy, ccz);
-            w.ax = ux; w.ay = uy; w.az = uz;
-            w.anchored = true;
-        }
-        return true;
-    }
-
-    // (d) the plan ended at step nplan: go back to the position after step nplan - 1
+    } else {
+        // (d) the plan ended at step nplan: go back to the position after step nplan - 1
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        if (k >= nplan) {
-            const uint32_t ak = (axes >> (2 * k)) & 3u;
-            Bx -= ak == 0 ? L : 0.0f;
-            By -= ak == 1 ? L : 0.0f;
-            Bz -= ak == 2 ? L : 0.0f;
-            off -= (uint32_t)(ak == 0 ? dx : (ak == 1 ? dy : dz));
-        }
-    }
-    Tx = rx != 0.0f ? (Bx - gsx) * arx : kInf;
-    Ty = ry != 0.0f ? (By - gsy) * ary : kInf;
-    Tz = rz != 0.0f ? (Bz - gsz) * arz : kInf;
-    int tie_at = w.tie_at, rtie_at = w.rtie_at;
-    if (hard) {
-        // the step the plan stopped at, decided in float64 exactly as the definition does
-        const int at = steps + nplan;
-        const float t1 = __builtin_amdgcn_fmed3f(Tx, fminf(Ty, Tz), -kInf);
-        const float t2 = __builtin_amdgcn_fmed3f(Tx, Ty, Tz);
-        int a = Tx == t1 ? 0 : (Ty == t1 ? 1 : 2);
-        bool tie = false;
-        if (t2 - t1 < 2e-5f + 1e-6f * t2) {
-            const double X = rx != 0.0f ? face64((int)fabsf(Bx), gx, rx) : __builtin_huge_val();
-            const double Y = ry != 0.0f ? face64((int)fabsf(By), gy, ry) : __builtin_huge_val();
-            const double Z = rz != 0.0f ? face64((int)fabsf(Bz), gz, rz) : __builtin_huge_val();
-            a = 0;
-            double m1 = X;
-            if (Y < m1) { a = 1; m1 = Y; }
-            if (Z < m1) { a = 2; m1 = Z; }
-            tie = (a != 0 && X - m1 < 1e-5) || (a != 1 && Y - m1 < 1e-5) || (a != 2 && Z - m1 < 1e-5);
-        }
-        // near-ties count at every voxel decision, at the cell level only on steps taken
-        if (tie && !cell) tie_at = min(tie_at, at);
-        const float ta = a == 0 ? Tx : (a == 1 ? Ty : Tz);
-        bool stop = ta > t_hi || (cell && ta >= t_lo);
-        if (!cell && !stop && ta >= t_lo) {
-            // range test (closed interval) in float64 inside the guard band
-            const double T64 = a == 0 ? face64((int)fabsf(Bx), gx, rx)
-                                      : (a == 1 ? face64((int)fabsf(By), gy, ry) : face64((int)fabsf(Bz), gz, rz));
-            const double dist = T64 * A.h;
-            stop = dist > A.max_range;
-            if (fabs(dist - A.max_range) < 1e-5 * A.h) rtie_at = min(rtie_at, at);
-        }
-        if (!stop) {
-            const float nBx = a == 0 ? Bx + L : Bx, nBy = a == 1 ? By + L : By, nBz = a == 2 ? Bz + L : Bz;
-            if (nBx <= Lx && nBy <= Ly && nBz <= Lz) {
-                // take it; the next round reads what it enters
-                if (tie && cell) tie_at = min(tie_at, at);
-                w.Bx = nBx; w.By = nBy; w.Bz = nBz;
-                w.Tx = a == 0 && rx != 0.0f ? (nBx - gsx) * arx : Tx;
-                w.Ty = a == 1 && ry != 0.0f ? (nBy - gsy) * ary : Ty;
-                w.Tz = a == 2 && rz != 0.0f ? (nBz - gsz) * arz : Tz;
-                w.off = off + (uint32_t)(a == 0 ? dx : (a == 1 ? dy : dz));
-                w.tie_at = tie_at;
-                w.rtie_at = rtie_at;
-                w.pending = true;
-                w.ent_a = a;
-                w.anchored = false;
-                w.steps = at + 1;
-                return true;
+        for (int k = 0; k < K; ++k) {
+            if (k >= nplan) {
+                const uint32_t ak = (axes >> (2 * k)) & 3u;
+                Bx -= ak == 0 ? L : 0.0f;
+                By -= ak == 1 ? L : 0.0f;
+                Bz -= ak == 2 ? L : 0.0f;
+                off -= (uint32_t)(ak == 0 ? dx : (ak == 1 ? dy : dz));
             }
-            exited = true;
+        }
+        Tx = rx != 0.0f ? (Bx - gsx) * arx : kInf;
+        Ty = ry != 0.0f ? (By - gsy) * ary : kInf;
+        Tz = rz != 0.0f ? (Bz - gsz) * arz : kInf;
+        int tie_at = w.tie_at, rtie_at = w.rtie_at;
+        bool taken = false;
+        if (hard) {
+            // the step the plan stopped at, decided in float64 exactly as the definition does
+            const int at = steps + nplan;
+            const float t1 = __builtin_amdgcn_fmed3f(Tx, fminf(Ty, Tz), -kInf);
+            const float t2 = __builtin_amdgcn_fmed3f(Tx, Ty, Tz);
+            int a = Tx == t1 ? 0 : (Ty == t1 ? 1 : 2);
+            bool tie = false;
+            if (t2 - t1 < 2e-5f + 1e-6f * t2) {
+                const double X = rx != 0.0f ? face64((int)fabsf(Bx), gx, rx) : __builtin_huge_val();
+                const double Y = ry != 0.0f ? face64((int)fabsf(By), gy, ry) : __builtin_huge_val();
+                const double Z = rz != 0.0f ? face64((int)fabsf(Bz), gz, rz) : __builtin_huge_val();
+                a = 0;
+                double m1 = X;
+                if (Y < m1) { a = 1; m1 = Y; }
+                if (Z < m1) { a = 2; m1 = Z; }
+                tie = (a != 0 && X - m1 < 1e-5) || (a != 1 && Y - m1 < 1e-5) || (a != 2 && Z - m1 < 1e-5);
+            }
+            // near-ties count at every voxel decision, at the cell level only on steps taken
+            if (tie && !cell) tie_at = min(tie_at, at);
+            const float ta = a == 0 ? Tx : (a == 1 ? Ty : Tz);
+            bool stop = ta > t_hi || (cell && ta >= t_lo);
+            if (!cell && !stop && ta >= t_lo) {
+                // range test (closed interval) in float64 inside the guard band
+                const double T64 = a == 0 ? face64((int)fabsf(Bx), gx, rx)
+                                          : (a == 1 ? face64((int)fabsf(By), gy, ry) : face64((int)fabsf(Bz), gz, rz));
+                const double dist = T64 * A.h;
+                stop = dist > A.max_range;
+                if (fabs(dist - A.max_range) < 1e-5 * A.h) rtie_at = min(rtie_at, at);
+            }
+            if (!stop) {
+                const float nBx = a == 0 ? Bx + L : Bx, nBy = a == 1 ? By + L : By, nBz = a == 2 ? Bz + L : Bz;
+                if (nBx <= Lx && nBy <= Ly && nBz <= Lz) {
+                    // take it; the next round reads what it enters
+                    if (tie && cell) tie_at = min(tie_at, at);
+                    w.Bx = nBx; w.By = nBy; w.Bz = nBz;
+                    w.Tx = a == 0 && rx != 0.0f ? (nBx - gsx) * arx : Tx;
+                    w.Ty = a == 1 && ry != 0.0f ? (nBy - gsy) * ary : Ty;
+                    w.Tz = a == 2 && rz != 0.0f ? (nBz - gsz) * arz : Tz;
+                    w.off = off + (uint32_t)(a == 0 ? dx : (a == 1 ? dy : dz));
+                    w.pending = true;
+                    w.ent_a = a;
+                    w.anchored = false;
+                    w.steps = at + 1;
+                    taken = true;
+                    go_on = true;
+                } else {
+                    exited = true;
+                }
+            }
+        }
+        w.tie_at = tie_at;
+        w.rtie_at = rtie_at;
+        if (!taken) {
+            // (e) the walk stops in this segment after step nplan - 1 (max_range, segment end,
+            // or the edge of the grid or of the whole cells)
+            w.steps = steps + nplan;
+            if (!cell) {
+                if (w.last || exited) {
+                    coords_of(R, 0, Bx, By, Bz, w.fx, w.fy, w.fz);        // the last voxel entered
+                    w.ended = true;
+                }
+            } else if (w.last || exited) {
+                // finish the current (free) cell voxel by voxel: the walk ends in it or just
+                // past it (max range, or the grid edge beyond the whole cells), so it stays at
+                // the voxel level
+                w.settled = true;
+                to_level = 0;
+                go_on = true;
+                if (nplan == 0 && w.anchored) {
+                    tx = w.ax; ty = w.ay; tz = w.az;
+                } else {
+                    need_entry = true;
+                    coords_of(R, kCellLog2, Bx, By, Bz, tx, ty, tz);
+                    ta_ = nplan > 0 ? (int)((axes >> (2 * (nplan - 1))) & 3u) : w.ent_a;
+                }
+            }
         }
     }
-    // (e) the walk stops in this segment after step nplan - 1 (max_range, segment end, or the
-    // edge of the grid or of the whole cells)
-    w.tie_at = tie_at;
-    w.rtie_at = rtie_at;
-    w.steps = steps + nplan;
-    if (!cell) {
-        if (w.last || exited) {
-            coords_of(R, 0, Bx, By, Bz, w.fx, w.fy, w.fz);        // the last voxel entered
-            w.ended = true;
-        }
+    if (hit_now) {
+        w.fx = hx; w.fy = hy; w.fz = hz;
+        w.hit_a = ha;
+        w.hit = w.ended = true;
         return false;
     }
-    if (!w.last && !exited) return false;                // the segment ends inside a free cell
-    // finish the current (free) cell voxel by voxel: the walk ends in it or just past it (max
-    // range, or the grid edge beyond the whole cells), so it stays at the voxel level
-    w.settled = true;
-    int vx, vy, vz;
-    if (nplan == 0 && w.anchored) {
-        vx = w.ax; vy = w.ay; vz = w.az;
-    } else {
-        int cx, cy, cz;
-        coords_of(R, kCellLog2, Bx, By, Bz, cx, cy, cz);
-        const int a = nplan > 0 ? (int)((axes >> (2 * (nplan - 1))) & 3u) : w.ent_a;
+    if (need_entry) {
         bool tie = false;
-        cell_entry(A, R, a, cx, cy, cz, vx, vy, vz, tie);
+        int vx, vy, vz;
+        cell_entry(A, R, ta_, tx, ty, tz, vx, vy, vz, tie);
+        if (tie && entry_tie_at >= 0) w.tie_at = min(w.tie_at, entry_tie_at);
+        tx = vx; ty = vy; tz = vz;
     }
-    to_voxels(w, R, m, vx, vy, vz, false, 0);
-    return true;
+    if (to_level >= 0) {
+        if (to_level != 0) { w.ax = ux; w.ay = uy; w.az = uz; }      // anchor for the cell level
+        enter_level(w, R, m, to_level, tx, ty, tz);
+        w.anchored = to_level != 0;
+        if (to_level == 0) {
+            w.pending = to_pending;
+            w.ent_a = ta_;
+        }
+    }
+    return go_on;
 }
 
 // Per-ray outcome, valid in the lane that reports the ray (its hit segment, else segment 0).
@@ -529,7 +537,7 @@ __device__ __forceinline__ RayOut trace_group(const RayArgs &A, bool valid, int 
     w.ended = false;
     w.hit = false;
     w.hit_step = -1;
-    w.d = __builtin_huge_val();
+    w.hit_a = 0;
     w.fx = w.fy = w.fz = 0;
     bool active = valid;
     const VT *vox = static_cast<const VT *>(m.data);
@@ -610,7 +618,15 @@ __device__ __forceinline__ RayOut trace_group(const RayArgs &A, bool valid, int 
     const uint64_t rm = (__ballot(rtie) >> base) & seg_bits;
     o.report = valid && seg == (h < S ? h : 0);
     o.hit = w.hit && seg == h;
-    o.d = o.hit ? w.d : __builtin_huge_val();
+    // the hit distance: the float64 parameter of the face through which the hit voxel was
+    // entered, in metres
+    double d = __builtin_huge_val();
+    if (o.hit) {
+        const double T64 = w.hit_a == 0 ? entry64(w.fx, R.gx, R.rx)
+                                        : (w.hit_a == 1 ? entry64(w.fy, R.gy, R.ry) : entry64(w.fz, R.gz, R.rz));
+        d = T64 * A.h;
+    }
+    o.d = d;
     o.flags = A.start_flags | (tm ? kRayTie : 0u) | (rm ? kRayRangeTie : 0u);
     o.hit_lin = o.hit ? w.fx + m.nx * (w.fy + m.ny * w.fz) : -1;
     return o;
