@@ -216,7 +216,14 @@ __device__ __forceinline__ int entry_coord(int lo, float gb, float rb, float irb
                                            float ra, int a, bool &tie)
 {
     const int hi = lo + (1 << kCellLog2) - 1;
-    int c = (int)floorf(fmaf(T32, rb, gb));
+    const float y = fmaf(T32, rb, gb);
+    int c = (int)floorf(y);
+    // y is within 1.8e-7 |T r| + 1.2e-7 |y| of g + T r (T32 carries three roundings, the fma
+    // one): away from a face by twice that, floor(y) is the answer; near a face the two
+    // bounding faces are checked in the crossing order
+    const float fr = y - floorf(y);
+    const float tol = 4e-7f * fabsf(T32 * rb) + 3e-7f * fabsf(y) + 1e-6f;
+    if (fr > tol && fr < 1.0f - tol && c >= lo && c <= hi) return c;
     c = min(max(c, lo), hi);
     const bool up = rb > 0.0f;
     const int f_in = up ? c : c + 1;              // face crossed into voxel c

@@ -10,7 +10,7 @@ namespace rmpc {
 
 // Steps (voxels or free cells) planned per lane and round of a single query by default
 // (4, 8 or 16 are compiled; measured fastest for one 65536-ray query on gfx950).
-constexpr int kLookahead = 4;
+constexpr int kLookahead = 8;
 
 // Threads per block of the query kernels (one tile = this many lanes).
 constexpr int kBlockThreads = 256;
