@@ -38,6 +38,15 @@ namespace {
 constexpr float kInf = __builtin_huge_valf();
 constexpr double kSegMargin = 1e-3;      // voxel units between a segment boundary and any crossing
 
+// Requires x in a vector register at this point (emits no instruction): the per-step masks of
+// a round are folded into integer bit masks step by step instead of being carried as 64-bit
+// comparison masks in scalar registers until the end of the round.
+template <class T>
+__device__ __forceinline__ void in_vgpr(T &x)
+{
+    asm volatile("" : "+v"(x));
+}
+
 // Float64 crossing parameter of the next face along one axis (r != 0) from voxel coordinate v.
 __device__ __forceinline__ double cross64(int v, float g, float r)
 {
@@ -179,19 +188,23 @@ __device__ __forceinline__ void coords_of(const RayF &R, int lg, float Bx, float
     z = ((int)fabsf(Bz) >> lg) - pz;
 }
 
-// Faces ahead before steps j+1 .. K-1 of a round were taken (2-bit axis codes).
-template <int K>
-__device__ __forceinline__ void undo_after(uint32_t axes, int j, float L, float &Bx, float &By, float &Bz)
+// A round keeps which of its planned steps went along x and along y as bit masks (bit k:
+// step k; the others went along z).  Undoing a set of steps is then one count per axis.
+__device__ __forceinline__ int step_axis(uint32_t mx, uint32_t my, int k)
 {
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        if (k > j) {
-            const uint32_t ak = (axes >> (2 * k)) & 3u;
-            Bx -= ak == 0 ? L : 0.0f;
-            By -= ak == 1 ? L : 0.0f;
-            Bz -= ak == 2 ? L : 0.0f;
-        }
-    }
+    return ((mx >> k) & 1u) ? 0 : (((my >> k) & 1u) ? 1 : 2);
+}
+
+// Faces ahead, and the element offset, before the steps in `sel` were taken.
+__device__ __forceinline__ void undo_steps(uint32_t sel, uint32_t mx, uint32_t my, float L, int dx, int dy, int dz,
+                                           float &Bx, float &By, float &Bz, uint32_t &off)
+{
+    const int nx = __builtin_popcount(sel & mx), ny = __builtin_popcount(sel & my);
+    const int nz = __builtin_popcount(sel) - nx - ny;
+    Bx -= L * (float)nx;
+    By -= L * (float)ny;
+    Bz -= L * (float)nz;
+    off -= (uint32_t)(dx * nx + dy * ny + dz * nz);
 }
 
 // Does face F of axis b come before the crossing of face Ba of axis a in the merged crossing
@@ -265,7 +278,8 @@ __device__ __forceinline__ void cell_entry(const RayArgs &A, const RayF &R, int 
 // whose decision needs float64 (two crossings inside the guard band, or a crossing near
 // max_range) ends the plan; once the round's loads are checked, that step is taken exactly
 // and what it enters is read at the start of the next round.  Only the axis of each planned
-// step is kept (2 bits); earlier positions are recovered by undoing later steps.
+// step is kept (one bit in an x mask and a y mask); earlier positions are recovered by undoing
+// later steps.
 //   voxel level: an occupied voxel is the hit; a round that ends inside a free cell moves the
 //     walk to the cell level.
 //   cell level: an occupied cell is entered at the voxel level (its entry voxel found from the
@@ -291,11 +305,11 @@ __device__ __forceinline__ bool walk_round(const RayArgs &A, Walker &w, const Ra
     // what the previous round's exact step entered is read first
     const VT pv = vox[w.pending ? off : safe];
     VT val[K];
-    uint32_t axes = 0;                // 2 bits per planned step
-    int nplan = 0;
+    uint32_t mx = 0, my = 0;          // planned steps along x, along y (bit k: step k)
+    uint32_t gm = 0;                  // planned steps that are taken
+    uint32_t ends = 0;                // bit 0: the plan ended at a step that needs float64;
+                                      // bit 1: the walk left the grid (voxels) or the whole cells
     bool going = true;                // the plan goes on
-    bool exited = false;              // the walk left the grid (voxels) or the whole cells (cells)
-    bool hard = false;                // the plan ended at a step that needs float64
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         // nearest and second-nearest crossings (no NaNs occur: +inf marks an axis never crossed)
@@ -315,13 +329,21 @@ __device__ __forceinline__ bool walk_round(const RayArgs &A, Walker &w, const Ra
         off += (uint32_t)(bx ? dx : (by ? dy : dz));
         const bool inside = (Bx <= Lx) & (By <= Ly) & (Bz <= Lz);
         const bool live = going & !stop;
-        hard = hard | (live & need64);
-        exited = exited | (live & !need64 & !inside);
+        const bool hard_k = live & need64, exit_k = live & !need64 & !inside;
         going = live & !need64 & inside;
         val[k] = vox[going ? off : safe];
-        axes |= (uint32_t)(bx ? 0 : (by ? 1 : 2)) << (2 * k);
-        nplan += going ? 1 : 0;
+        mx |= bx ? 1u << k : 0u;
+        my |= by ? 1u << k : 0u;
+        gm |= going ? 1u << k : 0u;
+        ends |= (hard_k ? 1u : 0u) | (exit_k ? 2u : 0u);
+        in_vgpr(mx);
+        in_vgpr(my);
+        in_vgpr(gm);
+        in_vgpr(ends);
     }
+    const int nplan = __builtin_popcount(gm);
+    const bool hard = (ends & 1u) != 0;
+    bool exited = (ends & 2u) != 0;
     // voxel level: the summary of the cell the walk is in after a full round (for the move to
     // the cell level), loaded before the plan's values are examined
     int ux, uy, uz;
@@ -330,10 +352,11 @@ __device__ __forceinline__ bool walk_round(const RayArgs &A, Walker &w, const Ra
     const bool cin = !cell && going && ccx < m.ncx && ccy < m.ncy && ccz < m.ncz;
     const VT cf = vox[cin ? m.cell_base + (uint32_t)ccx + (uint32_t)m.ncx * ((uint32_t)ccy + (uint32_t)m.ncy * (uint32_t)ccz)
                           : safe_c];
-    int hk = -1;
+    uint32_t occm = 0;                // planned steps that entered an occupied element
 #pragma unroll
-    for (int k = K - 1; k >= 0; --k)
-        if (k < nplan && Voxel<DT>::occ(val[k])) hk = k;
+    for (int k = 0; k < K; ++k) occm |= Voxel<DT>::occ(val[k]) ? 1u << k : 0u;
+    occm &= (1u << nplan) - 1u;
+    const int hk = occm ? __builtin_ctz(occm) : -1;
     const int steps = w.steps;
 
     // Each case below only records what happens; the shared tail then computes a cell's entry
@@ -366,10 +389,11 @@ __device__ __forceinline__ bool walk_round(const RayArgs &A, Walker &w, const Ra
     } else if (hk >= 0) {
         // (b) the first occupied voxel or cell among the planned steps
         float hBx = Bx, hBy = By, hBz = Bz;
-        undo_after<K>(axes, hk, L, hBx, hBy, hBz);
+        uint32_t hoff = off;
+        undo_steps(((1u << K) - 1u) & ~((2u << hk) - 1u), mx, my, L, dx, dy, dz, hBx, hBy, hBz, hoff);
         int cx, cy, cz;
         coords_of(R, w.lg, hBx, hBy, hBz, cx, cy, cz);
-        const int a = (int)((axes >> (2 * hk)) & 3u);
+        const int a = step_axis(mx, my, hk);
         w.steps = steps + hk + 1;
         if (!cell) {
             hit_now = true;
@@ -389,23 +413,14 @@ __device__ __forceinline__ bool walk_round(const RayArgs &A, Walker &w, const Ra
         go_on = true;
         if (cell) {
             w.anchored = false;
-            w.ent_a = (int)((axes >> (2 * (K - 1))) & 3u);
+            w.ent_a = step_axis(mx, my, K - 1);
         } else if (cin && !w.settled && !Voxel<DT>::occ(cf)) {
             to_level = kCellLog2;
             tx = ccx; ty = ccy; tz = ccz;
         }
     } else {
         // (d) the plan ended at step nplan: go back to the position after step nplan - 1
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            if (k >= nplan) {
-                const uint32_t ak = (axes >> (2 * k)) & 3u;
-                Bx -= ak == 0 ? L : 0.0f;
-                By -= ak == 1 ? L : 0.0f;
-                Bz -= ak == 2 ? L : 0.0f;
-                off -= (uint32_t)(ak == 0 ? dx : (ak == 1 ? dy : dz));
-            }
-        }
+        undo_steps(((1u << K) - 1u) & ~((1u << nplan) - 1u), mx, my, L, dx, dy, dz, Bx, By, Bz, off);
         Tx = rx != 0.0f ? (Bx - gsx) * arx : kInf;
         Ty = ry != 0.0f ? (By - gsy) * ary : kInf;
         Tz = rz != 0.0f ? (Bz - gsz) * arz : kInf;
@@ -484,7 +499,7 @@ __device__ __forceinline__ bool walk_round(const RayArgs &A, Walker &w, const Ra
                 } else {
                     need_entry = true;
                     coords_of(R, kCellLog2, Bx, By, Bz, tx, ty, tz);
-                    ta_ = nplan > 0 ? (int)((axes >> (2 * (nplan - 1))) & 3u) : w.ent_a;
+                    ta_ = nplan > 0 ? step_axis(mx, my, nplan - 1) : w.ent_a;
                 }
             }
         }
