@@ -89,17 +89,20 @@ struct Acc {
 // ------------------------------------------------------------------------------------
 // block and grid reductions of Acc
 //
-// A block writes one row per thread to LDS; 13 groups of 16 "column" lanes then merge one
-// quantity each (9 compensated pairs, 4 integers): lane q of a group merges rows q, q+16, ...
-// in row order, and the 16 lanes combine with a butterfly that always puts the lower lane
-// first.  Every step has a fixed order, so results do not depend on timing.
+// A block writes one row per thread to LDS.  Nine groups of 16 lanes (threads 0..143) merge
+// one compensated pair each and four groups in the last wave (threads 192..255) add one
+// integer counter each, so no wave mixes the two kinds.  Lane q of a group merges rows q,
+// q+16, ... in row order (all 16 loaded first), and the 16 lanes combine with a butterfly
+// that always puts the lower lane first.  Every step has a fixed order, so results do not
+// depend on timing.
 // ------------------------------------------------------------------------------------
 
 constexpr int kRowWords = 23;                 // odd row stride: conflict-free column reads
-constexpr int kColumns = 13;                  // 9 pairs + 4 integers
 constexpr int kColLanes = 16;
+constexpr int kPairLanes = 9 * kColLanes;     // threads merging the compensated pairs
+constexpr int kIntLane0 = kBlock - 4 * kColLanes;   // first thread adding the counters
 constexpr int kReduceLdsWords = kBlock * kRowWords;
-
+static_assert(kPairLanes <= kIntLane0 && kIntLane0 % kWave == 0, "pair and counter lanes share a wave");
 
 __device__ __forceinline__ void row_store(float *row, const Acc &a)
 {
@@ -109,85 +112,56 @@ __device__ __forceinline__ void row_store(float *row, const Acc &a)
     q[0] = a.n_hit; q[1] = a.n_contrib; q[2] = a.n_tie; q[3] = a.visits;
 }
 
-// Merge one column value (pair or integer) into (s, c).
-__device__ __forceinline__ void col_merge(int col, float &s, float &c, const float *src)
-{
-    if (col < 9) {
-        csum_merge(s, c, src[col], src[9 + col]);
-    } else {
-        const int32_t v = reinterpret_cast<const int32_t *>(src)[9 + col];
-        s = __int_as_float(__float_as_int(s) + v);
-    }
-}
-
-// Butterfly over the 16 lanes of a column group (lower lane first).
-__device__ __forceinline__ void col_butterfly(int col, float &s, float &c)
+// Butterfly over the 16 lanes of a pair group; the lower lane's value is always the left
+// operand of the merge.
+__device__ __forceinline__ void pair_butterfly(float &s, float &c)
 {
 #pragma unroll
     for (int off = 1; off < kColLanes; off <<= 1) {
         const float s2 = __shfl_xor(s, off, kWave);
         const float c2 = __shfl_xor(c, off, kWave);
-        if (col < 9) {
-            if (threadIdx.x & off) {
-                float ls = s2, lc = c2;
-                csum_merge(ls, lc, s, c);
-                s = ls; c = lc;
-            } else {
-                csum_merge(s, c, s2, c2);
-            }
-        } else {
-            s = __int_as_float(__float_as_int(s) + __float_as_int(s2));
-        }
+        const bool upper = (threadIdx.x & off) != 0;
+        float ls = upper ? s2 : s, lc = upper ? c2 : c;
+        csum_merge(ls, lc, upper ? s : s2, upper ? c : c2);
+        s = ls;
+        c = lc;
     }
 }
 
-// Column lanes (threadIdx < 13 * 16) with q == 0 end up holding the block total of their
-// column; they write it to out[] in partial layout (18 floats, then 4 integers).
+__device__ __forceinline__ int32_t int_butterfly(int32_t v)
+{
+#pragma unroll
+    for (int off = 1; off < kColLanes; off <<= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// The block total, written to out[] in partial layout (9 sums, 9 compensations, 4 counters).
 __device__ __forceinline__ void block_reduce_store(const Acc &a, float *lds, float *out)
 {
     row_store(lds + threadIdx.x * kRowWords, a);
     __syncthreads();
-    const int col = threadIdx.x / kColLanes, q = threadIdx.x % kColLanes;
-    if (col < kColumns) {
-        float s = 0.0f, c = 0.0f;
-        for (int r = q; r < kBlock; r += kColLanes) col_merge(col, s, c, lds + r * kRowWords);
-        col_butterfly(col, s, c);
-        if (q == 0) {
-            if (col < 9) { out[col] = s; out[9 + col] = c; }
-            else out[9 + col] = s;
-        }
-    }
-}
-
-// Merge partial rows src[stride * j], j = 0..n-1 (global memory), column-wise, into out[]
-// (LDS).  Loads of one lane are independent and issued together.
-__device__ __forceinline__ void merge_partials(const float *src, int stride, int n, float *out)
-{
-    const int col = threadIdx.x / kColLanes, q = threadIdx.x % kColLanes;
-    if (col < kColumns) {
-        float s = 0.0f, c = 0.0f;
-        for (int j0 = q; j0 < n; j0 += 8 * kColLanes) {
-            float vs[8], vc[8];
+    const int t = threadIdx.x, q = t % kColLanes;
+    if (t < kPairLanes) {
+        const int col = t / kColLanes;
+        float vs[kBlock / kColLanes], vc[kBlock / kColLanes];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int j = j0 + u * kColLanes;
-                const float *p = src + (size_t)stride * j;
-                vs[u] = j < n ? (col < 9 ? p[col] : p[9 + col]) : 0.0f;
-                vc[u] = j < n && col < 9 ? p[9 + col] : 0.0f;
-            }
+        for (int u = 0; u < kBlock / kColLanes; ++u) {
+            vs[u] = lds[(q + u * kColLanes) * kRowWords + col];
+            vc[u] = lds[(q + u * kColLanes) * kRowWords + 9 + col];
+        }
+        float s = vs[0], c = vc[0];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                if (j0 + u * kColLanes < n) {
-                    if (col < 9) csum_merge(s, c, vs[u], vc[u]);
-                    else s = __int_as_float(__float_as_int(s) + __float_as_int(vs[u]));
-                }
-            }
-        }
-        col_butterfly(col, s, c);
-        if (q == 0) {
-            if (col < 9) { out[col] = s; out[9 + col] = c; }
-            else out[9 + col] = s;
-        }
+        for (int u = 1; u < kBlock / kColLanes; ++u) csum_merge(s, c, vs[u], vc[u]);
+        pair_butterfly(s, c);
+        if (q == 0) { out[col] = s; out[9 + col] = c; }
+    } else if (t >= kIntLane0) {
+        const int col = (t - kIntLane0) / kColLanes;
+        const int32_t *rows = reinterpret_cast<const int32_t *>(lds);
+        int32_t v = 0;
+#pragma unroll
+        for (int u = 0; u < kBlock / kColLanes; ++u) v += rows[(q + u * kColLanes) * kRowWords + 18 + col];
+        v = int_butterfly(v);
+        if (q == 0) reinterpret_cast<int32_t *>(out)[18 + col] = v;
     }
 }
 
