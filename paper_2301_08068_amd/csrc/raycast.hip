@@ -47,6 +47,12 @@ __device__ __forceinline__ void in_vgpr(T &x)
     asm volatile("" : "+v"(x));
 }
 
+// Smallest float above x >= 0 (x itself if +inf): t > x  <=>  t >= next_up(x).
+__device__ __forceinline__ float next_up(float x)
+{
+    return x < kInf ? __int_as_float(__float_as_int(x) + 1) : x;
+}
+
 // Float64 crossing parameter of the next face along one axis (r != 0) from voxel coordinate v.
 __device__ __forceinline__ double cross64(int v, float g, float r)
 {
@@ -131,7 +137,8 @@ struct Walker {
     int lg;                           // 0: voxel level, kCellLog2: cell level
     float Bx, By, Bz;                 // s * coordinate of the face ahead (exact integers)
     float Tx, Ty, Tz;                 // float32 parameters of those faces
-    float Lx, Ly, Lz;                 // past these s*B the walk has left the grid (or the whole cells)
+    float t_exit;                     // float32 parameter of the first face on the edge of the grid
+                                      // (cells: of the whole cells) that the ray crosses
     uint32_t off;                     // element offset of the current voxel or cell
     int dx, dy, dz;                   // offset change of one step along each axis
     float t_hi;                       // stop once the next crossing exceeds this (float32)
@@ -170,9 +177,12 @@ __device__ __forceinline__ void enter_level(Walker &w, const RayF &R, const MapV
     const int vnx = m.nx, vny = m.ny, vnz = m.nz, cnx = m.ncx, cny = m.ncy, cnz = m.ncz;
     const uint32_t cell_base = m.cell_base;
     const int nx = cell ? cnx : vnx, ny = cell ? cny : vny, nz = cell ? cnz : vnz;
-    w.Lx = px ? (float)(nx << lg) : 0.0f;
-    w.Ly = py ? (float)(ny << lg) : 0.0f;
-    w.Lz = pz ? (float)(nz << lg) : 0.0f;
+    // the edge faces have the form of every other face, so a crossing equals t_exit exactly
+    // when it is the crossing of an edge face
+    const float ex = rx != 0.0f ? ((px ? (float)(nx << lg) : 0.0f) - R.gsx) * R.arx : kInf;
+    const float ey = ry != 0.0f ? ((py ? (float)(ny << lg) : 0.0f) - R.gsy) * R.ary : kInf;
+    const float ez = rz != 0.0f ? ((pz ? (float)(nz << lg) : 0.0f) - R.gsz) * R.arz : kInf;
+    w.t_exit = fminf(ex, fminf(ey, ez));
     w.off = (cell ? cell_base : 0u) + (uint32_t)ux + (uint32_t)nx * ((uint32_t)uy + (uint32_t)ny * (uint32_t)uz);
     w.dx = px ? 1 : -1;
     w.dy = py ? nx : -nx;
@@ -301,14 +311,17 @@ __device__ __forceinline__ bool walk_round(const RayArgs &A, Walker &w, const Ra
     float Bx = w.Bx, By = w.By, Bz = w.Bz, Tx = w.Tx, Ty = w.Ty, Tz = w.Tz;
     uint32_t off = w.off;
     const int dx = w.dx, dy = w.dy, dz = w.dz;
-    const float Lx = w.Lx, Ly = w.Ly, Lz = w.Lz, t_hi = w.t_hi, t_lo = w.t_lo;
+    const float t_exit = w.t_exit, t_hi = w.t_hi, t_lo = w.t_lo;
     // what the previous round's exact step entered is read first
     const VT pv = vox[w.pending ? off : safe];
     VT val[K];
+    // The plan stops at the first step that is not simply taken: one past the segment's end,
+    // near max_range (cells: the voxel level finishes there; voxels: float64 range test), on
+    // an edge face, or needing float64 for a near tie.  The first three are one comparison with
+    // t_stop; which of them it was is worked out again at the end of the round.
+    const float t_stop = fminf(fminf(t_lo, t_exit), next_up(t_hi));
     uint32_t mx = 0, my = 0;          // planned steps along x, along y (bit k: step k)
-    uint32_t gm = 0;                  // planned steps that are taken
-    uint32_t ends = 0;                // bit 0: the plan ended at a step that needs float64;
-                                      // bit 1: the walk left the grid (voxels) or the whole cells
+    int nplan = 0;                    // planned steps taken
     bool going = true;                // the plan goes on
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -317,9 +330,7 @@ __device__ __forceinline__ bool walk_round(const RayArgs &A, Walker &w, const Ra
         const float t2 = __builtin_amdgcn_fmed3f(Tx, Ty, Tz);
         // (bitwise operators: no short-circuit branches in the plan)
         const bool bx = Tx == t1, by = !bx & (Ty == t1), bz = !bx & !by;
-        const bool near_end = t1 >= t_lo;
-        const bool stop = (t1 > t_hi) | (cell & near_end);    // cells: finish near max_range at the voxel level
-        const bool need64 = (t2 - t1 < 2e-5f + 1e-6f * t2) | (!cell & near_end);
+        going = going & (t1 < t_stop) & (t2 - t1 >= 2e-5f + 1e-6f * t2);
         Bx = bx ? Bx + L : Bx;
         By = by ? By + L : By;
         Bz = bz ? Bz + L : Bz;
@@ -327,23 +338,14 @@ __device__ __forceinline__ bool walk_round(const RayArgs &A, Walker &w, const Ra
         Ty = by ? (By - gsy) * ary : Ty;
         Tz = bz ? (Bz - gsz) * arz : Tz;
         off += (uint32_t)(bx ? dx : (by ? dy : dz));
-        const bool inside = (Bx <= Lx) & (By <= Ly) & (Bz <= Lz);
-        const bool live = going & !stop;
-        const bool hard_k = live & need64, exit_k = live & !need64 & !inside;
-        going = live & !need64 & inside;
         val[k] = vox[going ? off : safe];
         mx |= bx ? 1u << k : 0u;
         my |= by ? 1u << k : 0u;
-        gm |= going ? 1u << k : 0u;
-        ends |= (hard_k ? 1u : 0u) | (exit_k ? 2u : 0u);
+        nplan += going ? 1 : 0;
         in_vgpr(mx);
         in_vgpr(my);
-        in_vgpr(gm);
-        in_vgpr(ends);
+        in_vgpr(nplan);
     }
-    const int nplan = __builtin_popcount(gm);
-    const bool hard = (ends & 1u) != 0;
-    bool exited = (ends & 2u) != 0;
     // voxel level: the summary of the cell the walk is in after a full round (for the move to
     // the cell level), loaded before the plan's values are examined
     int ux, uy, uz;
@@ -424,13 +426,20 @@ __device__ __forceinline__ bool walk_round(const RayArgs &A, Walker &w, const Ra
         Tx = rx != 0.0f ? (Bx - gsx) * arx : kInf;
         Ty = ry != 0.0f ? (By - gsy) * ary : kInf;
         Tz = rz != 0.0f ? (Bz - gsz) * arz : kInf;
+        // why the plan stopped at step nplan, from the same crossings the plan saw there
+        const float t1 = __builtin_amdgcn_fmed3f(Tx, fminf(Ty, Tz), -kInf);
+        const float t2 = __builtin_amdgcn_fmed3f(Tx, Ty, Tz);
+        const bool near_end = t1 >= t_lo;
+        const bool stop_n = (t1 > t_hi) | (cell & near_end);
+        const bool need64 = (t2 - t1 < 2e-5f + 1e-6f * t2) | (!cell & near_end);
+        const bool hard = !stop_n & need64;
+        // past the float64 cases an edge-face crossing is not tied, so t1 names it exactly
+        bool exited = !stop_n & !need64 & (t1 >= t_exit);
         int tie_at = w.tie_at, rtie_at = w.rtie_at;
         bool taken = false;
         if (hard) {
             // the step the plan stopped at, decided in float64 exactly as the definition does
             const int at = steps + nplan;
-            const float t1 = __builtin_amdgcn_fmed3f(Tx, fminf(Ty, Tz), -kInf);
-            const float t2 = __builtin_amdgcn_fmed3f(Tx, Ty, Tz);
             int a = Tx == t1 ? 0 : (Ty == t1 ? 1 : 2);
             bool tie = false;
             if (t2 - t1 < 2e-5f + 1e-6f * t2) {
@@ -457,7 +466,11 @@ __device__ __forceinline__ bool walk_round(const RayArgs &A, Walker &w, const Ra
             }
             if (!stop) {
                 const float nBx = a == 0 ? Bx + L : Bx, nBy = a == 1 ? By + L : By, nBz = a == 2 ? Bz + L : Bz;
-                if (nBx <= Lx && nBy <= Ly && nBz <= Lz) {
+                // the face crossed is an edge face when the new face ahead lies past the edge
+                const int pa = a == 0 ? rx > 0.0f : (a == 1 ? ry > 0.0f : rz > 0.0f);
+                const int na = a == 0 ? (cell ? m.ncx : m.nx) : (a == 1 ? (cell ? m.ncy : m.ny) : (cell ? m.ncz : m.nz));
+                const float edge = pa ? (float)(na << w.lg) : 0.0f;
+                if ((a == 0 ? nBx : (a == 1 ? nBy : nBz)) <= edge) {
                     // take it; the next round reads what it enters
                     if (tie && cell) tie_at = min(tie_at, at);
                     w.Bx = nBx; w.By = nBy; w.Bz = nBz;
