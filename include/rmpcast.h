@@ -107,8 +107,9 @@ typedef struct {
 /*
  * rmpc_create -- open a context on GPU `device`.
  *   arena_dev, arena_bytes: a caller-owned device buffer on that GPU from which the library
- *     sub-allocates everything it keeps on the device (maps, the ray-direction table,
- *     reduction partials).  It must stay valid until rmpc_destroy.  At least 2 MiB.
+ *     sub-allocates everything it keeps on the device (maps, the ray-direction table and
+ *     the direction-ordered ray lists, about 14 MB together, reduction partials).  It must
+ *     stay valid until rmpc_destroy.  At least 16 MiB.
  *   out: receives the context.
  * Computes the float32 Halton direction table (Sec. III-E Eq. 10) for RMPC_MAX_RAYS rays on
  * the device.  Errors: RMPC_E_INVALID (NULL, too small), RMPC_E_HIP.

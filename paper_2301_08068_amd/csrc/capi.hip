@@ -20,7 +20,7 @@
 
 namespace rmpc_host {
 
-constexpr size_t kMinArena = 2u << 20;
+constexpr size_t kMinArena = 16u << 20;
 constexpr int kMaxDim = 4096;
 
 thread_local std::string g_last_error;
@@ -120,7 +120,7 @@ std::vector<int32_t> coherent_order(const std::vector<float> &soa, int n)
 }
 
 // The ordered list used for n rays: the smallest ladder size >= n.
-void ray_list(const rmpc_ctx *ctx, int32_t n, const int32_t **list, int32_t *list_len)
+void ray_list(const rmpc_ctx *ctx, int32_t n, const rmpc::RayRec **list, int32_t *list_len)
 {
     const auto it = std::lower_bound(ctx->ladder.begin(), ctx->ladder.end(), n);
     const size_t k = (size_t)(it - ctx->ladder.begin());
@@ -176,8 +176,6 @@ rmpc_status setup_query(rmpc_ctx *ctx, int32_t map_id, const double x[3], int32_
     }
     ray_list(ctx, n_rays, &A.rays, &A.n_list);
     A.map = me.view;
-    A.dirs = ctx->dirs;
-    A.dir_stride = RMPC_MAX_RAYS;
     A.n_rays = n_rays;
     A.lin0 = A.v0[0] + n[0] * (A.v0[1] + n[1] * A.v0[2]);
     A.start_flags = start_flags;
@@ -247,7 +245,7 @@ const char *rmpc_last_error(void) { return g_last_error.c_str(); }
 rmpc_status rmpc_create(int device, void *arena_dev, size_t arena_bytes, rmpc_ctx **out)
 {
     if (!out || !arena_dev) return fail(RMPC_E_INVALID, "NULL argument");
-    if (arena_bytes < kMinArena) return fail(RMPC_E_INVALID, "arena smaller than 2 MiB");
+    if (arena_bytes < kMinArena) return fail(RMPC_E_INVALID, "arena smaller than 16 MiB");
     int ndev = 0;
     RMPC_HIP(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) return fail(RMPC_E_INVALID, "no such device");
@@ -276,9 +274,10 @@ rmpc_status rmpc_create(int device, void *arena_dev, size_t arena_bytes, rmpc_ct
     c->ev0 = c->ev1 = nullptr;
     c->prof_ms = 0.0;
     c->prof_n = 0;
-    size_t o_dirs, o_part, o_ticket, o_order, o_counts;
+    size_t o_dirs, o_part, o_ticket, o_order, o_counts, o_tmp;
     if (!c->alloc.alloc(sizeof(float) * 3 * RMPC_MAX_RAYS, &o_dirs) ||
         !c->alloc.alloc(sizeof(int32_t) * RMPC_MAX_RAYS, &o_order) ||
+        !c->alloc.alloc(sizeof(int32_t) * RMPC_MAX_RAYS, &o_tmp) ||
         !c->alloc.alloc(sizeof(int32_t) * 1024, &o_counts) ||
         !c->alloc.alloc(sizeof(float) * rmpc::kMaxPartialSlots * rmpc::kPartialWords, &o_part) ||
         !c->alloc.alloc(256, &o_ticket)) {
@@ -288,6 +287,7 @@ rmpc_status rmpc_create(int device, void *arena_dev, size_t arena_bytes, rmpc_ct
     c->dirs = reinterpret_cast<float *>(c->arena + o_dirs);
     c->order = reinterpret_cast<int32_t *>(c->arena + o_order);
     c->counts = reinterpret_cast<int32_t *>(c->arena + o_counts);
+    c->list_tmp = reinterpret_cast<int32_t *>(c->arena + o_tmp);
     c->partials = reinterpret_cast<float *>(c->arena + o_part);
     c->ticket = reinterpret_cast<uint32_t *>(c->arena + o_ticket);
     hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&c->result_host), sizeof(rmpc_result),
@@ -320,17 +320,22 @@ rmpc_status rmpc_create(int device, void *arena_dev, size_t arena_bytes, rmpc_ct
     c->ladder = list_ladder();
     for (size_t k = 0; k < c->ladder.size() && e == hipSuccess; ++k) {
         const int32_t n = c->ladder[k];
-        if (n == RMPC_MAX_RAYS) { c->ladder_lists.push_back(c->order); continue; }
         size_t off;
-        if (!c->alloc.alloc(sizeof(int32_t) * (size_t)n, &off)) {
+        if (!c->alloc.alloc(sizeof(rmpc::RayRec) * (size_t)n, &off)) {
             (void)hipHostFree(c->result_host);
             (void)hipHostFree(c->done_host);
             delete c;
             return fail(RMPC_E_NOMEM, "arena too small for the ray lists");
         }
-        int32_t *list = reinterpret_cast<int32_t *>(c->arena + off);
-        rmpc::CompactArgs ca{c->order, RMPC_MAX_RAYS, n, c->counts, list};
-        e = rmpc::launch_compact(ca, nullptr);
+        rmpc::RayRec *list = reinterpret_cast<rmpc::RayRec *>(c->arena + off);
+        const int32_t *idx = c->order;
+        if (n < RMPC_MAX_RAYS) {
+            rmpc::CompactArgs ca{c->order, RMPC_MAX_RAYS, n, c->counts, c->list_tmp};
+            e = rmpc::launch_compact(ca, nullptr);
+            idx = c->list_tmp;
+        }
+        rmpc::GatherArgs ga{idx, n, c->dirs, RMPC_MAX_RAYS, list};
+        if (e == hipSuccess) e = rmpc::launch_gather(ga, nullptr);
         c->ladder_lists.push_back(list);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(nullptr);

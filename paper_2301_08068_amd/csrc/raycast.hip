@@ -467,8 +467,13 @@ __device__ __forceinline__ bool walk_round(const RayArgs &A, Walker &w, const Ra
             if (!stop) {
                 const float nBx = a == 0 ? Bx + L : Bx, nBy = a == 1 ? By + L : By, nBz = a == 2 ? Bz + L : Bz;
                 // the face crossed is an edge face when the new face ahead lies past the edge
+                // (the sizes pass through readfirstlane as values: a select among fields of the
+                // kernel argument would become an indexed load from a private copy of it)
+                const int vnx = __builtin_amdgcn_readfirstlane(m.nx), vny = __builtin_amdgcn_readfirstlane(m.ny);
+                const int vnz = __builtin_amdgcn_readfirstlane(m.nz), cnx = __builtin_amdgcn_readfirstlane(m.ncx);
+                const int cny = __builtin_amdgcn_readfirstlane(m.ncy), cnz = __builtin_amdgcn_readfirstlane(m.ncz);
                 const int pa = a == 0 ? rx > 0.0f : (a == 1 ? ry > 0.0f : rz > 0.0f);
-                const int na = a == 0 ? (cell ? m.ncx : m.nx) : (a == 1 ? (cell ? m.ncy : m.ny) : (cell ? m.ncz : m.nz));
+                const int na = a == 0 ? (cell ? cnx : vnx) : (a == 1 ? (cell ? cny : vny) : (cell ? cnz : vnz));
                 const float edge = pa ? (float)(na << w.lg) : 0.0f;
                 if ((a == 0 ? nBx : (a == 1 ? nBy : nBz)) <= edge) {
                     // take it; the next round reads what it enters
@@ -542,6 +547,12 @@ __device__ __forceinline__ bool walk_round(const RayArgs &A, Walker &w, const Ra
     return go_on;
 }
 
+// Entry j of an ordered ray list as one 16-byte load: direction in x, y, z, Halton index bits in w.
+__device__ __forceinline__ float4 load_ray(const RayRec *rays, int j)
+{
+    return reinterpret_cast<const float4 *>(rays)[j];
+}
+
 // Per-ray outcome, valid in the lane that reports the ray (its hit segment, else segment 0).
 struct RayOut {
     bool report;
@@ -579,7 +590,7 @@ __device__ __forceinline__ RayOut trace_group(const RayArgs &A, bool valid, int 
     const uint32_t safe_v = A.lin0;
     const uint32_t safe_c = m.ncx > 0 && m.ncy > 0 && m.ncz > 0 ? m.cell_base : safe_v;
     // the summary of the start voxel's cell: the same for every segment-0 lane (issued now,
-    // while the segment bounds are computed); other segments load theirs below
+    // while the segment bounds are computed)
     const int c0x = A.v0[0] >> kCellLog2, c0y = A.v0[1] >> kCellLog2, c0z = A.v0[2] >> kCellLog2;
     const bool c0in = c0x < m.ncx && c0y < m.ncy && c0z < m.ncz;
     const VT cf0 = vox[c0in ? m.cell_base + (uint32_t)c0x + (uint32_t)m.ncx * ((uint32_t)c0y + (uint32_t)m.ncy * (uint32_t)c0z)
@@ -608,22 +619,15 @@ __device__ __forceinline__ RayOut trace_group(const RayArgs &A, bool valid, int 
             w.t_lo = kInf;
         }
     }
-    {
-        // start at the cell level when the start voxel's cell is free
-        const int cx = ux >> kCellLog2, cy = uy >> kCellLog2, cz = uz >> kCellLog2;
-        const bool cin = active && cx < m.ncx && cy < m.ncy && cz < m.ncz;
-        VT cf = cf0;
-        if (S > 1)
-            cf = vox[cin && seg != 0 ? m.cell_base + (uint32_t)cx + (uint32_t)m.ncx * ((uint32_t)cy + (uint32_t)m.ncy * (uint32_t)cz)
-                                     : safe_c];
-        if (seg == 0) cf = cf0;
-        if (cin && !Voxel<DT>::occ(cf)) {
-            enter_level(w, R, m, kCellLog2, cx, cy, cz);
-            w.ax = ux; w.ay = uy; w.az = uz;
-            w.anchored = true;
-        } else {
-            enter_level(w, R, m, 0, ux, uy, uz);
-        }
+    // segment 0 starts at the cell level when the start voxel's cell is free; later segments
+    // start at the voxel level (their cell's summary would be one more dependent load before
+    // the walk) and move to the cell level after their first full round in a free cell
+    if (seg == 0 && c0in && !Voxel<DT>::occ(cf0)) {
+        enter_level(w, R, m, kCellLog2, c0x, c0y, c0z);
+        w.ax = ux; w.ay = uy; w.az = uz;
+        w.anchored = true;
+    } else {
+        enter_level(w, R, m, 0, ux, uy, uz);
     }
 
     const int lane = threadIdx.x & (kWave - 1);
@@ -726,9 +730,9 @@ __device__ __forceinline__ void ray_tile(const RayArgs &A, int tile, int n_tiles
     const int p = tile * kBlock + threadIdx.x;
     const int j = p < A.n_list * S ? p / S : 0;
     const int seg = p & (S - 1);
-    const int i = A.rays[j];
-    const bool valid = p < A.n_list * S && i < A.n_rays;
-    const float rx = A.dirs[i], ry = A.dirs[i + A.dir_stride], rz = A.dirs[i + 2 * A.dir_stride];
+    const float4 rr = load_ray(A.rays, j);
+    const bool valid = p < A.n_list * S && __float_as_int(rr.w) < A.n_rays;
+    const float rx = rr.x, ry = rr.y, rz = rr.z;
     Acc acc;
     acc.zero();
     if (in_coll) {
@@ -887,9 +891,10 @@ __global__ void __launch_bounds__(kBlock, 4) trace_debug_kernel(RayArgs A)
     const int p = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     const int j = p < A.n_list * S ? p / S : 0;
     const int seg = p & (S - 1);
-    const int i = A.rays[j];
+    const float4 rr = load_ray(A.rays, j);
+    const int i = __float_as_int(rr.w);
     const bool valid = p < A.n_list * S && i < A.n_rays;
-    const float rx = A.dirs[i], ry = A.dirs[i + A.dir_stride], rz = A.dirs[i + 2 * A.dir_stride];
+    const float rx = rr.x, ry = rr.y, rz = rr.z;
     if (start_occupied<DT>(A)) {
         if (valid && seg == 0) {
             A.dbg_hit[i] = A.lin0;

@@ -76,10 +76,11 @@ struct rmpc_ctx {
     float *dirs;            // structure of arrays, RMPC_MAX_RAYS per component
     int32_t *order;         // all Halton indices in direction-coherent (Hilbert) order
     int32_t *counts;        // compaction scratch
+    int32_t *list_tmp;      // compaction output before the gather into ray records
     // ordered ray lists for a ladder of list sizes (all built at creation): a query with N
     // rays walks the list of the smallest size >= N and skips entries >= N
     std::vector<int32_t> ladder;            // ascending sizes, last = RMPC_MAX_RAYS
-    std::vector<const int32_t *> ladder_lists;
+    std::vector<const rmpc::RayRec *> ladder_lists;
     float *partials;
     uint32_t *ticket;
     rmpc_result *result_host;   // pinned, written by the kernels

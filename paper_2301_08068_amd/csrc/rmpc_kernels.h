@@ -41,12 +41,17 @@ struct PolicyF {
     float c, eta_rep, inv_nu_rep, eta_damp, inv_nu_damp, radius, inv_radius, eps;
 };
 
+// One entry of an ordered ray list: the float32 direction of Halton ray i and i itself, so
+// that a lane gets its ray with one 16-byte load.
+struct alignas(16) RayRec {
+    float x, y, z;
+    int32_t i;
+};
+
 // Everything one map query needs.
 struct RayArgs {
     MapView map;
-    const float *dirs;           // direction table, structure of arrays: x[], y[], z[]
-    int32_t dir_stride;          // elements between the x, y and z arrays
-    const int32_t *rays;         // ordered Halton indices; entries >= n_rays are skipped
+    const RayRec *rays;          // ordered ray list; entries with i >= n_rays are skipped
     int32_t n_list;              // length of `rays` (>= n_rays)
     int32_t n_rays;
     float g[3];                  // start in grid units, float32((x - origin) / h)
@@ -137,6 +142,15 @@ struct CompactArgs {
     int32_t *out;                // n entries
 };
 
+// out[k] = {dirs[idx[k]] (x, y, z from a structure of arrays with stride `stride`), idx[k]}.
+struct GatherArgs {
+    const int32_t *idx;
+    int32_t n;
+    const float *dirs;
+    int32_t stride;
+    RayRec *out;
+};
+
 struct SummaryArgs {
     MapView map;                 // grid in place; summaries are written at cell_base
 };
@@ -152,6 +166,7 @@ hipError_t launch_scan(const ScanArgs &a, hipStream_t s, hipEvent_t ev0 = nullpt
 hipError_t launch_directions(const DirsArgs &a, hipStream_t s);
 hipError_t launch_cell_summary(const SummaryArgs &a, hipStream_t s);
 hipError_t launch_compact(const CompactArgs &a, hipStream_t s);
+hipError_t launch_gather(const GatherArgs &a, hipStream_t s);
 // Persistent fused batch: `blocks` resident blocks pull tiles from a counter.
 hipError_t launch_batch(const BatchArgs &a, int blocks, int lookahead, hipStream_t s);
 // Resident blocks per CU of the batch kernel for a lookahead.

@@ -102,7 +102,21 @@ __global__ void __launch_bounds__(1024) compact_scatter_kernel(CompactArgs A)
     if (keep) A.out[off] = A.order[j];
 }
 
+__global__ void __launch_bounds__(256) gather_kernel(GatherArgs A)
+{
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= A.n) return;
+    const int32_t i = A.idx[k];
+    A.out[k] = RayRec{A.dirs[i], A.dirs[i + A.stride], A.dirs[i + 2 * A.stride], i};
+}
+
 }  // namespace
+
+hipError_t launch_gather(const GatherArgs &a, hipStream_t s)
+{
+    gather_kernel<<<(a.n + 255) / 256, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
 
 hipError_t launch_compact(const CompactArgs &a, hipStream_t s)
 {
