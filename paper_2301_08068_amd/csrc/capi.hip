@@ -385,18 +385,23 @@ rmpc_status rmpc_map_upload(rmpc_ctx *ctx, const rmpc_map_desc *desc, const void
     v.ncx = desc->nx >> rmpc::kCellLog2;
     v.ncy = desc->ny >> rmpc::kCellLog2;
     v.ncz = desc->nz >> rmpc::kCellLog2;
+    v.nbx = desc->nx >> rmpc::kBrickLog2;
+    v.nby = desc->ny >> rmpc::kBrickLog2;
+    v.nbz = desc->nz >> rmpc::kBrickLog2;
     const uint64_t cell_base = (n_log + 255) / 256 * 256;
-    const uint64_t n_all = cell_base + (uint64_t)v.ncx * v.ncy * v.ncz;
+    const uint64_t brick_base = (cell_base + (uint64_t)v.ncx * v.ncy * v.ncz + 255) / 256 * 256;
+    const uint64_t n_all = brick_base + (uint64_t)v.nbx * v.nby * v.nbz;
     if (n_all >= (1ull << 32)) return fail(RMPC_E_INVALID, "grid too large for 32-bit voxel offsets");
     v.cell_base = (uint32_t)cell_base;
+    v.brick_base = (uint32_t)brick_base;
     const size_t eb = elem_bytes(desc->dtype);
     size_t off;
     if (!ctx->alloc.alloc(n_all * eb, &off)) return fail(RMPC_E_NOMEM, "arena full (map)");
     v.data = ctx->arena + off;
-    // the grid is stored as given (x-fastest); the cell summaries follow it
+    // the grid is stored as given (x-fastest); the cell and brick summaries follow it
     hipError_t e = hipMemcpyAsync(ctx->arena + off, voxels, n_log * eb,
                                   voxels_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = rmpc::launch_cell_summary(rmpc::SummaryArgs{v}, s);
+    if (e == hipSuccess) e = rmpc::launch_map_summaries(rmpc::SummaryArgs{v}, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         ctx->alloc.release(off);

@@ -129,12 +129,13 @@ __device__ __forceinline__ RayF make_ray(const RayArgs &A, float rx, float ry, f
     return R;
 }
 
-// One lane's walk through one segment of one ray.  The walk moves either voxel by voxel or,
-// while it is inside cells whose summary says "free", cell by cell (lg = kCellLog2): a cell's
-// faces are voxel faces, so both levels take their decisions on the same crossing
-// parameters and visit the cells in the order the voxel walk would.
+// One lane's walk through one segment of one ray.  The walk moves voxel by voxel, brick by
+// brick (2^3 voxels, lg = kBrickLog2) while it is inside bricks whose summary says "free", or
+// cell by cell (8^3 voxels, lg = kCellLog2) inside free cells: brick and cell faces are voxel
+// faces, so every level takes its decisions on the same crossing parameters and visits its
+// elements in the order the voxel walk would.
 struct Walker {
-    int lg;                           // 0: voxel level, kCellLog2: cell level
+    int lg;                           // 0: voxel level, kBrickLog2: brick level, kCellLog2: cell level
     float Bx, By, Bz;                 // s * coordinate of the face ahead (exact integers)
     float Tx, Ty, Tz;                 // float32 parameters of those faces
     float t_exit;                     // float32 parameter of the first face on the edge of the grid
@@ -146,9 +147,12 @@ struct Walker {
     bool last;                        // the segment ending at max_range
     bool pending;                     // voxel level: the current voxel is still to be read
     int ent_a;                        // axis across which the current voxel or cell was entered
-    bool anchored;                    // cell level: (ax, ay, az) is a voxel of the walk in the cell
-    bool settled;                     // finishing the last cell voxel by voxel: no return to cells
-    int ax, ay, az;
+    bool anchored;                    // brick or cell level: the walk is still in the element it
+                                      // entered at anchor (ax, ay, az) of level anch_lg: a voxel
+                                      // of the walk, or (cells only) a brick entered across anch_a
+    bool settled;                     // finishing the last brick or cell voxel by voxel: no return
+                                      // to coarser levels
+    int ax, ay, az, anch_lg, anch_a;
     int steps;                        // decisions taken so far (orders the near-tie records)
     int tie_at, rtie_at;              // first decision index with a (range) near-tie
     // outcome
@@ -159,13 +163,13 @@ struct Walker {
     int fx, fy, fz;                   // last voxel entered when ended (the hit voxel on a hit)
 };
 
-// Start walking at voxel (lg = 0) or cell (lg = kCellLog2) (ux, uy, uz).
+// Start walking at element (ux, uy, uz) of level lg (voxel, brick or cell).
 __device__ __forceinline__ void enter_level(Walker &w, const RayF &R, const MapView &m, int lg, int ux, int uy,
                                             int uz)
 {
     const float rx = R.rx, ry = R.ry, rz = R.rz;
     const int px = rx > 0.0f, py = ry > 0.0f, pz = rz > 0.0f;
-    const bool cell = lg != 0;
+    const bool cell = lg == kCellLog2, brick = lg == kBrickLog2;
     w.lg = lg;
     const int bx = (ux + px) << lg, by = (uy + py) << lg, bz = (uz + pz) << lg;
     w.Bx = (float)(px ? bx : -bx);
@@ -175,15 +179,17 @@ __device__ __forceinline__ void enter_level(Walker &w, const RayF &R, const MapV
     w.Ty = ry != 0.0f ? (w.By - R.gsy) * R.ary : kInf;
     w.Tz = rz != 0.0f ? (w.Bz - R.gsz) * R.arz : kInf;
     const int vnx = m.nx, vny = m.ny, vnz = m.nz, cnx = m.ncx, cny = m.ncy, cnz = m.ncz;
-    const uint32_t cell_base = m.cell_base;
-    const int nx = cell ? cnx : vnx, ny = cell ? cny : vny, nz = cell ? cnz : vnz;
+    const int bnx = m.nbx, bny = m.nby, bnz = m.nbz;
+    const uint32_t base = cell ? m.cell_base : (brick ? m.brick_base : 0u);
+    const int nx = cell ? cnx : (brick ? bnx : vnx), ny = cell ? cny : (brick ? bny : vny);
+    const int nz = cell ? cnz : (brick ? bnz : vnz);
     // the edge faces have the form of every other face, so a crossing equals t_exit exactly
     // when it is the crossing of an edge face
     const float ex = rx != 0.0f ? ((px ? (float)(nx << lg) : 0.0f) - R.gsx) * R.arx : kInf;
     const float ey = ry != 0.0f ? ((py ? (float)(ny << lg) : 0.0f) - R.gsy) * R.ary : kInf;
     const float ez = rz != 0.0f ? ((pz ? (float)(nz << lg) : 0.0f) - R.gsz) * R.arz : kInf;
     w.t_exit = fminf(ex, fminf(ey, ez));
-    w.off = (cell ? cell_base : 0u) + (uint32_t)ux + (uint32_t)nx * ((uint32_t)uy + (uint32_t)ny * (uint32_t)uz);
+    w.off = base + (uint32_t)ux + (uint32_t)nx * ((uint32_t)uy + (uint32_t)ny * (uint32_t)uz);
     w.dx = px ? 1 : -1;
     w.dy = py ? nx : -nx;
     w.dz = pz ? nx * ny : -(nx * ny);
@@ -233,12 +239,11 @@ __device__ __forceinline__ bool crossed_first(int F, float gb, float rb, float i
 }
 
 // Coordinate along axis b (rb != 0) of the voxel the walk is in right after crossing face Ba
-// of axis a at float32 parameter T32, known to lie in [lo, lo + 7]: the float32 estimate
+// of axis a at float32 parameter T32, known to lie in [lo, hi]: the float32 estimate
 // floor(g + T r), confirmed on the face behind it and the face ahead of it.
-__device__ __forceinline__ int entry_coord(int lo, float gb, float rb, float irb, int b, float T32, int Ba, float ga,
-                                           float ra, int a, bool &tie)
+__device__ __forceinline__ int entry_coord(int lo, int hi, float gb, float rb, float irb, int b, float T32, int Ba,
+                                           float ga, float ra, int a, bool &tie)
 {
-    const int hi = lo + (1 << kCellLog2) - 1;
     const float y = fmaf(T32, rb, gb);
     int c = (int)floorf(y);
     // y is within 1.8e-7 |T r| + 1.2e-7 |y| of g + T r (T32 carries three roundings, the fma
@@ -260,53 +265,59 @@ __device__ __forceinline__ int entry_coord(int lo, float gb, float rb, float irb
     return c;
 }
 
-// Voxel the walk is in right after entering cell (cx, cy, cz) across its face on axis a.
-__device__ __forceinline__ void cell_entry(const RayArgs &A, const RayF &R, int a, int cx, int cy, int cz,
+// Voxel the walk is in right after entering element (cx, cy, cz) of level lg (a brick or a
+// cell) across its face on axis a.
+__device__ __forceinline__ void cell_entry(const RayArgs &A, const RayF &R, int lg, int a, int cx, int cy, int cz,
                                            int &vx, int &vy, int &vz, bool &tie)
 {
-    constexpr int E = 1 << kCellLog2;
+    const int E = 1 << lg;
     const float gx = R.gx, gy = R.gy, gz = R.gz, rx = R.rx, ry = R.ry, rz = R.rz;
     const int px = rx > 0.0f, py = ry > 0.0f, pz = rz > 0.0f;
     // 1/r with the bits of the walk's own reciprocal
     const float irx = px ? R.arx : -R.arx, iry = py ? R.ary : -R.ary, irz = pz ? R.arz : -R.arz;
-    const int lx = cx << kCellLog2, ly = cy << kCellLog2, lz = cz << kCellLog2;
+    const int lx = cx << lg, ly = cy << lg, lz = cz << lg;
     // the face crossed: the cell's low face when travelling up the axis, else its high face
     const int Ba = a == 0 ? (px ? lx : lx + E) : (a == 1 ? (py ? ly : ly + E) : (pz ? lz : lz + E));
     const float ga = a == 0 ? gx : (a == 1 ? gy : gz);
     const float ra = a == 0 ? rx : (a == 1 ? ry : rz);
     const float ira = a == 0 ? irx : (a == 1 ? iry : irz);
     const float T32 = ((float)Ba - ga) * ira;
-    vx = a == 0 ? (px ? lx : lx + E - 1) : (rx != 0.0f ? entry_coord(lx, gx, rx, irx, 0, T32, Ba, ga, ra, a, tie) : A.v0[0]);
-    vy = a == 1 ? (py ? ly : ly + E - 1) : (ry != 0.0f ? entry_coord(ly, gy, ry, iry, 1, T32, Ba, ga, ra, a, tie) : A.v0[1]);
-    vz = a == 2 ? (pz ? lz : lz + E - 1) : (rz != 0.0f ? entry_coord(lz, gz, rz, irz, 2, T32, Ba, ga, ra, a, tie) : A.v0[2]);
+    vx = a == 0 ? (px ? lx : lx + E - 1) : (rx != 0.0f ? entry_coord(lx, lx + E - 1, gx, rx, irx, 0, T32, Ba, ga, ra, a, tie) : A.v0[0]);
+    vy = a == 1 ? (py ? ly : ly + E - 1) : (ry != 0.0f ? entry_coord(ly, ly + E - 1, gy, ry, iry, 1, T32, Ba, ga, ra, a, tie) : A.v0[1]);
+    vz = a == 2 ? (pz ? lz : lz + E - 1) : (rz != 0.0f ? entry_coord(lz, lz + E - 1, gz, rz, irz, 2, T32, Ba, ga, ra, a, tie) : A.v0[2]);
 }
 
 // Plan K steps at the current level, load what they enter, and act on the first occupied
-// voxel or cell.  Returns true while the walk goes on.  The planned steps have no branches:
-// the axis step is done with selects, each step's load is issued as soon as its offset is
-// known, and steps past the end of the plan load a harmless offset and are ignored.  A step
-// whose decision needs float64 (two crossings inside the guard band, or a crossing near
+// voxel, brick or cell.  Returns true while the walk goes on.  The planned steps have no
+// branches: the axis step is done with selects, each step's load is issued as soon as its
+// offset is known, and steps past the end of the plan load a harmless offset and are ignored.
+// A step whose decision needs float64 (two crossings inside the guard band, or a crossing near
 // max_range) ends the plan; once the round's loads are checked, that step is taken exactly
 // and what it enters is read at the start of the next round.  Only the axis of each planned
 // step is kept (one bit in an x mask and a y mask); earlier positions are recovered by undoing
 // later steps.
 //   voxel level: an occupied voxel is the hit; a round that ends inside a free cell moves the
-//     walk to the cell level.
-//   cell level: an occupied cell is entered at the voxel level (its entry voxel found from the
-//     crossing); at max_range or the edge of the cells, the current free cell is finished at
-//     the voxel level so that the walk's last voxel and range decision are exact.
+//     walk to the cell level, one that ends inside a free brick to the brick level.
+//   brick level: an occupied brick is entered at the voxel level (its entry voxel found from
+//     the crossing); a round that ends inside a free cell moves the walk to the cell level.
+//   cell level: an occupied cell is entered at the brick level, in the brick that holds its
+//     entry voxel.
+//   brick and cell levels: at max_range or the edge of the whole bricks or cells, the current
+//     free brick or cell is finished at the voxel level so that the walk's last voxel and range
+//     decision are exact.
 template <int DT, int K, bool DEBUG>
 __device__ __forceinline__ bool walk_round(const RayArgs &A, Walker &w, const RayF &R, uint32_t safe_v,
-                                           uint32_t safe_c)
+                                           uint32_t safe_b, uint32_t safe_c)
 {
     using VT = typename Voxel<DT>::T;
     const MapView &m = A.map;
     const VT *vox = static_cast<const VT *>(m.data);
     const float gx = R.gx, gy = R.gy, gz = R.gz, rx = R.rx, ry = R.ry, rz = R.rz;
     const float gsx = R.gsx, gsy = R.gsy, gsz = R.gsz, arx = R.arx, ary = R.ary, arz = R.arz;
-    const bool cell = w.lg != 0;
-    const float L = cell ? (float)(1 << kCellLog2) : 1.0f;
-    const uint32_t safe = cell ? safe_c : safe_v;
+    const int lg = w.lg;
+    const bool coarse = lg != 0, cell = lg == kCellLog2;
+    const float L = (float)(1 << lg);
+    const uint32_t safe = cell ? safe_c : (coarse ? safe_b : safe_v);
     // the round works on copies (selects between registers, never between fields)
     float Bx = w.Bx, By = w.By, Bz = w.Bz, Tx = w.Tx, Ty = w.Ty, Tz = w.Tz;
     uint32_t off = w.off;
@@ -346,14 +357,20 @@ __device__ __forceinline__ bool walk_round(const RayArgs &A, Walker &w, const Ra
         in_vgpr(my);
         in_vgpr(nplan);
     }
-    // voxel level: the summary of the cell the walk is in after a full round (for the move to
-    // the cell level), loaded before the plan's values are examined
-    int ux, uy, uz;
-    coords_of(R, 0, Bx, By, Bz, ux, uy, uz);
-    const int ccx = ux >> kCellLog2, ccy = uy >> kCellLog2, ccz = uz >> kCellLog2;
+    // after a full round: the summaries of the cell (voxel and brick levels) and of the brick
+    // (voxel level) the walk is in, for a move to a coarser level, loaded before the plan's
+    // values are examined
+    int ux, uy, uz;                   // the walk's element at its level
+    coords_of(R, lg, Bx, By, Bz, ux, uy, uz);
+    const int csh = kCellLog2 - lg;
+    const int ccx = ux >> csh, ccy = uy >> csh, ccz = uz >> csh;
     const bool cin = !cell && going && ccx < m.ncx && ccy < m.ncy && ccz < m.ncz;
     const VT cf = vox[cin ? m.cell_base + (uint32_t)ccx + (uint32_t)m.ncx * ((uint32_t)ccy + (uint32_t)m.ncy * (uint32_t)ccz)
                           : safe_c];
+    const int bcx = ux >> kBrickLog2, bcy = uy >> kBrickLog2, bcz = uz >> kBrickLog2;
+    const bool bin = !coarse && going && bcx < m.nbx && bcy < m.nby && bcz < m.nbz;
+    const VT bf = vox[bin ? m.brick_base + (uint32_t)bcx + (uint32_t)m.nbx * ((uint32_t)bcy + (uint32_t)m.nby * (uint32_t)bcz)
+                          : safe_b];
     uint32_t occm = 0;                // planned steps that entered an occupied element
 #pragma unroll
     for (int k = 0; k < K; ++k) occm |= Voxel<DT>::occ(val[k]) ? 1u << k : 0u;
@@ -361,64 +378,81 @@ __device__ __forceinline__ bool walk_round(const RayArgs &A, Walker &w, const Ra
     const int hk = occm ? __builtin_ctz(occm) : -1;
     const int steps = w.steps;
 
-    // Each case below only records what happens; the shared tail then computes a cell's entry
-    // voxel and moves the walk to its new level once, whatever mix of cases a wave's lanes take.
+    // Each case below only records what happens; the shared tail then computes an entry voxel
+    // and moves the walk to its new level once, whatever mix of cases a wave's lanes take.
     bool go_on = false;               // the walk continues next round
     bool hit_now = false;             // the hit voxel (hx, hy, hz), entered across axis ha
     int hx = 0, hy = 0, hz = 0, ha = 0;
-    int to_level = -1;                // >= 0: continue at this level
-    bool need_entry = false;          // the target voxel is the entry voxel of cell (tx, ty, tz) across axis ta_
-    int tx = 0, ty = 0, tz = 0, ta_ = 0;
+    int to_level = -1;                // >= 0: continue at this level, in the element that holds
+    int tx = 0, ty = 0, tz = 0;       //   voxel (tx, ty, tz)
+    int entry_lg = 0;                 // > 0: that voxel is the entry voxel of element (ex, ey, ez)
+    int ex = 0, ey = 0, ez = 0;       //   of this level, entered across axis ta_
+    int ta_ = 0;
     int entry_tie_at = -1;            // decision index of that entry, for its near-tie record (-1: none)
-    bool to_pending = false;          // the target voxel is still to be read
+    bool to_pending = false;          // the element the walk continues in is still to be read
+    int anch = -1;                    // >= 0: level of the new anchor (nax, nay, naz), axis naa
+    int nax = 0, nay = 0, naz = 0, naa = 0;
 
     const bool pending_hit = w.pending && Voxel<DT>::occ(pv);
     w.pending = false;
     if (pending_hit) {
-        // (a) the voxel or cell entered by the previous round's exact step
+        // (a) the voxel, brick or cell entered by the previous round's exact step (or, for a
+        // brick, by the descent from its cell)
         int px_, py_, pz_;
-        coords_of(R, w.lg, w.Bx, w.By, w.Bz, px_, py_, pz_);
-        if (!cell) {
+        coords_of(R, lg, w.Bx, w.By, w.Bz, px_, py_, pz_);
+        go_on = coarse;
+        if (!coarse) {
             hit_now = true;
             hx = px_; hy = py_; hz = pz_; ha = w.ent_a;
             w.hit_step = steps - 1;
+        } else if (!cell && w.anchored) {
+            // a brick entered from its cell: the cell's entry voxel is the brick's
+            to_level = 0; to_pending = true;
+            tx = w.ax; ty = w.ay; tz = w.az; ta_ = w.ent_a;
         } else {
-            to_level = 0; need_entry = true; to_pending = true;
-            tx = px_; ty = py_; tz = pz_; ta_ = w.ent_a;
+            to_level = cell ? kBrickLog2 : 0; to_pending = true;
+            entry_lg = lg; ex = px_; ey = py_; ez = pz_; ta_ = w.ent_a;
             entry_tie_at = steps - 1;
-            go_on = true;
         }
     } else if (hk >= 0) {
-        // (b) the first occupied voxel or cell among the planned steps
+        // (b) the first occupied voxel, brick or cell among the planned steps
         float hBx = Bx, hBy = By, hBz = Bz;
         uint32_t hoff = off;
         undo_steps(((1u << K) - 1u) & ~((2u << hk) - 1u), mx, my, L, dx, dy, dz, hBx, hBy, hBz, hoff);
         int cx, cy, cz;
-        coords_of(R, w.lg, hBx, hBy, hBz, cx, cy, cz);
+        coords_of(R, lg, hBx, hBy, hBz, cx, cy, cz);
         const int a = step_axis(mx, my, hk);
         w.steps = steps + hk + 1;
-        if (!cell) {
+        if (!coarse) {
             hit_now = true;
             hx = cx; hy = cy; hz = cz; ha = a;
             w.hit_step = steps + hk;
         } else {
-            to_level = 0; need_entry = true; to_pending = true;
-            tx = cx; ty = cy; tz = cz; ta_ = a;
+            to_level = cell ? kBrickLog2 : 0; to_pending = true;
+            entry_lg = lg; ex = cx; ey = cy; ez = cz; ta_ = a;
             entry_tie_at = steps + hk;
             go_on = true;
         }
     } else if (nplan == K) {
-        // (c) a full round: continue, at the cell level if the walk is inside a free cell
+        // (c) a full round: continue, at a coarser level if the walk is inside a free cell or
+        // (voxel level) a free brick
         w.Bx = Bx; w.By = By; w.Bz = Bz; w.Tx = Tx; w.Ty = Ty; w.Tz = Tz;
         w.off = off;
         w.steps = steps + K;
         go_on = true;
-        if (cell) {
+        const int a_last = step_axis(mx, my, K - 1);
+        if (coarse) {
             w.anchored = false;
-            w.ent_a = step_axis(mx, my, K - 1);
-        } else if (cin && !w.settled && !Voxel<DT>::occ(cf)) {
+            w.ent_a = a_last;
+        }
+        if (!cell && !w.settled && cin && !Voxel<DT>::occ(cf)) {
             to_level = kCellLog2;
-            tx = ccx; ty = ccy; tz = ccz;
+            tx = ux << lg; ty = uy << lg; tz = uz << lg;
+            anch = lg; nax = ux; nay = uy; naz = uz; naa = a_last;
+        } else if (!coarse && !w.settled && bin && !Voxel<DT>::occ(bf)) {
+            to_level = kBrickLog2;
+            tx = ux; ty = uy; tz = uz;
+            anch = 0; nax = ux; nay = uy; naz = uz;
         }
     } else {
         // (d) the plan ended at step nplan: go back to the position after step nplan - 1
@@ -430,8 +464,8 @@ __device__ __forceinline__ bool walk_round(const RayArgs &A, Walker &w, const Ra
         const float t1 = __builtin_amdgcn_fmed3f(Tx, fminf(Ty, Tz), -kInf);
         const float t2 = __builtin_amdgcn_fmed3f(Tx, Ty, Tz);
         const bool near_end = t1 >= t_lo;
-        const bool stop_n = (t1 > t_hi) | (cell & near_end);
-        const bool need64 = (t2 - t1 < 2e-5f + 1e-6f * t2) | (!cell & near_end);
+        const bool stop_n = (t1 > t_hi) | (coarse & near_end);
+        const bool need64 = (t2 - t1 < 2e-5f + 1e-6f * t2) | (!coarse & near_end);
         const bool hard = !stop_n & need64;
         // past the float64 cases an edge-face crossing is not tied, so t1 names it exactly
         bool exited = !stop_n & !need64 & (t1 >= t_exit);
@@ -452,11 +486,12 @@ __device__ __forceinline__ bool walk_round(const RayArgs &A, Walker &w, const Ra
                 if (Z < m1) { a = 2; m1 = Z; }
                 tie = (a != 0 && X - m1 < 1e-5) || (a != 1 && Y - m1 < 1e-5) || (a != 2 && Z - m1 < 1e-5);
             }
-            // near-ties count at every voxel decision, at the cell level only on steps taken
-            if (tie && !cell) tie_at = min(tie_at, at);
+            // near-ties count at every voxel decision, at the brick and cell levels only on
+            // steps taken
+            if (tie && !coarse) tie_at = min(tie_at, at);
             const float ta = a == 0 ? Tx : (a == 1 ? Ty : Tz);
-            bool stop = ta > t_hi || (cell && ta >= t_lo);
-            if (!cell && !stop && ta >= t_lo) {
+            bool stop = ta > t_hi || (coarse && ta >= t_lo);
+            if (!coarse && !stop && ta >= t_lo) {
                 // range test (closed interval) in float64 inside the guard band
                 const double T64 = a == 0 ? face64((int)fabsf(Bx), gx, rx)
                                           : (a == 1 ? face64((int)fabsf(By), gy, ry) : face64((int)fabsf(Bz), gz, rz));
@@ -472,12 +507,16 @@ __device__ __forceinline__ bool walk_round(const RayArgs &A, Walker &w, const Ra
                 const int vnx = __builtin_amdgcn_readfirstlane(m.nx), vny = __builtin_amdgcn_readfirstlane(m.ny);
                 const int vnz = __builtin_amdgcn_readfirstlane(m.nz), cnx = __builtin_amdgcn_readfirstlane(m.ncx);
                 const int cny = __builtin_amdgcn_readfirstlane(m.ncy), cnz = __builtin_amdgcn_readfirstlane(m.ncz);
+                const int bnx = __builtin_amdgcn_readfirstlane(m.nbx), bny = __builtin_amdgcn_readfirstlane(m.nby);
+                const int bnz = __builtin_amdgcn_readfirstlane(m.nbz);
                 const int pa = a == 0 ? rx > 0.0f : (a == 1 ? ry > 0.0f : rz > 0.0f);
-                const int na = a == 0 ? (cell ? cnx : vnx) : (a == 1 ? (cell ? cny : vny) : (cell ? cnz : vnz));
-                const float edge = pa ? (float)(na << w.lg) : 0.0f;
+                const int nxl = cell ? cnx : (coarse ? bnx : vnx), nyl = cell ? cny : (coarse ? bny : vny);
+                const int nzl = cell ? cnz : (coarse ? bnz : vnz);
+                const int na = a == 0 ? nxl : (a == 1 ? nyl : nzl);
+                const float edge = pa ? (float)(na << lg) : 0.0f;
                 if ((a == 0 ? nBx : (a == 1 ? nBy : nBz)) <= edge) {
                     // take it; the next round reads what it enters
-                    if (tie && cell) tie_at = min(tie_at, at);
+                    if (tie && coarse) tie_at = min(tie_at, at);
                     w.Bx = nBx; w.By = nBy; w.Bz = nBz;
                     w.Tx = a == 0 && rx != 0.0f ? (nBx - gsx) * arx : Tx;
                     w.Ty = a == 1 && ry != 0.0f ? (nBy - gsy) * ary : Ty;
@@ -498,25 +537,29 @@ __device__ __forceinline__ bool walk_round(const RayArgs &A, Walker &w, const Ra
         w.rtie_at = rtie_at;
         if (!taken) {
             // (e) the walk stops in this segment after step nplan - 1 (max_range, segment end,
-            // or the edge of the grid or of the whole cells)
+            // or the edge of the grid or of the whole bricks or cells)
             w.steps = steps + nplan;
-            if (!cell) {
+            if (!coarse) {
                 if (w.last || exited) {
                     coords_of(R, 0, Bx, By, Bz, w.fx, w.fy, w.fz);        // the last voxel entered
                     w.ended = true;
                 }
             } else if (w.last || exited) {
-                // finish the current (free) cell voxel by voxel: the walk ends in it or just
-                // past it (max range, or the grid edge beyond the whole cells), so it stays at
-                // the voxel level
+                // finish the current (free) brick or cell voxel by voxel: the walk ends in it or
+                // just past it (max range, or the grid edge beyond the whole bricks or cells),
+                // so it stays at the voxel level
                 w.settled = true;
                 to_level = 0;
                 go_on = true;
                 if (nplan == 0 && w.anchored) {
-                    tx = w.ax; ty = w.ay; tz = w.az;
+                    if (w.anch_lg == 0) {
+                        tx = w.ax; ty = w.ay; tz = w.az;
+                    } else {
+                        entry_lg = w.anch_lg; ex = w.ax; ey = w.ay; ez = w.az; ta_ = w.anch_a;
+                    }
                 } else {
-                    need_entry = true;
-                    coords_of(R, kCellLog2, Bx, By, Bz, tx, ty, tz);
+                    entry_lg = lg;
+                    coords_of(R, lg, Bx, By, Bz, ex, ey, ez);
                     ta_ = nplan > 0 ? step_axis(mx, my, nplan - 1) : w.ent_a;
                 }
             }
@@ -528,21 +571,21 @@ __device__ __forceinline__ bool walk_round(const RayArgs &A, Walker &w, const Ra
         w.hit = w.ended = true;
         return false;
     }
-    if (need_entry) {
+    if (entry_lg != 0) {
         bool tie = false;
         int vx, vy, vz;
-        cell_entry(A, R, ta_, tx, ty, tz, vx, vy, vz, tie);
+        cell_entry(A, R, entry_lg, ta_, ex, ey, ez, vx, vy, vz, tie);
         if (tie && entry_tie_at >= 0) w.tie_at = min(w.tie_at, entry_tie_at);
         tx = vx; ty = vy; tz = vz;
+        if (to_level == kBrickLog2) { anch = 0; nax = vx; nay = vy; naz = vz; }    // a cell's entry voxel
     }
     if (to_level >= 0) {
-        if (to_level != 0) { w.ax = ux; w.ay = uy; w.az = uz; }      // anchor for the cell level
-        enter_level(w, R, m, to_level, tx, ty, tz);
-        w.anchored = to_level != 0;
-        if (to_level == 0) {
-            w.pending = to_pending;
-            w.ent_a = ta_;
-        }
+        enter_level(w, R, m, to_level, tx >> to_level, ty >> to_level, tz >> to_level);
+        w.anchored = anch >= 0;
+        w.anch_lg = anch; w.anch_a = naa;
+        w.ax = nax; w.ay = nay; w.az = naz;
+        w.pending = to_pending;
+        w.ent_a = ta_;
     }
     return go_on;
 }
@@ -578,6 +621,7 @@ __device__ __forceinline__ RayOut trace_group(const RayArgs &A, bool valid, int 
     w.anchored = false;
     w.settled = false;
     w.ax = w.ay = w.az = 0;
+    w.anch_lg = w.anch_a = 0;
     w.steps = 0;
     w.tie_at = w.rtie_at = 1 << 30;
     w.ended = false;
@@ -589,6 +633,7 @@ __device__ __forceinline__ RayOut trace_group(const RayArgs &A, bool valid, int 
     const VT *vox = static_cast<const VT *>(m.data);
     const uint32_t safe_v = A.lin0;
     const uint32_t safe_c = m.ncx > 0 && m.ncy > 0 && m.ncz > 0 ? m.cell_base : safe_v;
+    const uint32_t safe_b = m.nbx > 0 && m.nby > 0 && m.nbz > 0 ? m.brick_base : safe_v;
     // the summary of the start voxel's cell: the same for every segment-0 lane (issued now,
     // while the segment bounds are computed)
     const int c0x = A.v0[0] >> kCellLog2, c0y = A.v0[1] >> kCellLog2, c0z = A.v0[2] >> kCellLog2;
@@ -621,7 +666,7 @@ __device__ __forceinline__ RayOut trace_group(const RayArgs &A, bool valid, int 
     }
     // segment 0 starts at the cell level when the start voxel's cell is free; later segments
     // start at the voxel level (their cell's summary would be one more dependent load before
-    // the walk) and move to the cell level after their first full round in a free cell
+    // the walk) and move to a coarser level after their first full round in a free brick or cell
     if (seg == 0 && c0in && !Voxel<DT>::occ(cf0)) {
         enter_level(w, R, m, kCellLog2, c0x, c0y, c0z);
         w.ax = ux; w.ay = uy; w.az = uz;
@@ -638,7 +683,7 @@ __device__ __forceinline__ RayOut trace_group(const RayArgs &A, bool valid, int 
         const uint64_t hm = __ballot(w.hit);
         if (hm & lower) active = false;                  // a lower segment already hit
         if (!__any(active)) break;
-        if (active) active = walk_round<DT, K, DEBUG>(A, w, R, safe_v, safe_c);
+        if (active) active = walk_round<DT, K, DEBUG>(A, w, R, safe_v, safe_b, safe_c);
     }
     // combine the group: the lowest segment with a hit owns the ray; the lowest segment whose
     // walk ended holds the ray's last voxel

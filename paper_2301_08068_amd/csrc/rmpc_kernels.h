@@ -30,10 +30,13 @@ struct MapView {
     int32_t nx, ny, nz, dtype;
     uint32_t cell_base;          // element offset of the cell summaries
     int32_t ncx, ncy, ncz;       // whole cells along each axis
+    uint32_t brick_base;         // element offset of the brick summaries
+    int32_t nbx, nby, nbz;       // whole bricks along each axis
 };
 
-// log2 of the edge of a summary cell, in voxels.
+// log2 of the edge, in voxels, of a summary cell and of a summary brick.
 constexpr int kCellLog2 = 3;
+constexpr int kBrickLog2 = 1;
 
 // Policy constants in float32 (reciprocals precomputed on the host).
 struct PolicyF {
@@ -164,7 +167,7 @@ hipError_t launch_raycast(const RayArgs &a, hipStream_t s, bool debug, hipEvent_
 hipError_t launch_scan(const ScanArgs &a, hipStream_t s, hipEvent_t ev0 = nullptr,
                        hipEvent_t ev1 = nullptr);
 hipError_t launch_directions(const DirsArgs &a, hipStream_t s);
-hipError_t launch_cell_summary(const SummaryArgs &a, hipStream_t s);
+hipError_t launch_map_summaries(const SummaryArgs &a, hipStream_t s);
 hipError_t launch_compact(const CompactArgs &a, hipStream_t s);
 hipError_t launch_gather(const GatherArgs &a, hipStream_t s);
 // Persistent fused batch: `blocks` resident blocks pull tiles from a counter.

@@ -43,24 +43,40 @@ __global__ void directions_kernel(DirsArgs A)
     A.out[i + 2 * A.n] = (float)z;
 }
 
-// Summary of cell c (8 x 8 x 8 voxels, whole cells only): the occupied value when any of
-// its voxels is occupied, else the free value, stored after the grid.
-template <int DT>
-__global__ void cell_summary_kernel(MapView m, typename Voxel<DT>::T occ_val, typename Voxel<DT>::T free_val)
+// Summary of each whole block of (2^LG)^3 voxels: "occupied" if any voxel in it is, stored
+// at base + bx + nbx * (by + nby * bz).
+template <int DT, int LG>
+__global__ void summary_kernel(MapView m, uint32_t base, int nbx, int nby, int nbz, typename Voxel<DT>::T occ_val,
+                               typename Voxel<DT>::T free_val)
 {
     using T = typename Voxel<DT>::T;
-    const int n_cells = m.ncx * m.ncy * m.ncz;
+    constexpr int E = 1 << LG;
+    const int n_blocks = nbx * nby * nbz;
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n_cells) return;
-    const int cx = c % m.ncx, cy = (c / m.ncx) % m.ncy, cz = c / (m.ncx * m.ncy);
+    if (c >= n_blocks) return;
+    const int cx = c % nbx, cy = (c / nbx) % nby, cz = c / (nbx * nby);
     T *data = static_cast<T *>(const_cast<void *>(m.data));
     bool any = false;
-    for (int k = 0; k < (1 << (3 * kCellLog2)) && !any; ++k) {
-        const int x = (cx << kCellLog2) + (k & 7), y = (cy << kCellLog2) + ((k >> 3) & 7),
-                  z = (cz << kCellLog2) + (k >> 6);
+    for (int k = 0; k < E * E * E && !any; ++k) {
+        const int x = (cx << LG) + (k % E), y = (cy << LG) + ((k / E) % E), z = (cz << LG) + k / (E * E);
         any = Voxel<DT>::occ(data[(uint32_t)x + (uint32_t)m.nx * ((uint32_t)y + (uint32_t)m.ny * (uint32_t)z)]);
     }
-    data[m.cell_base + (uint32_t)c] = any ? occ_val : free_val;
+    data[base + (uint32_t)c] = any ? occ_val : free_val;
+}
+
+template <int DT, int LG>
+void launch_summary(const MapView &m, uint32_t base, int nbx, int nby, int nbz, typename Voxel<DT>::T occ_val,
+                    typename Voxel<DT>::T free_val, hipStream_t s)
+{
+    const int n = nbx * nby * nbz;
+    if (n > 0) summary_kernel<DT, LG><<<(n + 255) / 256, 256, 0, s>>>(m, base, nbx, nby, nbz, occ_val, free_val);
+}
+
+template <int DT>
+void launch_summaries(const MapView &m, typename Voxel<DT>::T occ_val, typename Voxel<DT>::T free_val, hipStream_t s)
+{
+    launch_summary<DT, kCellLog2>(m, m.cell_base, m.ncx, m.ncy, m.ncz, occ_val, free_val, s);
+    launch_summary<DT, kBrickLog2>(m, m.brick_base, m.nbx, m.nby, m.nbz, occ_val, free_val, s);
 }
 
 // Chunk-wise count of entries < n (one 1024-entry chunk per block).
@@ -132,17 +148,12 @@ hipError_t launch_directions(const DirsArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_cell_summary(const SummaryArgs &a, hipStream_t s)
+hipError_t launch_map_summaries(const SummaryArgs &a, hipStream_t s)
 {
-    const int n_cells = a.map.ncx * a.map.ncy * a.map.ncz;
-    if (n_cells == 0) return hipSuccess;
-    const unsigned blocks = (unsigned)((n_cells + 255) / 256);
     switch (a.map.dtype) {
-    case RMPC_TSDF_F32: cell_summary_kernel<RMPC_TSDF_F32><<<blocks, 256, 0, s>>>(a.map, -1.0f, 1.0f); break;
-    case RMPC_TSDF_F16:
-        cell_summary_kernel<RMPC_TSDF_F16><<<blocks, 256, 0, s>>>(a.map, (uint16_t)0xbc00, (uint16_t)0x3c00);
-        break;
-    default: cell_summary_kernel<RMPC_OCC_U8><<<blocks, 256, 0, s>>>(a.map, (uint8_t)1, (uint8_t)0); break;
+    case RMPC_TSDF_F32: launch_summaries<RMPC_TSDF_F32>(a.map, -1.0f, 1.0f, s); break;
+    case RMPC_TSDF_F16: launch_summaries<RMPC_TSDF_F16>(a.map, (uint16_t)0xbc00, (uint16_t)0x3c00, s); break;
+    default: launch_summaries<RMPC_OCC_U8>(a.map, (uint8_t)1, (uint8_t)0, s); break;
     }
     return hipGetLastError();
 }
