@@ -30,11 +30,10 @@ template <> struct Voxel<RMPC_TSDF_F32> {
 };
 template <> struct Voxel<RMPC_TSDF_F16> {
     using T = uint16_t;
-    // binary16 <= 0: +-0, or sign set and not NaN
+    // binary16 <= 0 as one half-precision comparison (NaN compares false: free)
     static __device__ __forceinline__ bool occ(uint16_t b)
     {
-        uint32_t mag = b & 0x7fffu;
-        return mag == 0u || ((b & 0x8000u) && mag <= 0x7c00u);
+        return __builtin_bit_cast(_Float16, b) <= (_Float16)0.0f;
     }
 };
 template <> struct Voxel<RMPC_OCC_U8> {
