@@ -79,8 +79,9 @@ typedef struct {
 
 /* Per-ray debug flags (rmpc_trace_debug). */
 #define RMPC_RAY_TIE 1u          /* two face crossings within 1e-5 voxel at a decision the
-                                    walk took (crossings inside 8^3 cells it skipped as free
-                                    are not examined; every decision is exact regardless) */
+                                    walk took (crossings inside 8^3 cells and 2^3 bricks it
+                                    skipped as free are not examined; every decision is exact
+                                    regardless) */
 #define RMPC_RAY_RANGE_TIE 2u    /* a face crossing within 1e-5 voxel of max_range */
 #define RMPC_RAY_START_FACE 4u   /* the start lies within 1e-5 voxel of a face */
 #define RMPC_RAY_IN_COLLISION 8u /* the start voxel is occupied */
@@ -98,7 +99,8 @@ typedef struct {
     uint32_t flags;             /* RMPC_Q_* */
     int32_t n_rays;             /* rays cast (or scan points read) */
     int64_t visits;             /* voxels the rays' walks entered, start voxel included (the
-                                   walk reads far fewer: it skips free 8^3 cells whole) */
+                                   walk reads far fewer: it skips free 8^3 cells and 2^3
+                                   bricks whole) */
 } rmpc_result;
 
 /* Largest ray count per query (the Halton table length). */
@@ -129,7 +131,8 @@ rmpc_status rmpc_destroy(rmpc_ctx *ctx);
  *     the call.
  *   map_id_out: receives an id >= 0.
  * The library keeps the grid as given (x-fastest) in the arena and adds one summary element
- * per whole 8 x 8 x 8 cell (occupied when any of its voxels is).  Blocking.
+ * per whole 8 x 8 x 8 cell and one per whole 2 x 2 x 2 brick (occupied when any of its voxels
+ * is), about 1/7 of the grid's size more.  Blocking.
  * Errors: RMPC_E_INVALID, RMPC_E_NOMEM (arena full), RMPC_E_HIP.
  */
 rmpc_status rmpc_map_upload(rmpc_ctx *ctx, const rmpc_map_desc *desc, const void *voxels,
@@ -199,7 +202,8 @@ typedef struct {
 #define RMPC_CONFIG_QUERY 0     /* rmpc_query and rmpc_trace_debug */
 #define RMPC_CONFIG_BATCH 1     /* rmpc_query_batch */
 typedef struct {
-    int32_t lookahead;          /* steps (voxels or free cells) planned per round: 4, 8 or 16 */
+    int32_t lookahead;          /* steps (voxels, free bricks or free cells) planned per
+                                   round: 4, 8 or 16 */
     int32_t lane_target_log2;   /* split rays into segments until a query has ~2^this lanes (10..22) */
     int32_t blocks_per_cu;      /* batches: resident blocks per CU of the persistent kernel (0 = max) */
     int32_t use_graph;          /* batches: 1 = replay the launch from a captured hipGraph */
