@@ -253,3 +253,37 @@ def test_corner_starts_and_cell_face_ranges(ctx, tiny, tiny_map):
             gt = ctx.trace(mid, x, 4096, P)
             o = oracle.trace(om, oracle.grid_start(om, x), oracle.directions(4096), rmax)
             compare_trace(gt, o, f"corner {g} range {rmax}")
+
+
+@pytest.mark.parametrize("density", [0.0, 0.02, 0.15])
+def test_random_occupancy_parity(ctx, density):
+    """Random occupancy on an odd-sized 61 x 66 x 59 grid.  With 2 % of the voxels occupied
+    nearly every 8^3 cell is occupied while most 2^3 bricks are free, so walks go down from
+    cells to bricks and back up all the time; at 15 % few bricks are free; an empty grid is
+    walked at the coarsest level up to its edge (and its partial bricks and cells voxel by
+    voxel).  Every ray as the oracle's, for lookahead 4, 8 and 16."""
+    from paper_2301_08068_amd import binding as B
+    rng = np.random.default_rng(int(density * 1000) + 7)
+    shape = (59, 66, 61)                       # z, y, x
+    t = np.where(rng.uniform(size=shape) < density, -0.05, 0.05).astype(np.float32)
+    h, org = 0.1, np.array([-1.0, 0.5, 2.0])
+    mid = ctx.upload(t, h, org, "f32")
+    om = oracle.OracleMap(t, h, org, "f32")
+    saved = ctx.config(B.CONFIG_QUERY)
+    try:
+        for K in (4, 8, 16):
+            ctx.config(B.CONFIG_QUERY, lookahead=K)
+            for s in range(2):
+                while True:
+                    gi = rng.integers(0, shape[::-1])          # x, y, z
+                    if t[gi[2], gi[1], gi[0]] > 0:
+                        break
+                x = org + (gi + rng.uniform(0.05, 0.95, 3)) * h
+                for rmax in (2.5, 8.0):
+                    P = dict(P_TINY, max_range=rmax)
+                    g = ctx.trace(mid, x, 4096, P)
+                    o = oracle.trace(om, oracle.grid_start(om, x), oracle.directions(4096), rmax)
+                    compare_trace(g, o, f"density {density} lookahead {K} state {s} range {rmax}")
+    finally:
+        ctx.config(B.CONFIG_QUERY, **saved)
+        ctx.release(mid)
