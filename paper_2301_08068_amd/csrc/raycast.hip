@@ -8,7 +8,8 @@
 // and the float32 Halton direction r, in rounds that plan K steps ahead (the visited offsets
 // do not depend on the loaded values, so K loads are in flight), and stops at the first
 // occupied voxel, at its segment's end, at max_range or at the grid's edge.  Inside cells of
-// 8 x 8 x 8 voxels that the map's summaries mark free the walk steps cell by cell.  A wave
+// 8 x 8 x 8 voxels and bricks of 2 x 2 x 2 voxels that the map's summaries mark free the walk
+// steps cell by cell or brick by brick.  A wave
 // ballot after every round stops lanes whose ray already has a hit in a lower segment.  The
 // lane holding the ray's hit evaluates the obstacle policy of Sec. III-C in registers and adds
 // it to compensated float32 sums; the last block to finish resolves in float64.
@@ -18,10 +19,11 @@
 // max_range, lie within a guard band that bounds the float32 error, the decision is redone in
 // float64 from the same formula, so every traversal decision -- including which axis steps at
 // an exact tie (the lowest index) -- and the hit distance d = T h are the float64 values of
-// the definition.  Cell faces are voxel faces, so the cell-level walk takes the voxel walk's
-// decisions restricted to them.  A segment starts at a float64-located voxel on the ray's
-// walk, at a parameter chosen at least kSegMargin away from every face crossing, so the
-// float32 end test of the previous segment and the start of the next agree exactly.
+// the definition.  Brick and cell faces are voxel faces, so the coarse walks take the voxel
+// walk's decisions restricted to them.  A segment starts at a float64-located voxel on the ray's
+// walk, at a parameter chosen away from every face crossing by more than the float32 error of
+// a crossing parameter, so the float32 end test of the previous segment and the start of the
+// next agree exactly.
 
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
@@ -36,7 +38,12 @@ namespace rmpc {
 namespace {
 
 constexpr float kInf = __builtin_huge_valf();
-constexpr double kSegMargin = 1e-3;      // voxel units between a segment boundary and any crossing
+// Voxel units between a segment boundary t and any face crossing: kSegMargin + kSegMarginRel * t.
+// A float32 crossing parameter is within 1.8e-7 T of its value and t_hi = float32(t) within
+// 6e-8 t, so no float32 end test can land on the wrong side; below 0.025 for any t up to the
+// diagonal of a 4096^3 grid, so one crossing excludes at most one of the 0.05-spaced candidates.
+constexpr double kSegMargin = 1e-3;
+constexpr double kSegMarginRel = 1e-6;
 
 // Requires x in a vector register at this point (emits no instruction): the per-step masks of
 // a round are folded into integer bit masks step by step instead of being carried as 64-bit
@@ -77,7 +84,7 @@ __device__ __forceinline__ bool start_occupied(const RayArgs &A)
 }
 
 // Segment boundary of a ray near t_nom: the first of 16 candidates t = t_nom + 0.05 c (voxel
-// units) whose distance to every face crossing of the ray is at least kSegMargin.  Within 0.8
+// units) whose distance to every face crossing of the ray is at least the margin.  Within 0.8
 // voxel units each axis crosses at most two faces, so at most six candidates are excluded and
 // the search cannot fail for real inputs; `ok` is false otherwise.  Returns the voxel there.
 __device__ __forceinline__ double seg_boundary(double t_nom, float gx, float gy, float gz, float rx,
@@ -90,10 +97,11 @@ __device__ __forceinline__ double seg_boundary(double t_nom, float gx, float gy,
         vx = (int)floor((double)gx + t * (double)rx);
         vy = (int)floor((double)gy + t * (double)ry);
         vz = (int)floor((double)gz + t * (double)rz);
+        const double mg = kSegMargin + kSegMarginRel * t;
         bool good = true;
-        if (rx != 0.0f) good = good && cross64(vx, gx, rx) - t >= kSegMargin && t - entry64(vx, gx, rx) >= kSegMargin;
-        if (ry != 0.0f) good = good && cross64(vy, gy, ry) - t >= kSegMargin && t - entry64(vy, gy, ry) >= kSegMargin;
-        if (rz != 0.0f) good = good && cross64(vz, gz, rz) - t >= kSegMargin && t - entry64(vz, gz, rz) >= kSegMargin;
+        if (rx != 0.0f) good = good && cross64(vx, gx, rx) - t >= mg && t - entry64(vx, gx, rx) >= mg;
+        if (ry != 0.0f) good = good && cross64(vy, gy, ry) - t >= mg && t - entry64(vy, gy, ry) >= mg;
+        if (rz != 0.0f) good = good && cross64(vz, gz, rz) - t >= mg && t - entry64(vz, gz, rz) >= mg;
         ok = good;
     }
     return t;
@@ -660,7 +668,7 @@ __device__ __forceinline__ RayOut trace_group(const RayArgs &A, bool valid, int 
         const double te = seg_boundary(tmax * e / S, R.gx, R.gy, R.gz, rx, ry, rz, bx, by, bz, ok);
         if (ok) {
             w.last = false;
-            w.t_hi = (float)te;       // no crossing lies within kSegMargin of te
+            w.t_hi = (float)te;       // no crossing lies within the segment margin of te
             w.t_lo = kInf;
         }
     }

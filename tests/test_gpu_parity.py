@@ -287,3 +287,32 @@ def test_random_occupancy_parity(ctx, density):
     finally:
         ctx.config(B.CONFIG_QUERY, **saved)
         ctx.release(mid)
+
+
+def test_long_walks_parity(ctx):
+    """A 2500 x 36 x 10 grid with sparse obstacles and a 130 m range (2600 voxels): rays along
+    the long axis walk thousands of voxels split into 8 and 16 segments, so segment ends lie far
+    along the ray, where float32 crossing parameters carry their largest absolute error."""
+    from paper_2301_08068_amd import binding as B
+    rng = np.random.default_rng(11)
+    shape = (10, 36, 2500)
+    t = np.where(rng.uniform(size=shape) < 0.0004, -0.05, 0.05).astype(np.float32)
+    h, org = 0.05, np.zeros(3)
+    mid = ctx.upload(t, h, org, "f32")
+    om = oracle.OracleMap(t, h, org, "f32")
+    saved = ctx.config(B.CONFIG_QUERY)
+    P = dict(P_TINY, max_range=130.0)
+    try:
+        for s in range(3):
+            while True:
+                gi = np.array([rng.integers(0, 40), rng.integers(0, 36), rng.integers(0, 10)])
+                if t[gi[2], gi[1], gi[0]] > 0:
+                    break
+            x = org + (gi + rng.uniform(0.05, 0.95, 3)) * h
+            o = oracle.trace(om, oracle.grid_start(om, x), oracle.directions(8192), P["max_range"])
+            for lt in (17, 20):
+                ctx.config(B.CONFIG_QUERY, lookahead=8, lane_target_log2=lt)
+                compare_trace(ctx.trace(mid, x, 8192, P), o, f"long state {s} lane target 2^{lt}")
+    finally:
+        ctx.config(B.CONFIG_QUERY, **saved)
+        ctx.release(mid)
