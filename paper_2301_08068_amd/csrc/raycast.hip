@@ -856,7 +856,10 @@ __device__ __forceinline__ FinishSlots single_slots(float *partials, uint32_t *t
 // One map query per launch; block b takes tile xcd_tile(b).
 template <int DT, int K>
 // 4 waves per SIMD keep every block of a 2^18-lane query resident at once
-__global__ void __launch_bounds__(kBlock, 4) raycast_rmp_kernel(RayArgs A)
+// One 65,536-ray query at the default lane target has 2 waves per SIMD, so the kernel is built
+// for 2: the register budget then fits lookahead 16 without spills (lookahead 4 and 8 still
+// stay within 128 registers, 4 waves per SIMD).
+__global__ void __launch_bounds__(kBlock, 2) raycast_rmp_kernel(RayArgs A)
 {
     __shared__ float lds[kReduceLdsWords];
     ray_tile<DT, K>(A, xcd_tile(blockIdx.x, gridDim.x), gridDim.x,
