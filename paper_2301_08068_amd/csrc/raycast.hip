@@ -403,43 +403,33 @@ __device__ __forceinline__ bool walk_round(const RayArgs &A, Walker &w, const Ra
 
     const bool pending_hit = w.pending && Voxel<DT>::occ(pv);
     w.pending = false;
-    if (pending_hit) {
-        // (a) the voxel, brick or cell entered by the previous round's exact step (or, for a
-        // brick, by the descent from its cell)
-        int px_, py_, pz_;
-        coords_of(R, lg, w.Bx, w.By, w.Bz, px_, py_, pz_);
+    // Every case continues from the position after one step j of the plan: the step that
+    // entered the first occupied element, the last step taken, or none (j = -1: the round's
+    // start, which is the element the previous round's exact step entered).  The plan applied
+    // all K steps to (B, off), so the later ones are undone once here for all lanes.
+    const int j = pending_hit ? -1 : (hk >= 0 ? hk : nplan - 1);
+    undo_steps(((1u << K) - 1u) & ~(j >= 0 ? (2u << j) - 1u : 0u), mx, my, L, dx, dy, dz, Bx, By, Bz, off);
+    int jx, jy, jz;                   // the element after step j, entered across axis aj
+    coords_of(R, lg, Bx, By, Bz, jx, jy, jz);
+    const int aj = j >= 0 ? step_axis(mx, my, j) : w.ent_a;
+    if (pending_hit || hk >= 0) {
+        // (a, b) the element entered at decision steps + j is occupied: the voxel, brick or cell
+        // entered by the previous round's exact step (or, for a brick, by the descent from its
+        // cell), or the first occupied one among the planned steps
+        w.steps = steps + j + 1;
         go_on = coarse;
         if (!coarse) {
             hit_now = true;
-            hx = px_; hy = py_; hz = pz_; ha = w.ent_a;
-            w.hit_step = steps - 1;
-        } else if (!cell && w.anchored) {
+            hx = jx; hy = jy; hz = jz; ha = aj;
+            w.hit_step = steps + j;
+        } else if (pending_hit && !cell && w.anchored) {
             // a brick entered from its cell: the cell's entry voxel is the brick's
             to_level = 0; to_pending = true;
-            tx = w.ax; ty = w.ay; tz = w.az; ta_ = w.ent_a;
+            tx = w.ax; ty = w.ay; tz = w.az; ta_ = aj;
         } else {
             to_level = cell ? kBrickLog2 : 0; to_pending = true;
-            entry_lg = lg; ex = px_; ey = py_; ez = pz_; ta_ = w.ent_a;
-            entry_tie_at = steps - 1;
-        }
-    } else if (hk >= 0) {
-        // (b) the first occupied voxel, brick or cell among the planned steps
-        float hBx = Bx, hBy = By, hBz = Bz;
-        uint32_t hoff = off;
-        undo_steps(((1u << K) - 1u) & ~((2u << hk) - 1u), mx, my, L, dx, dy, dz, hBx, hBy, hBz, hoff);
-        int cx, cy, cz;
-        coords_of(R, lg, hBx, hBy, hBz, cx, cy, cz);
-        const int a = step_axis(mx, my, hk);
-        w.steps = steps + hk + 1;
-        if (!coarse) {
-            hit_now = true;
-            hx = cx; hy = cy; hz = cz; ha = a;
-            w.hit_step = steps + hk;
-        } else {
-            to_level = cell ? kBrickLog2 : 0; to_pending = true;
-            entry_lg = lg; ex = cx; ey = cy; ez = cz; ta_ = a;
-            entry_tie_at = steps + hk;
-            go_on = true;
+            entry_lg = lg; ex = jx; ey = jy; ez = jz; ta_ = aj;
+            entry_tie_at = steps + j;
         }
     } else if (nplan == K) {
         // (c) a full round: continue, at a coarser level if the walk is inside a free cell or
@@ -448,23 +438,21 @@ __device__ __forceinline__ bool walk_round(const RayArgs &A, Walker &w, const Ra
         w.off = off;
         w.steps = steps + K;
         go_on = true;
-        const int a_last = step_axis(mx, my, K - 1);
         if (coarse) {
             w.anchored = false;
-            w.ent_a = a_last;
+            w.ent_a = aj;
         }
         if (!cell && !w.settled && cin && !Voxel<DT>::occ(cf)) {
             to_level = kCellLog2;
             tx = ux << lg; ty = uy << lg; tz = uz << lg;
-            anch = lg; nax = ux; nay = uy; naz = uz; naa = a_last;
+            anch = lg; nax = ux; nay = uy; naz = uz; naa = aj;
         } else if (!coarse && !w.settled && bin && !Voxel<DT>::occ(bf)) {
             to_level = kBrickLog2;
             tx = ux; ty = uy; tz = uz;
             anch = 0; nax = ux; nay = uy; naz = uz;
         }
     } else {
-        // (d) the plan ended at step nplan: go back to the position after step nplan - 1
-        undo_steps(((1u << K) - 1u) & ~((1u << nplan) - 1u), mx, my, L, dx, dy, dz, Bx, By, Bz, off);
+        // (d) the plan ended at step nplan: continue from the position after step nplan - 1
         Tx = rx != 0.0f ? (Bx - gsx) * arx : kInf;
         Ty = ry != 0.0f ? (By - gsy) * ary : kInf;
         Tz = rz != 0.0f ? (Bz - gsz) * arz : kInf;
@@ -567,8 +555,7 @@ __device__ __forceinline__ bool walk_round(const RayArgs &A, Walker &w, const Ra
                     }
                 } else {
                     entry_lg = lg;
-                    coords_of(R, lg, Bx, By, Bz, ex, ey, ez);
-                    ta_ = nplan > 0 ? step_axis(mx, my, nplan - 1) : w.ent_a;
+                    ex = jx; ey = jy; ez = jz; ta_ = aj;
                 }
             }
         }
