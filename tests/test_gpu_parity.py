@@ -316,3 +316,40 @@ def test_long_walks_parity(ctx):
     finally:
         ctx.config(B.CONFIG_QUERY, **saved)
         ctx.release(mid)
+
+
+@pytest.mark.parametrize("enc", ["f32", "f16"])
+def test_special_values_occupancy(ctx, enc):
+    """Maps holding +-0, +-inf, NaNs of both signs and subnormals of both signs: a voxel is
+    occupied exactly when its value compares <= 0 (NaN free, -0 occupied, a positive subnormal
+    free), in the walk and in the cell and brick summaries alike."""
+    rng = np.random.default_rng(31 if enc == "f32" else 32)
+    shape = (36, 40, 48)
+    if enc == "f32":
+        specials = np.array([0.0, -0.0, np.inf, -np.inf, np.nan, -np.nan, 1e-45, -1e-45, 1.0, -1.0],
+                            np.float32).view(np.uint32)
+        free = np.float32(0.05).view(np.uint32)
+        t = np.full(shape, free, np.uint32)
+    else:
+        specials = np.array([0x0000, 0x8000, 0x7c00, 0xfc00, 0x7e00, 0xfe00, 0x0001, 0x8001, 0x3c00, 0xbc00],
+                            np.uint16)
+        t = np.full(shape, 0x2a66, np.uint16)                   # binary16 0.05
+    mask = rng.uniform(size=shape) < 0.03
+    t[mask] = rng.choice(specials, size=int(mask.sum()))
+    data = t.view(np.float32) if enc == "f32" else t
+    h, org = 0.1, np.zeros(3)
+    mid = ctx.upload(data, h, org, enc)
+    om = oracle.OracleMap(data, h, org, enc)
+    try:
+        for s in range(4):
+            while True:
+                gi = rng.integers(0, shape[::-1])
+                v = data[gi[2], gi[1], gi[0]]
+                if (enc == "f32" and v > 0) or (enc == "f16" and int(v) in (0x2a66, 0x3c00, 0x7c00)):
+                    break
+            x = org + (gi + rng.uniform(0.05, 0.95, 3)) * h
+            P = dict(P_TINY, max_range=6.0)
+            o = oracle.trace(om, oracle.grid_start(om, x), oracle.directions(4096), P["max_range"])
+            compare_trace(ctx.trace(mid, x, 4096, P), o, f"{enc} specials state {s}")
+    finally:
+        ctx.release(mid)
