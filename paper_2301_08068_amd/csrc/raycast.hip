@@ -147,14 +147,14 @@ struct Walker {
     float Bx, By, Bz;                 // s * coordinate of the face ahead (exact integers)
     float Tx, Ty, Tz;                 // float32 parameters of those faces
     float t_exit;                     // float32 parameter of the first face on the edge of the grid
-                                      // (cells: of the whole cells) that the ray crosses
-    uint32_t off;                     // element offset of the current voxel or cell
+                                      // (bricks, cells: of the whole bricks, cells) that the ray crosses
+    uint32_t off;                     // element offset of the current voxel, brick or cell
     int dx, dy, dz;                   // offset change of one step along each axis
     float t_hi;                       // stop once the next crossing exceeds this (float32)
     float t_lo;                       // crossings at or beyond this get the float64 range test
     bool last;                        // the segment ending at max_range
-    bool pending;                     // voxel level: the current voxel is still to be read
-    int ent_a;                        // axis across which the current voxel or cell was entered
+    bool pending;                     // the current voxel, brick or cell is still to be read
+    int ent_a;                        // axis across which the current element was entered
     bool anchored;                    // brick or cell level: the walk is still in the element it
                                       // entered at anchor (ax, ay, az) of level anch_lg: a voxel
                                       // of the walk, or (cells only) a brick entered across anch_a
@@ -275,7 +275,7 @@ __device__ __forceinline__ int entry_coord(int lo, int hi, float gb, float rb, f
 
 // Voxel the walk is in right after entering element (cx, cy, cz) of level lg (a brick or a
 // cell) across its face on axis a.
-__device__ __forceinline__ void cell_entry(const RayArgs &A, const RayF &R, int lg, int a, int cx, int cy, int cz,
+__device__ __forceinline__ void entry_voxel(const RayArgs &A, const RayF &R, int lg, int a, int cx, int cy, int cz,
                                            int &vx, int &vy, int &vz, bool &tie)
 {
     const int E = 1 << lg;
@@ -313,7 +313,7 @@ __device__ __forceinline__ void cell_entry(const RayArgs &A, const RayF &R, int 
 //   brick and cell levels: at max_range or the edge of the whole bricks or cells, the current
 //     free brick or cell is finished at the voxel level so that the walk's last voxel and range
 //     decision are exact.
-template <int DT, int K, bool DEBUG>
+template <int DT, int K>
 __device__ __forceinline__ bool walk_round(const RayArgs &A, Walker &w, const RayF &R, uint32_t safe_v,
                                            uint32_t safe_b, uint32_t safe_c)
 {
@@ -569,7 +569,7 @@ __device__ __forceinline__ bool walk_round(const RayArgs &A, Walker &w, const Ra
     if (entry_lg != 0) {
         bool tie = false;
         int vx, vy, vz;
-        cell_entry(A, R, entry_lg, ta_, ex, ey, ez, vx, vy, vz, tie);
+        entry_voxel(A, R, entry_lg, ta_, ex, ey, ez, vx, vy, vz, tie);
         if (tie && entry_tie_at >= 0) w.tie_at = min(w.tie_at, entry_tie_at);
         tx = vx; ty = vy; tz = vz;
         if (to_level == kBrickLog2) { anch = 0; nax = vx; nay = vy; naz = vz; }    // a cell's entry voxel
@@ -602,7 +602,7 @@ struct RayOut {
 };
 
 // Walk one ray with the S lanes of its group; every lane of the wave must call this.
-template <int DT, int K, bool DEBUG>
+template <int DT, int K>
 __device__ __forceinline__ RayOut trace_group(const RayArgs &A, bool valid, int seg, int S,
                                               float rx, float ry, float rz)
 {
@@ -678,7 +678,7 @@ __device__ __forceinline__ RayOut trace_group(const RayArgs &A, bool valid, int 
         const uint64_t hm = __ballot(w.hit);
         if (hm & lower) active = false;                  // a lower segment already hit
         if (!__any(active)) break;
-        if (active) active = walk_round<DT, K, DEBUG>(A, w, R, safe_v, safe_b, safe_c);
+        if (active) active = walk_round<DT, K>(A, w, R, safe_v, safe_b, safe_c);
     }
     // combine the group: the lowest segment with a hit owns the ray; the lowest segment whose
     // walk ended holds the ray's last voxel
@@ -783,7 +783,7 @@ __device__ __forceinline__ void ray_tile(const RayArgs &A, int tile, int n_tiles
             policy_accumulate(A.pol, rx, ry, rz, 0.0f, acc);
         }
     } else {
-        const RayOut o = trace_group<DT, K, false>(A, valid, seg, S, rx, ry, rz);
+        const RayOut o = trace_group<DT, K>(A, valid, seg, S, rx, ry, rz);
         acc.visits = o.visits_lane;
         if (o.report) {
             acc.n_tie = (o.flags & kRayTie) != 0;
@@ -928,7 +928,7 @@ __global__ void __launch_bounds__(kBlock, 3) batch_kernel(BatchArgs B)
 }
 
 template <int DT, int K>
-__global__ void __launch_bounds__(kBlock, 4) trace_debug_kernel(RayArgs A)
+__global__ void __launch_bounds__(kBlock, 2) trace_debug_kernel(RayArgs A)
 {
     const int S = A.segments;
     const int p = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
@@ -947,7 +947,7 @@ __global__ void __launch_bounds__(kBlock, 4) trace_debug_kernel(RayArgs A)
         }
         return;
     }
-    const RayOut o = trace_group<DT, K, true>(A, valid, seg, S, rx, ry, rz);
+    const RayOut o = trace_group<DT, K>(A, valid, seg, S, rx, ry, rz);
     // the ray's visit count is the sum over its group
     int v = o.visits_lane;
     for (int off = 1; off < S; off <<= 1) v += __shfl_xor(v, off, kWave);

@@ -44,7 +44,7 @@ def test_precision_report(ctx, paper_map):
              "f = pinv(S) b (relative to the largest entry)",
              f"{'state':>6} {'enc':>4} {'hit_mismatch':>12} {'d_max_rel':>10} {'S_rel':>10} {'b_rel':>10} "
              f"{'f_rel':>10} {'rank':>4}"]
-    worst = {}
+    worst, allv, n_ill, d_med = {}, {}, {}, {}
     try:
         for seed in SEEDS:
             x, v = W.free_state(paper_map, seed)
@@ -58,6 +58,9 @@ def test_precision_report(ctx, paper_map):
                 compare_query(q, o_q, f"{e} seed {seed}")
                 res[e] = (tr, q)
                 hs = (tr["hit"] >= 0) & (o_tr["hit"] >= 0)
+                if hs.any():
+                    rel = np.abs(tr["d"][hs] - o_tr["d"][hs]) / o_tr["d"][hs].clip(1e-300)
+                    d_med[e] = max(d_med.get(e, 0.0), float(np.median(rel)))
                 d_rel = float(np.max(np.abs(tr["d"][hs] - o_tr["d"][hs]) / o_tr["d"][hs].clip(1e-300))) \
                     if hs.any() else 0.0
                 f_rel = float(np.linalg.norm(q["f"] - o_q["f"]) / max(np.linalg.norm(o_q["f"]), 1e-300))
@@ -65,6 +68,8 @@ def test_precision_report(ctx, paper_map):
                            b=_rel(q["b"], o_q["b"]), f=f_rel)
                 for k, val in row.items():
                     worst[(e, k)] = max(worst.get((e, k), 0), val)
+                    allv.setdefault((e, k), []).append(val)
+                n_ill[e] = n_ill.get(e, 0) + int((q["flags"] & oracle.Q_ILL) != 0)
                 lines.append(f"{seed:>6} {e:>4} {row['mis']:>12d} {row['d']:>10.2e} {row['S']:>10.2e} "
                              f"{row['b']:>10.2e} {row['f']:>10.2e} {q['rank']:>4d}")
             # identical occupancy -> identical walks and bitwise identical results
@@ -77,6 +82,10 @@ def test_precision_report(ctx, paper_map):
         for mid in mids.values():
             ctx.release(mid)
     lines.append("worst: " + ", ".join(f"{e}.{k}={v:.2e}" for (e, k), v in sorted(worst.items())))
+    lines.append("median: " + ", ".join(f"{e}.{k}={np.median(v):.2e}" for (e, k), v in sorted(allv.items())))
+    lines.append("per-ray distance error, median over hit rays: "
+                 + ", ".join(f"{e}={v:.2e}" for e, v in sorted(d_med.items())))
+    lines.append("results flagged ILL: " + ", ".join(f"{e}={n}" for e, n in sorted(n_ill.items())))
     text = "\n".join(lines)
     print(text)
     if os.path.isdir("gpurun_out"):
