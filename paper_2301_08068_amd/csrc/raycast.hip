@@ -629,12 +629,16 @@ __device__ __forceinline__ RayOut trace_group(const RayArgs &A, bool valid, int 
     const uint32_t safe_v = A.lin0;
     const uint32_t safe_c = m.ncx > 0 && m.ncy > 0 && m.ncz > 0 ? m.cell_base : safe_v;
     const uint32_t safe_b = m.nbx > 0 && m.nby > 0 && m.nbz > 0 ? m.brick_base : safe_v;
-    // the summary of the start voxel's cell: the same for every segment-0 lane (issued now,
-    // while the segment bounds are computed)
+    // the summaries of the start voxel's cell and brick: the same for every segment-0 lane
+    // (issued now, while the segment bounds are computed)
     const int c0x = A.v0[0] >> kCellLog2, c0y = A.v0[1] >> kCellLog2, c0z = A.v0[2] >> kCellLog2;
     const bool c0in = c0x < m.ncx && c0y < m.ncy && c0z < m.ncz;
     const VT cf0 = vox[c0in ? m.cell_base + (uint32_t)c0x + (uint32_t)m.ncx * ((uint32_t)c0y + (uint32_t)m.ncy * (uint32_t)c0z)
                             : safe_c];
+    const int b0x = A.v0[0] >> kBrickLog2, b0y = A.v0[1] >> kBrickLog2, b0z = A.v0[2] >> kBrickLog2;
+    const bool b0in = b0x < m.nbx && b0y < m.nby && b0z < m.nbz;
+    const VT bf0 = vox[b0in ? m.brick_base + (uint32_t)b0x + (uint32_t)m.nbx * ((uint32_t)b0y + (uint32_t)m.nby * (uint32_t)b0z)
+                            : safe_b];
     // segment start
     int ux = A.v0[0], uy = A.v0[1], uz = A.v0[2];
     if (seg != 0) {
@@ -659,16 +663,28 @@ __device__ __forceinline__ RayOut trace_group(const RayArgs &A, bool valid, int 
             w.t_lo = kInf;
         }
     }
-    // segment 0 starts at the cell level when the start voxel's cell is free; later segments
-    // start at the voxel level (their cell's summary would be one more dependent load before
-    // the walk) and move to a coarser level after their first full round in a free brick or cell
-    if (seg == 0 && c0in && !Voxel<DT>::occ(cf0)) {
-        enter_level(w, R, m, kCellLog2, c0x, c0y, c0z);
-        w.ax = ux; w.ay = uy; w.az = uz;
-        w.anchored = true;
-    } else {
-        enter_level(w, R, m, 0, ux, uy, uz);
+    // every segment starts at the coarsest level whose element around its start voxel is free
+    // (a later segment reads those summaries once its start voxel is known), anchored at the
+    // start voxel
+    int scx = c0x, scy = c0y, scz = c0z, sbx = b0x, sby = b0y, sbz = b0z;
+    bool sc_in = c0in, sb_in = b0in;
+    VT cf = cf0, bf = bf0;
+    if (seg != 0) {
+        scx = ux >> kCellLog2; scy = uy >> kCellLog2; scz = uz >> kCellLog2;
+        sbx = ux >> kBrickLog2; sby = uy >> kBrickLog2; sbz = uz >> kBrickLog2;
+        sc_in = scx < m.ncx && scy < m.ncy && scz < m.ncz;
+        sb_in = sbx < m.nbx && sby < m.nby && sbz < m.nbz;
+        cf = vox[sc_in ? m.cell_base + (uint32_t)scx + (uint32_t)m.ncx * ((uint32_t)scy + (uint32_t)m.ncy * (uint32_t)scz)
+                       : safe_c];
+        bf = vox[sb_in ? m.brick_base + (uint32_t)sbx + (uint32_t)m.nbx * ((uint32_t)sby + (uint32_t)m.nby * (uint32_t)sbz)
+                       : safe_b];
     }
+    const bool start_cell = sc_in && !Voxel<DT>::occ(cf), start_brick = !start_cell && sb_in && !Voxel<DT>::occ(bf);
+    if (start_cell) enter_level(w, R, m, kCellLog2, scx, scy, scz);
+    else if (start_brick) enter_level(w, R, m, kBrickLog2, sbx, sby, sbz);
+    else enter_level(w, R, m, 0, ux, uy, uz);
+    w.anchored = start_cell || start_brick;
+    w.ax = ux; w.ay = uy; w.az = uz;
 
     const int lane = threadIdx.x & (kWave - 1);
     const int base = lane & ~(S - 1);
