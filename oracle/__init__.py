@@ -212,3 +212,64 @@ def scan(points: np.ndarray, v, p: Dict[str, float]) -> Dict:
     lib().orc_scan(_ptr(pts, C.c_float), pts.shape[0], _ptr(_d3(v), C.c_double), C.byref(ps),
                    C.byref(r))
     return _result_dict(r)
+
+
+# ------------------------------------------------------------------------------------------
+# closed-loop rollout (Sec. III-A Eq. 1 with the goal attractor of Sec. III-B): the ray policy
+# summed with the attractor (metric I), resolved and integrated step by step
+# ------------------------------------------------------------------------------------------
+
+ROLLOUT_GOAL, ROLLOUT_COLLISION, ROLLOUT_LEFT_GRID, ROLLOUT_TIMEOUT = 1, 2, 3, 4
+
+
+def attractor(goal, x, v, alpha: float, beta: float, c: float) -> np.ndarray:
+    """Goal attractor force (Sec. III-B Eq. 2): alpha s(goal - x) - beta v, s of Eq. 3."""
+    return alpha * soft_normalize(np.asarray(goal, np.float64) - np.asarray(x, np.float64), c) \
+        - beta * np.asarray(v, np.float64)
+
+
+def smoothness(xs: np.ndarray) -> float:
+    """Mean angular similarity 1 - acos(cos angle)/pi between consecutive displacement segments
+    of a path (1.0: straight; the path measure of Sec. IV-A); 1.0 with fewer than two segments."""
+    seg = np.diff(np.asarray(xs, np.float64), axis=0)
+    seg = seg[np.linalg.norm(seg, axis=1) > 0.0]
+    if len(seg) < 2:
+        return 1.0
+    a, b = seg[:-1], seg[1:]
+    cosang = np.sum(a * b, axis=1) / (np.linalg.norm(a, axis=1) * np.linalg.norm(b, axis=1))
+    return float(np.mean(1.0 - np.arccos(np.clip(cosang, -1.0, 1.0)) / np.pi))
+
+
+def rollout(m: OracleMap, x0, v0, n_rays: int, p: Dict[str, float], goal, alpha: float, beta: float,
+            dt: float, max_steps: int, goal_tol: float, nthreads: int = 1) -> Dict:
+    """Each step k: stop when within goal_tol of the goal or outside the grid; query the state
+    (stop when its voxel is occupied); a_k = (I + S)^-1 (f_a + b) with S, b the ray sums and f_a
+    the attractor; v_{k+1} = v_k + a_k dt, x_{k+1} = x_k + v_{k+1} dt (semi-implicit Euler)."""
+    x = np.array(x0, np.float64)
+    v = np.array(v0, np.float64)
+    xs, vs, acc = [x.copy()], [v.copy()], []
+    status = ROLLOUT_TIMEOUT
+    for _ in range(max_steps):
+        if np.linalg.norm(x - np.asarray(goal, np.float64)) <= goal_tol:
+            status = ROLLOUT_GOAL
+            break
+        try:
+            q = query(m, x, v, n_rays, p, nthreads=nthreads)
+        except ValueError:
+            status = ROLLOUT_LEFT_GRID
+            break
+        if q["flags"] & Q_IN_COLLISION:
+            status = ROLLOUT_COLLISION
+            break
+        a = np.linalg.solve(np.eye(3) + q["S"], attractor(goal, x, v, alpha, beta, p["c"]) + q["b"])
+        v = v + a * dt
+        x = x + v * dt
+        xs.append(x.copy())
+        vs.append(v.copy())
+        acc.append(a)
+    else:
+        if np.linalg.norm(x - np.asarray(goal, np.float64)) <= goal_tol:
+            status = ROLLOUT_GOAL
+    xs = np.array(xs)
+    return dict(status=status, n_steps=len(xs) - 1, x=xs, v=np.array(vs), a=np.array(acc).reshape(-1, 3),
+                smoothness=smoothness(xs), path_length=float(np.sum(np.linalg.norm(np.diff(xs, axis=0), axis=1))))
