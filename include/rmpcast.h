@@ -347,6 +347,51 @@ rmpc_status rmpc_server_stats(rmpc_ctx *ctx, rmpc_server_counters *out);
  */
 rmpc_status rmpc_server_stop(rmpc_ctx *ctx);
 
+/* ------------------------------------------------------------------------------------------
+ * Closed-loop rollout: the ray policy summed with the goal attractor of Sec. III-B (Eq. 2,
+ * metric I; s of Eq. 3 with params->c), resolved (Eq. 1) and integrated step by step, as the
+ * paper's simulated flights do (Sec. IV-A).
+ * ------------------------------------------------------------------------------------------ */
+
+typedef struct {
+    double goal[3];             /* goal position, world metres */
+    double alpha, beta;         /* attractor gain and damping (> 0) */
+    double dt;                  /* integration step, s (> 0) */
+    int32_t max_steps;          /* >= 0 */
+    double goal_tol;            /* success radius around the goal, m (>= 0) */
+} rmpc_rollout_params;
+
+#define RMPC_ROLLOUT_GOAL 1u       /* the state came within goal_tol of the goal */
+#define RMPC_ROLLOUT_COLLISION 2u  /* the state's voxel is occupied */
+#define RMPC_ROLLOUT_LEFT_GRID 3u  /* the state left the grid */
+#define RMPC_ROLLOUT_TIMEOUT 4u    /* max_steps steps taken */
+
+typedef struct {
+    uint32_t status;            /* RMPC_ROLLOUT_* */
+    int32_t n_steps;            /* integration steps taken */
+    double smoothness;          /* mean of 1 - angle / pi between consecutive displacements
+                                   (1: straight; 1 with fewer than two non-zero steps) */
+    double path_length_m;
+    double x[3], v[3];          /* final state */
+} rmpc_rollout_result;
+
+/*
+ * rmpc_rollout -- fly from (x0, v0) toward rp->goal.  Each step k: stop when within goal_tol of
+ * the goal (RMPC_ROLLOUT_GOAL) or outside the grid (RMPC_ROLLOUT_LEFT_GRID); run the query of
+ * (x_k, v_k) with n_rays rays (rmpc_query) and stop when its voxel is occupied
+ * (RMPC_ROLLOUT_COLLISION); then a_k = (I + A)^-1 (f_a + b) in float64, with A, b the query's
+ * sums and f_a = alpha s(goal - x_k) - beta v_k, and v_{k+1} = v_k + a_k dt,
+ * x_{k+1} = x_k + v_{k+1} dt.  After max_steps steps the status is RMPC_ROLLOUT_TIMEOUT (or GOAL
+ * if the last state is within goal_tol).
+ *   traj_host: NULL, or a host array of (max_steps + 1) x 6 doubles receiving x, v of every state
+ *     (row k = state k; rows past out->n_steps are left untouched).
+ *   out: the outcome.  Blocking (one query per step).
+ * Errors: those of rmpc_query other than RMPC_E_OUT_OF_BOUNDS; RMPC_E_INVALID for bad rp.
+ */
+rmpc_status rmpc_rollout(rmpc_ctx *ctx, int32_t map_id, const double x0[3], const double v0[3], int32_t n_rays,
+                         const rmpc_params *params, const rmpc_rollout_params *rp, void *hip_stream,
+                         double *traj_host, rmpc_rollout_result *out);
+
 /* rmpc_last_error -- text of the calling thread's last error ("" if none). */
 const char *rmpc_last_error(void);
 

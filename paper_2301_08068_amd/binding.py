@@ -84,6 +84,18 @@ _lib = C.CDLL(LIB_PATH)
 _P = C.POINTER
 _lib.rmpc_last_error.restype = C.c_char_p
 _lib.rmpc_last_error.argtypes = []
+class RolloutParams(C.Structure):
+    _fields_ = [("goal", C.c_double * 3), ("alpha", C.c_double), ("beta", C.c_double), ("dt", C.c_double),
+                ("max_steps", C.c_int32), ("goal_tol", C.c_double)]
+
+
+class RolloutResult(C.Structure):
+    _fields_ = [("status", C.c_uint32), ("n_steps", C.c_int32), ("smoothness", C.c_double),
+                ("path_length_m", C.c_double), ("x", C.c_double * 3), ("v", C.c_double * 3)]
+
+
+ROLLOUT_GOAL, ROLLOUT_COLLISION, ROLLOUT_LEFT_GRID, ROLLOUT_TIMEOUT = 1, 2, 3, 4
+
 _SIGS = {
     "rmpc_create": [C.c_int, C.c_void_p, C.c_size_t, _P(C.c_void_p)],
     "rmpc_destroy": [C.c_void_p],
@@ -111,6 +123,8 @@ _SIGS = {
                             _P(C.c_int32)],
     "rmpc_server_stats": [C.c_void_p, _P(ServerCounters)],
     "rmpc_server_stop": [C.c_void_p],
+    "rmpc_rollout": [C.c_void_p, C.c_int32, _P(C.c_double), _P(C.c_double), C.c_int32, _P(Params),
+                     _P(RolloutParams), C.c_void_p, _P(C.c_double), _P(RolloutResult)],
 }
 for _name, _args in _SIGS.items():
     getattr(_lib, _name).argtypes = _args
@@ -192,6 +206,26 @@ def rmpc_query(ctx: int, map_id: int, x, v, n_rays: int, params: Dict[str, float
     _check(_lib.rmpc_query(C.c_void_p(ctx), map_id, _d3(x), _d3(v), int(n_rays), C.byref(ps),
                            C.c_void_p(_stream_ptr(stream)), C.byref(r)), "rmpc_query")
     return result_dict(r)
+
+
+def rmpc_rollout(ctx: int, map_id: int, x0, v0, n_rays: int, params: Dict[str, float], goal, alpha: float,
+                 beta: float, dt: float, max_steps: int, goal_tol: float, trajectory: bool = False,
+                 stream=None) -> Dict:
+    """Closed-loop rollout; with trajectory=True also returns the visited states x, v."""
+    rp = RolloutParams((C.c_double * 3)(*[float(g) for g in np.asarray(goal, np.float64).reshape(3)]),
+                       float(alpha), float(beta), float(dt), int(max_steps), float(goal_tol))
+    traj = np.zeros((int(max_steps) + 1, 6), np.float64) if trajectory else None
+    tp = traj.ctypes.data_as(_P(C.c_double)) if traj is not None else None
+    r = RolloutResult()
+    ps = params_struct(params)
+    _check(_lib.rmpc_rollout(C.c_void_p(ctx), int(map_id), _d3(x0), _d3(v0), int(n_rays), C.byref(ps),
+                             C.byref(rp), C.c_void_p(_stream_ptr(stream)), tp, C.byref(r)), "rmpc_rollout")
+    out = dict(status=r.status, n_steps=r.n_steps, smoothness=r.smoothness, path_length=r.path_length_m,
+               x_final=np.array(r.x[:]), v_final=np.array(r.v[:]))
+    if traj is not None:
+        out["x"] = traj[:r.n_steps + 1, :3].copy()
+        out["v"] = traj[:r.n_steps + 1, 3:].copy()
+    return out
 
 
 class PreparedQuery:
@@ -423,6 +457,11 @@ class Context:
 
     def directions(self, n: int) -> np.ndarray:
         return rmpc_directions(self.ptr, n)
+
+    def rollout(self, map_id: int, x0, v0, n_rays: int, params: Dict[str, float], goal, alpha: float,
+                beta: float, dt: float, max_steps: int, goal_tol: float, trajectory: bool = False) -> Dict:
+        return rmpc_rollout(self.ptr, map_id, x0, v0, n_rays, params, goal, alpha, beta, dt, max_steps,
+                            goal_tol, trajectory, stream=self.stream)
 
     def query_batch(self, queries, map_params=None, scan_params=None) -> list:
         """queries: list of dicts (see query_descs); scan points as cuda float32 tensors under

@@ -1,0 +1,130 @@
+"""GPU closed-loop rollouts (rmpc_rollout) against the oracle's: the same trajectory on an empty
+map, the oracle's acceleration at every sampled state of a GPU trajectory among obstacles, the
+same outcome in a collision case, and the edge cases of the call."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from paper_2301_08068_amd import workloads as W  # noqa: E402
+
+P = W.params("static", max_range=5.0)
+ALPHA, BETA, DT = 10.0, 15.0, 0.01
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2301_08068_amd import binding
+    c = binding.Context(0, arena_bytes=1 << 30)
+    yield c
+    c.close()
+
+
+def _oracle_accel(om, x, v, n, goal):
+    """The oracle's combined acceleration and the error scale of the GPU's: (I + S)^-1 has norm
+    <= 1, so errors dS, db of the sums move a by at most |db| + |dS| |a|."""
+    q = oracle.query(om, x, v, n, P, nthreads=8)
+    a = np.linalg.solve(np.eye(3) + q["S"], oracle.attractor(goal, x, v, ALPHA, BETA, P["c"]) + q["b"])
+    return a, np.linalg.norm(q["b"]) + np.linalg.norm(q["S"], 2) * np.linalg.norm(a)
+
+
+def test_empty_map_matches_oracle_trajectory(ctx):
+    t = np.ones((40, 40, 40), np.float32)
+    mid = ctx.upload(t, 0.1, np.zeros(3), "f32")
+    om = oracle.OracleMap(t, 0.1, np.zeros(3), "f32")
+    try:
+        x0, v0, goal = np.array([0.55, 1.3, 2.2]), np.array([0.2, -0.4, 0.1]), np.array([3.4, 2.9, 1.1])
+        g = ctx.rollout(mid, x0, v0, 1024, P, goal, ALPHA, BETA, DT, 800, 0.05, trajectory=True)
+        o = oracle.rollout(om, x0, v0, 1024, P, goal, ALPHA, BETA, DT, 800, 0.05)
+        from paper_2301_08068_amd import binding as B
+        assert g["status"] == o["status"] == B.ROLLOUT_GOAL
+        assert g["n_steps"] == o["n_steps"]
+        assert np.allclose(g["x"], o["x"], rtol=0, atol=1e-9)
+        assert np.allclose(g["v"], o["v"], rtol=0, atol=1e-9)
+        assert abs(g["smoothness"] - o["smoothness"]) < 1e-9
+        assert abs(g["path_length"] - o["path_length"]) < 1e-9
+    finally:
+        ctx.release(mid)
+
+
+def test_obstacle_map_accelerations_match_oracle(ctx, tiny_map):
+    """Among obstacles, every 5th state of a GPU trajectory (and its last) gets the oracle's
+    combined acceleration, to 1e-5 of the size of the ray sums (their float32 compensated
+    accumulation is good to about 3e-7 of the largest entry)."""
+    from paper_2301_08068_amd import binding as B
+    mid = ctx.upload(tiny_map.tsdf, tiny_map.voxel_m, tiny_map.origin_m, "f32")
+    om = oracle.OracleMap.from_voxelmap(tiny_map)
+    try:
+        done = 0
+        for seed in range(40, 60):
+            x0, _ = W.free_state(tiny_map, seed)
+            goal, _ = W.free_state(tiny_map, seed + 1000)
+            if np.linalg.norm(goal - x0) < 2.0:
+                continue
+            g = ctx.rollout(mid, x0, np.zeros(3), 1024, P, goal, ALPHA, BETA, DT, 300, 0.1, trajectory=True)
+            xs, vs = g["x"], g["v"]
+            ks = sorted(set(range(0, g["n_steps"], 5)) | {g["n_steps"] - 1}) if g["n_steps"] > 0 else []
+            for k in ks:
+                a_g = (vs[k + 1] - vs[k]) / DT
+                a_o, scale = _oracle_accel(om, xs[k], vs[k], 1024, goal)
+                assert np.linalg.norm(a_g - a_o) <= 1e-5 * scale + 1e-9, (seed, k, a_g, a_o)
+            # the outcome is consistent with the oracle's reading of the final state
+            xf, vf = xs[-1], vs[-1]
+            if g["status"] == B.ROLLOUT_GOAL:
+                assert np.linalg.norm(xf - goal) <= 0.1
+            elif g["status"] == B.ROLLOUT_COLLISION:
+                assert oracle.query(om, xf, vf, 64, P)["flags"] & oracle.Q_IN_COLLISION
+            done += 1
+            if done == 4:
+                break
+        assert done == 4
+    finally:
+        ctx.release(mid)
+
+
+def test_collision_matches_oracle(ctx):
+    """A wall and no obstacle force: GPU and oracle fly into the wall and stop at the same step."""
+    from paper_2301_08068_amd import binding as B
+    t = np.ones((40, 40, 40), np.float32)
+    t[:, :, 20] = -0.05
+    mid = ctx.upload(t, 0.1, np.zeros(3), "f32")
+    om = oracle.OracleMap(t, 0.1, np.zeros(3), "f32")
+    p = dict(P, eta_rep=0.0, eta_damp=0.0)
+    try:
+        x0, goal = [0.55, 2.05, 2.05], [3.5, 2.05, 2.05]
+        g = ctx.rollout(mid, x0, [0, 0, 0], 64, p, goal, ALPHA, BETA, DT, 2000, 0.05)
+        o = oracle.rollout(om, x0, [0, 0, 0], 64, p, goal, ALPHA, BETA, DT, 2000, 0.05)
+        assert g["status"] == o["status"] == B.ROLLOUT_COLLISION
+        assert g["n_steps"] == o["n_steps"]
+        assert np.allclose(g["x_final"], o["x"][-1], rtol=0, atol=1e-9)
+    finally:
+        ctx.release(mid)
+
+
+def test_rollout_edge_cases(ctx, tiny_map):
+    from paper_2301_08068_amd import binding as B
+    mid = ctx.upload(tiny_map.tsdf, tiny_map.voxel_m, tiny_map.origin_m, "f32")
+    try:
+        x0, _ = W.free_state(tiny_map, 7)
+        # start at the goal: no step
+        r = ctx.rollout(mid, x0, [0, 0, 0], 256, P, x0, ALPHA, BETA, DT, 50, 0.01)
+        assert r["status"] == B.ROLLOUT_GOAL and r["n_steps"] == 0 and r["smoothness"] == 1.0
+        # max_steps = 0
+        r = ctx.rollout(mid, x0, [0, 0, 0], 256, P, x0 + 1.0, ALPHA, BETA, DT, 0, 0.01)
+        assert r["status"] == B.ROLLOUT_TIMEOUT and r["n_steps"] == 0
+        # a start outside the grid ends at once
+        r = ctx.rollout(mid, [-1.0, 0.5, 0.5], [0, 0, 0], 256, P, x0, ALPHA, BETA, DT, 50, 0.01)
+        assert r["status"] == B.ROLLOUT_LEFT_GRID and r["n_steps"] == 0
+        # invalid parameters are refused
+        for kw in (dict(alpha=0.0), dict(beta=-1.0), dict(dt=0.0), dict(max_steps=-1), dict(goal_tol=float("nan"))):
+            args = dict(alpha=ALPHA, beta=BETA, dt=DT, max_steps=10, goal_tol=0.01)
+            args.update(kw)
+            with pytest.raises(B.RmpcError) as e:
+                ctx.rollout(mid, x0, [0, 0, 0], 256, P, x0 + 1.0, **args)
+            assert e.value.status == B.RMPC_E_INVALID
+    finally:
+        ctx.release(mid)
