@@ -300,12 +300,67 @@ def serve_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def rollout_bench(args):
+    """Closed-loop flights (ray policy + goal attractor, 100 Hz steps) between seeded free start
+    and goal states at least 5 m apart on the 400^3 map, for several ray counts: success rate,
+    path smoothness and time per step (one blocking query plus the float64 update)."""
+    import numpy as np
+    from paper_2301_08068_amd import binding
+    from paper_2301_08068_amd import workloads as W
+    vm = W.paper_map(2)
+    params = W.params("static", max_range=10.0)
+    alpha, beta, dt, max_steps, tol = 10.0, 15.0, 0.01, 6000, 0.2
+    ctx = binding.Context(0, arena_bytes=1 << 30)
+    mid = ctx.upload(vm.tsdf, vm.voxel_m, vm.origin_m, "f32")
+    pairs, k = [], 0
+    while len(pairs) < args.rollouts:
+        x0, _ = W.free_state(vm, 600 + k)
+        goal, _ = W.free_state(vm, 900 + k)
+        k += 1
+        if np.linalg.norm(goal - x0) >= 5.0:
+            pairs.append((x0, goal))
+    ctx.rollout(mid, pairs[0][0], np.zeros(3), 1024, params, pairs[0][1], alpha, beta, dt, 50, tol)   # warm
+    rows = []
+    # the ray sums as the paper writes them (weight 1), and weighted as if 1024 rays were cast
+    for weighting in ("as_written", "per_1024_rays"):
+        for n in (16, 64, 256, 1024, 4096, 65536):
+            w = 1.0 if weighting == "as_written" else 1024.0 / n
+            res, t0 = [], time.perf_counter()
+            for x0, goal in pairs:
+                res.append(ctx.rollout(mid, x0, np.zeros(3), n, params, goal, alpha, beta, dt, max_steps, tol,
+                                       ray_weight=w))
+            el = time.perf_counter() - t0
+            steps = sum(r["n_steps"] for r in res)
+            ok = [r for r in res if r["status"] == binding.ROLLOUT_GOAL]
+            row = {"ray_weighting": weighting, "rays": n, "success_rate": len(ok) / len(res),
+                   "collisions": sum(r["status"] == binding.ROLLOUT_COLLISION for r in res),
+                   "timeouts": sum(r["status"] == binding.ROLLOUT_TIMEOUT for r in res),
+                   "smoothness_mean": float(np.mean([r["smoothness"] for r in ok])) if ok else None,
+                   "smoothness_p10": float(np.percentile([r["smoothness"] for r in ok], 10)) if ok else None,
+                   "steps": steps, "ms_per_step": 1e3 * el / max(steps, 1)}
+            rows.append(row)
+            print(json.dumps({"progress": row}), file=sys.stderr, flush=True)
+    ctx.close()
+    best = rows[5]
+    out = {"metric": "closed-loop rollout success rate and smoothness vs rays per query",
+           "value": best["success_rate"], "unit": "fraction of flights reaching the goal", "n_gpus": 1,
+           "steps": int(sum(r["steps"] for r in rows)), "warmup": 1, "ms_per_step": best["ms_per_step"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": f"{len(pairs)} flights between seeded free states >= 5 m apart on the 400^3 "
+                                  "f32 map (0.05 m, map seed 2); static-map policy parameters, attractor "
+                                  f"alpha {alpha}, beta {beta}; dt {dt} s, at most {max_steps} steps, goal "
+                                  f"radius {tol} m", "per_ray_count": rows}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=30)
-    ap.add_argument("--config", default="paper", choices=sorted(CONFIGS) + ["batch", "serve"])
+    ap.add_argument("--config", default="paper", choices=sorted(CONFIGS) + ["batch", "serve", "rollout"])
+    ap.add_argument("--rollouts", type=int, default=24, help="rollout config: flights per ray count")
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--serve-slots", type=int, default=3)
     ap.add_argument("--lookahead", type=int, default=0, help="query launch: steps planned per round (4, 8, 16)")
@@ -344,6 +399,9 @@ def main():
         return
     if args.config == "serve":
         serve_bench(args)
+        return
+    if args.config == "rollout":
+        rollout_bench(args)
         return
 
     kind, enc, seed, n_rays, rmax = CONFIGS[args.config]

@@ -359,6 +359,9 @@ typedef struct {
     double dt;                  /* integration step, s (> 0) */
     int32_t max_steps;          /* >= 0 */
     double goal_tol;            /* success radius around the goal, m (>= 0) */
+    double ray_weight;          /* >= 0: multiplies the ray sums A, b before the attractor is
+                                   added (1: Eq. 1 as written; N_ref / n_rays weighs the ray
+                                   policy as if N_ref rays were cast) */
 } rmpc_rollout_params;
 
 #define RMPC_ROLLOUT_GOAL 1u       /* the state came within goal_tol of the goal */
@@ -379,8 +382,8 @@ typedef struct {
  * rmpc_rollout -- fly from (x0, v0) toward rp->goal.  Each step k: stop when within goal_tol of
  * the goal (RMPC_ROLLOUT_GOAL) or outside the grid (RMPC_ROLLOUT_LEFT_GRID); run the query of
  * (x_k, v_k) with n_rays rays (rmpc_query) and stop when its voxel is occupied
- * (RMPC_ROLLOUT_COLLISION); then a_k = (I + A)^-1 (f_a + b) in float64, with A, b the query's
- * sums and f_a = alpha s(goal - x_k) - beta v_k, and v_{k+1} = v_k + a_k dt,
+ * (RMPC_ROLLOUT_COLLISION); then a_k = (I + w A)^-1 (f_a + w b) in float64, with A, b the
+ * query's sums, w = ray_weight and f_a = alpha s(goal - x_k) - beta v_k, and v_{k+1} = v_k + a_k dt,
  * x_{k+1} = x_k + v_{k+1} dt.  After max_steps steps the status is RMPC_ROLLOUT_TIMEOUT (or GOAL
  * if the last state is within goal_tol).
  *   traj_host: NULL, or a host array of (max_steps + 1) x 6 doubles receiving x, v of every state

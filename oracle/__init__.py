@@ -241,10 +241,11 @@ def smoothness(xs: np.ndarray) -> float:
 
 
 def rollout(m: OracleMap, x0, v0, n_rays: int, p: Dict[str, float], goal, alpha: float, beta: float,
-            dt: float, max_steps: int, goal_tol: float, nthreads: int = 1) -> Dict:
+            dt: float, max_steps: int, goal_tol: float, nthreads: int = 1, ray_weight: float = 1.0) -> Dict:
     """Each step k: stop when within goal_tol of the goal or outside the grid; query the state
-    (stop when its voxel is occupied); a_k = (I + S)^-1 (f_a + b) with S, b the ray sums and f_a
-    the attractor; v_{k+1} = v_k + a_k dt, x_{k+1} = x_k + v_{k+1} dt (semi-implicit Euler)."""
+    (stop when its voxel is occupied); a_k = (I + w S)^-1 (f_a + w b) with S, b the ray sums,
+    w = ray_weight (1: Eq. 1 as written) and f_a the attractor; v_{k+1} = v_k + a_k dt,
+    x_{k+1} = x_k + v_{k+1} dt (semi-implicit Euler)."""
     x = np.array(x0, np.float64)
     v = np.array(v0, np.float64)
     xs, vs, acc = [x.copy()], [v.copy()], []
@@ -261,7 +262,8 @@ def rollout(m: OracleMap, x0, v0, n_rays: int, p: Dict[str, float], goal, alpha:
         if q["flags"] & Q_IN_COLLISION:
             status = ROLLOUT_COLLISION
             break
-        a = np.linalg.solve(np.eye(3) + q["S"], attractor(goal, x, v, alpha, beta, p["c"]) + q["b"])
+        a = np.linalg.solve(np.eye(3) + ray_weight * q["S"],
+                            attractor(goal, x, v, alpha, beta, p["c"]) + ray_weight * q["b"])
         v = v + a * dt
         x = x + v * dt
         xs.append(x.copy())

@@ -86,7 +86,7 @@ _lib.rmpc_last_error.restype = C.c_char_p
 _lib.rmpc_last_error.argtypes = []
 class RolloutParams(C.Structure):
     _fields_ = [("goal", C.c_double * 3), ("alpha", C.c_double), ("beta", C.c_double), ("dt", C.c_double),
-                ("max_steps", C.c_int32), ("goal_tol", C.c_double)]
+                ("max_steps", C.c_int32), ("goal_tol", C.c_double), ("ray_weight", C.c_double)]
 
 
 class RolloutResult(C.Structure):
@@ -210,10 +210,10 @@ def rmpc_query(ctx: int, map_id: int, x, v, n_rays: int, params: Dict[str, float
 
 def rmpc_rollout(ctx: int, map_id: int, x0, v0, n_rays: int, params: Dict[str, float], goal, alpha: float,
                  beta: float, dt: float, max_steps: int, goal_tol: float, trajectory: bool = False,
-                 stream=None) -> Dict:
+                 stream=None, ray_weight: float = 1.0) -> Dict:
     """Closed-loop rollout; with trajectory=True also returns the visited states x, v."""
     rp = RolloutParams((C.c_double * 3)(*[float(g) for g in np.asarray(goal, np.float64).reshape(3)]),
-                       float(alpha), float(beta), float(dt), int(max_steps), float(goal_tol))
+                       float(alpha), float(beta), float(dt), int(max_steps), float(goal_tol), float(ray_weight))
     traj = np.zeros((int(max_steps) + 1, 6), np.float64) if trajectory else None
     tp = traj.ctypes.data_as(_P(C.c_double)) if traj is not None else None
     r = RolloutResult()
@@ -459,9 +459,10 @@ class Context:
         return rmpc_directions(self.ptr, n)
 
     def rollout(self, map_id: int, x0, v0, n_rays: int, params: Dict[str, float], goal, alpha: float,
-                beta: float, dt: float, max_steps: int, goal_tol: float, trajectory: bool = False) -> Dict:
+                beta: float, dt: float, max_steps: int, goal_tol: float, trajectory: bool = False,
+                ray_weight: float = 1.0) -> Dict:
         return rmpc_rollout(self.ptr, map_id, x0, v0, n_rays, params, goal, alpha, beta, dt, max_steps,
-                            goal_tol, trajectory, stream=self.stream)
+                            goal_tol, trajectory, stream=self.stream, ray_weight=ray_weight)
 
     def query_batch(self, queries, map_params=None, scan_params=None) -> list:
         """queries: list of dicts (see query_descs); scan points as cuda float32 tensors under

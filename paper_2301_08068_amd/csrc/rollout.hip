@@ -79,7 +79,7 @@ rmpc_status rmpc_rollout(rmpc_ctx *ctx, int32_t map_id, const double x0[3], cons
     if (!finite3(x0) || !finite3(v0) || !finite3(rp->goal)) return fail(RMPC_E_INVALID, "state or goal not finite");
     if (!(rp->alpha > 0.0) || !(rp->beta > 0.0) || !(rp->dt > 0.0) || !std::isfinite(rp->alpha) ||
         !std::isfinite(rp->beta) || !std::isfinite(rp->dt) || rp->max_steps < 0 || !(rp->goal_tol >= 0.0) ||
-        !std::isfinite(rp->goal_tol))
+        !std::isfinite(rp->goal_tol) || !(rp->ray_weight >= 0.0) || !std::isfinite(rp->ray_weight))
         return fail(RMPC_E_INVALID, "rollout parameters out of range");
     double x[3], v[3];
     std::memcpy(x, x0, sizeof x);
@@ -106,12 +106,13 @@ rmpc_status rmpc_rollout(rmpc_ctx *ctx, int32_t map_id, const double x0[3], cons
             status = RMPC_ROLLOUT_COLLISION;
             break;
         }
-        // f_a = alpha s(goal - x) - beta v (Eq. 2), metric I; a = (I + A)^-1 (f_a + b) (Eq. 1)
-        double u[3], s[3], r[3], a[3];
+        // f_a = alpha s(goal - x) - beta v (Eq. 2), metric I; a = (I + w A)^-1 (f_a + w b) (Eq. 1)
+        double u[3], s[3], r[3], a[3], wA[9];
         for (int i = 0; i < 3; ++i) u[i] = rp->goal[i] - x[i];
         soft_normalize(u, params->c, s);
-        for (int i = 0; i < 3; ++i) r[i] = rp->alpha * s[i] - rp->beta * v[i] + q.b[i];
-        if (!solve_identity_plus(q.A, r, a)) return fail(RMPC_E_HIP, "metric sum is not positive semi-definite");
+        for (int i = 0; i < 3; ++i) r[i] = rp->alpha * s[i] - rp->beta * v[i] + rp->ray_weight * q.b[i];
+        for (int i = 0; i < 9; ++i) wA[i] = rp->ray_weight * q.A[i];
+        if (!solve_identity_plus(wA, r, a)) return fail(RMPC_E_HIP, "metric sum is not positive semi-definite");
         double seg[3];
         for (int i = 0; i < 3; ++i) {
             v[i] += a[i] * rp->dt;

@@ -24,12 +24,12 @@ def ctx():
     c.close()
 
 
-def _oracle_accel(om, x, v, n, goal):
-    """The oracle's combined acceleration and the error scale of the GPU's: (I + S)^-1 has norm
-    <= 1, so errors dS, db of the sums move a by at most |db| + |dS| |a|."""
+def _oracle_accel(om, x, v, n, goal, w=1.0):
+    """The oracle's combined acceleration and the error scale of the GPU's: (I + w S)^-1 has
+    norm <= 1, so errors dS, db of the sums move a by at most w (|db| + |dS| |a|)."""
     q = oracle.query(om, x, v, n, P, nthreads=8)
-    a = np.linalg.solve(np.eye(3) + q["S"], oracle.attractor(goal, x, v, ALPHA, BETA, P["c"]) + q["b"])
-    return a, np.linalg.norm(q["b"]) + np.linalg.norm(q["S"], 2) * np.linalg.norm(a)
+    a = np.linalg.solve(np.eye(3) + w * q["S"], oracle.attractor(goal, x, v, ALPHA, BETA, P["c"]) + w * q["b"])
+    return a, w * (np.linalg.norm(q["b"]) + np.linalg.norm(q["S"], 2) * np.linalg.norm(a))
 
 
 def test_empty_map_matches_oracle_trajectory(ctx):
@@ -51,7 +51,8 @@ def test_empty_map_matches_oracle_trajectory(ctx):
         ctx.release(mid)
 
 
-def test_obstacle_map_accelerations_match_oracle(ctx, tiny_map):
+@pytest.mark.parametrize("w", [1.0, 0.25])
+def test_obstacle_map_accelerations_match_oracle(ctx, tiny_map, w):
     """Among obstacles, every 5th state of a GPU trajectory (and its last) gets the oracle's
     combined acceleration, to 1e-5 of the size of the ray sums (their float32 compensated
     accumulation is good to about 3e-7 of the largest entry)."""
@@ -65,12 +66,13 @@ def test_obstacle_map_accelerations_match_oracle(ctx, tiny_map):
             goal, _ = W.free_state(tiny_map, seed + 1000)
             if np.linalg.norm(goal - x0) < 2.0:
                 continue
-            g = ctx.rollout(mid, x0, np.zeros(3), 1024, P, goal, ALPHA, BETA, DT, 300, 0.1, trajectory=True)
+            g = ctx.rollout(mid, x0, np.zeros(3), 1024, P, goal, ALPHA, BETA, DT, 300, 0.1, trajectory=True,
+                            ray_weight=w)
             xs, vs = g["x"], g["v"]
             ks = sorted(set(range(0, g["n_steps"], 5)) | {g["n_steps"] - 1}) if g["n_steps"] > 0 else []
             for k in ks:
                 a_g = (vs[k + 1] - vs[k]) / DT
-                a_o, scale = _oracle_accel(om, xs[k], vs[k], 1024, goal)
+                a_o, scale = _oracle_accel(om, xs[k], vs[k], 1024, goal, w)
                 assert np.linalg.norm(a_g - a_o) <= 1e-5 * scale + 1e-9, (seed, k, a_g, a_o)
             # the outcome is consistent with the oracle's reading of the final state
             xf, vf = xs[-1], vs[-1]
@@ -120,7 +122,8 @@ def test_rollout_edge_cases(ctx, tiny_map):
         r = ctx.rollout(mid, [-1.0, 0.5, 0.5], [0, 0, 0], 256, P, x0, ALPHA, BETA, DT, 50, 0.01)
         assert r["status"] == B.ROLLOUT_LEFT_GRID and r["n_steps"] == 0
         # invalid parameters are refused
-        for kw in (dict(alpha=0.0), dict(beta=-1.0), dict(dt=0.0), dict(max_steps=-1), dict(goal_tol=float("nan"))):
+        for kw in (dict(alpha=0.0), dict(beta=-1.0), dict(dt=0.0), dict(max_steps=-1), dict(goal_tol=float("nan")),
+                   dict(ray_weight=-1.0)):
             args = dict(alpha=ALPHA, beta=BETA, dt=DT, max_steps=10, goal_tol=0.01)
             args.update(kw)
             with pytest.raises(B.RmpcError) as e:

@@ -79,3 +79,17 @@ def test_collision_is_detected():
     r2 = oracle.rollout(om, [0.55, 2.05, 2.05], [0, 0, 0], 256, P, [3.5, 2.05, 2.05], ALPHA, BETA, DT, 600, 0.05)
     assert r2["status"] != oracle.ROLLOUT_COLLISION
     assert r2["x"][:, 0].max() < 2.0
+
+
+def test_zero_ray_weight_ignores_obstacles():
+    """ray_weight = 0 removes the ray policy: the flight toward a goal behind a wall is the
+    free-space flight (bit for bit) until it enters the wall."""
+    t = np.ones((40, 40, 40), np.float32)
+    t[:, :, 20] = -0.05
+    om = oracle.OracleMap(t, 0.1, np.zeros(3), "f32")
+    free = oracle.OracleMap(np.ones((40, 40, 40), np.float32), 0.1, np.zeros(3), "f32")
+    x0, goal = [0.55, 2.05, 2.05], [3.5, 2.05, 2.05]
+    r = oracle.rollout(om, x0, [0, 0, 0], 256, P, goal, ALPHA, BETA, DT, 2000, 0.05, ray_weight=0.0)
+    f = oracle.rollout(free, x0, [0, 0, 0], 256, P, goal, ALPHA, BETA, DT, r["n_steps"], 0.05)
+    assert r["status"] == oracle.ROLLOUT_COLLISION
+    assert np.array_equal(r["x"], f["x"][: r["n_steps"] + 1])
