@@ -362,6 +362,8 @@ typedef struct {
     double ray_weight;          /* >= 0: multiplies the ray sums A, b before the attractor is
                                    added (1: Eq. 1 as written; N_ref / n_rays weighs the ray
                                    policy as if N_ref rays were cast) */
+    int32_t smooth_every;       /* >= 1: the smoothness is measured on the states every
+                                   smooth_every steps (1: every integration step) */
 } rmpc_rollout_params;
 
 #define RMPC_ROLLOUT_GOAL 1u       /* the state came within goal_tol of the goal */
@@ -372,8 +374,10 @@ typedef struct {
 typedef struct {
     uint32_t status;            /* RMPC_ROLLOUT_* */
     int32_t n_steps;            /* integration steps taken */
-    double smoothness;          /* mean of 1 - angle / pi between consecutive displacements
-                                   (1: straight; 1 with fewer than two non-zero steps) */
+    double smoothness;          /* mean of 1 - angle / pi between consecutive non-zero
+                                   displacements of the sampled states x_0, x_m, x_2m, ...
+                                   (m = smooth_every; 1 with fewer than two such displacements;
+                                   Sec. IV-B's path smoothness) */
     double path_length_m;
     double x[3], v[3];          /* final state */
 } rmpc_rollout_result;
@@ -394,6 +398,29 @@ typedef struct {
 rmpc_status rmpc_rollout(rmpc_ctx *ctx, int32_t map_id, const double x0[3], const double v0[3], int32_t n_rays,
                          const rmpc_params *params, const rmpc_rollout_params *rp, void *hip_stream,
                          double *traj_host, rmpc_rollout_result *out);
+
+/* A flight of a batched rollout. */
+typedef struct {
+    int32_t map_id;
+    int32_t n_rays;             /* rays per query, 1..65536 */
+    double x0[3], v0[3];        /* start state */
+    rmpc_rollout_params rp;     /* goal, gains, step, limits of this flight */
+} rmpc_flight;
+
+/*
+ * rmpc_rollout_batch -- n independent flights (each as rmpc_rollout defines it) advanced
+ * together: every step runs the queries of all flights still flying as one rmpc_query_batch
+ * launch, so n flights cost about as many launches as the longest one has steps.
+ *   flights[n], out[n]: host arrays, 1 <= n.  A flight leaves the batch when it ends; the
+ *   others are unaffected.
+ * Each flight's outcome is bit for bit the one rmpc_rollout gives when the batch launch
+ * configuration (RMPC_CONFIG_BATCH) equals the query configuration (RMPC_CONFIG_QUERY).
+ * Every flight is validated first (unknown map, n_rays, parameters); any invalid one fails the
+ * call with its index in the message and nothing is written.  Blocking.
+ * Errors: RMPC_E_INVALID, RMPC_E_NOMAP, and those of rmpc_query_batch.
+ */
+rmpc_status rmpc_rollout_batch(rmpc_ctx *ctx, const rmpc_flight *flights, int32_t n, const rmpc_params *params,
+                               void *hip_stream, rmpc_rollout_result *out);
 
 /* rmpc_last_error -- text of the calling thread's last error ("" if none). */
 const char *rmpc_last_error(void);

@@ -228,10 +228,11 @@ def attractor(goal, x, v, alpha: float, beta: float, c: float) -> np.ndarray:
         - beta * np.asarray(v, np.float64)
 
 
-def smoothness(xs: np.ndarray) -> float:
-    """Mean angular similarity 1 - acos(cos angle)/pi between consecutive displacement segments
-    of a path (1.0: straight; the path measure of Sec. IV-A); 1.0 with fewer than two segments."""
-    seg = np.diff(np.asarray(xs, np.float64), axis=0)
+def smoothness(xs: np.ndarray, every: int = 1) -> float:
+    """Mean angular similarity 1 - acos(cos angle)/pi between consecutive non-zero displacement
+    segments of a path sampled at every ``every``-th point xs[0], xs[every], ... (1.0: straight;
+    the path measure of Sec. IV-B); 1.0 with fewer than two segments."""
+    seg = np.diff(np.asarray(xs, np.float64)[::every], axis=0)
     seg = seg[np.linalg.norm(seg, axis=1) > 0.0]
     if len(seg) < 2:
         return 1.0
@@ -241,7 +242,8 @@ def smoothness(xs: np.ndarray) -> float:
 
 
 def rollout(m: OracleMap, x0, v0, n_rays: int, p: Dict[str, float], goal, alpha: float, beta: float,
-            dt: float, max_steps: int, goal_tol: float, nthreads: int = 1, ray_weight: float = 1.0) -> Dict:
+            dt: float, max_steps: int, goal_tol: float, nthreads: int = 1, ray_weight: float = 1.0,
+            smooth_every: int = 1) -> Dict:
     """Each step k: stop when within goal_tol of the goal or outside the grid; query the state
     (stop when its voxel is occupied); a_k = (I + w S)^-1 (f_a + w b) with S, b the ray sums,
     w = ray_weight (1: Eq. 1 as written) and f_a the attractor; v_{k+1} = v_k + a_k dt,
@@ -274,4 +276,4 @@ def rollout(m: OracleMap, x0, v0, n_rays: int, p: Dict[str, float], goal, alpha:
             status = ROLLOUT_GOAL
     xs = np.array(xs)
     return dict(status=status, n_steps=len(xs) - 1, x=xs, v=np.array(vs), a=np.array(acc).reshape(-1, 3),
-                smoothness=smoothness(xs), path_length=float(np.sum(np.linalg.norm(np.diff(xs, axis=0), axis=1))))
+                smoothness=smoothness(xs, smooth_every), path_length=float(np.sum(np.linalg.norm(np.diff(xs, axis=0), axis=1))))

@@ -80,13 +80,22 @@ class Result(C.Structure):
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run paper_2301_08068_amd/build.py")
+# The library finds the HIP runtime by soname (libamdhip64.so.7), which torch also ships: torch
+# must load first so that one runtime, torch's, serves both the arena/streams and the library.
+import torch  # noqa: E402,F401
 _lib = C.CDLL(LIB_PATH)
 _P = C.POINTER
 _lib.rmpc_last_error.restype = C.c_char_p
 _lib.rmpc_last_error.argtypes = []
 class RolloutParams(C.Structure):
     _fields_ = [("goal", C.c_double * 3), ("alpha", C.c_double), ("beta", C.c_double), ("dt", C.c_double),
-                ("max_steps", C.c_int32), ("goal_tol", C.c_double), ("ray_weight", C.c_double)]
+                ("max_steps", C.c_int32), ("goal_tol", C.c_double), ("ray_weight", C.c_double),
+                ("smooth_every", C.c_int32)]
+
+
+class Flight(C.Structure):
+    _fields_ = [("map_id", C.c_int32), ("n_rays", C.c_int32), ("x0", C.c_double * 3), ("v0", C.c_double * 3),
+                ("rp", RolloutParams)]
 
 
 class RolloutResult(C.Structure):
@@ -125,6 +134,7 @@ _SIGS = {
     "rmpc_server_stop": [C.c_void_p],
     "rmpc_rollout": [C.c_void_p, C.c_int32, _P(C.c_double), _P(C.c_double), C.c_int32, _P(Params),
                      _P(RolloutParams), C.c_void_p, _P(C.c_double), _P(RolloutResult)],
+    "rmpc_rollout_batch": [C.c_void_p, _P(Flight), C.c_int32, _P(Params), C.c_void_p, _P(RolloutResult)],
 }
 for _name, _args in _SIGS.items():
     getattr(_lib, _name).argtypes = _args
@@ -208,24 +218,52 @@ def rmpc_query(ctx: int, map_id: int, x, v, n_rays: int, params: Dict[str, float
     return result_dict(r)
 
 
+def rollout_params(goal, alpha: float, beta: float, dt: float, max_steps: int, goal_tol: float,
+                   ray_weight: float = 1.0, smooth_every: int = 1) -> RolloutParams:
+    return RolloutParams((C.c_double * 3)(*[float(g) for g in np.asarray(goal, np.float64).reshape(3)]),
+                         float(alpha), float(beta), float(dt), int(max_steps), float(goal_tol), float(ray_weight),
+                         int(smooth_every))
+
+
+def _rollout_dict(r: RolloutResult) -> Dict:
+    return dict(status=r.status, n_steps=r.n_steps, smoothness=r.smoothness, path_length=r.path_length_m,
+                x_final=np.array(r.x[:]), v_final=np.array(r.v[:]))
+
+
 def rmpc_rollout(ctx: int, map_id: int, x0, v0, n_rays: int, params: Dict[str, float], goal, alpha: float,
                  beta: float, dt: float, max_steps: int, goal_tol: float, trajectory: bool = False,
-                 stream=None, ray_weight: float = 1.0) -> Dict:
+                 stream=None, ray_weight: float = 1.0, smooth_every: int = 1) -> Dict:
     """Closed-loop rollout; with trajectory=True also returns the visited states x, v."""
-    rp = RolloutParams((C.c_double * 3)(*[float(g) for g in np.asarray(goal, np.float64).reshape(3)]),
-                       float(alpha), float(beta), float(dt), int(max_steps), float(goal_tol), float(ray_weight))
+    rp = rollout_params(goal, alpha, beta, dt, max_steps, goal_tol, ray_weight, smooth_every)
     traj = np.zeros((int(max_steps) + 1, 6), np.float64) if trajectory else None
     tp = traj.ctypes.data_as(_P(C.c_double)) if traj is not None else None
     r = RolloutResult()
     ps = params_struct(params)
     _check(_lib.rmpc_rollout(C.c_void_p(ctx), int(map_id), _d3(x0), _d3(v0), int(n_rays), C.byref(ps),
                              C.byref(rp), C.c_void_p(_stream_ptr(stream)), tp, C.byref(r)), "rmpc_rollout")
-    out = dict(status=r.status, n_steps=r.n_steps, smoothness=r.smoothness, path_length=r.path_length_m,
-               x_final=np.array(r.x[:]), v_final=np.array(r.v[:]))
+    out = _rollout_dict(r)
     if traj is not None:
         out["x"] = traj[:r.n_steps + 1, :3].copy()
         out["v"] = traj[:r.n_steps + 1, 3:].copy()
     return out
+
+
+def rmpc_rollout_batch(ctx: int, flights, params: Dict[str, float], stream=None) -> list:
+    """Batched rollout.  flights: dicts with map_id, n_rays, x0, v0, goal, alpha, beta, dt,
+    max_steps, goal_tol and optionally ray_weight, smooth_every."""
+    fs = (Flight * len(flights))()
+    for k, f in enumerate(flights):
+        fs[k].map_id = int(f["map_id"])
+        fs[k].n_rays = int(f["n_rays"])
+        fs[k].x0 = (C.c_double * 3)(*np.asarray(f["x0"], np.float64).reshape(3).tolist())
+        fs[k].v0 = (C.c_double * 3)(*np.asarray(f["v0"], np.float64).reshape(3).tolist())
+        fs[k].rp = rollout_params(f["goal"], f["alpha"], f["beta"], f["dt"], f["max_steps"], f["goal_tol"],
+                                  f.get("ray_weight", 1.0), f.get("smooth_every", 1))
+    out = (RolloutResult * len(flights))()
+    ps = params_struct(params)
+    _check(_lib.rmpc_rollout_batch(C.c_void_p(ctx), fs, len(flights), C.byref(ps), C.c_void_p(_stream_ptr(stream)),
+                                   out), "rmpc_rollout_batch")
+    return [_rollout_dict(r) for r in out]
 
 
 class PreparedQuery:
@@ -460,9 +498,13 @@ class Context:
 
     def rollout(self, map_id: int, x0, v0, n_rays: int, params: Dict[str, float], goal, alpha: float,
                 beta: float, dt: float, max_steps: int, goal_tol: float, trajectory: bool = False,
-                ray_weight: float = 1.0) -> Dict:
+                ray_weight: float = 1.0, smooth_every: int = 1) -> Dict:
         return rmpc_rollout(self.ptr, map_id, x0, v0, n_rays, params, goal, alpha, beta, dt, max_steps,
-                            goal_tol, trajectory, stream=self.stream, ray_weight=ray_weight)
+                            goal_tol, trajectory, stream=self.stream, ray_weight=ray_weight,
+                            smooth_every=smooth_every)
+
+    def rollout_batch(self, flights, params: Dict[str, float]) -> list:
+        return rmpc_rollout_batch(self.ptr, flights, params, stream=self.stream)
 
     def query_batch(self, queries, map_params=None, scan_params=None) -> list:
         """queries: list of dicts (see query_descs); scan points as cuda float32 tensors under

@@ -152,6 +152,16 @@ int segments_for(int32_t n_rays, double span, int lane_target_log2)
     return S;
 }
 
+bool grid_coords(const rmpc_map_desc &d, const double x[3], float g[3])
+{
+    const int32_t n[3] = {d.nx, d.ny, d.nz};
+    for (int a = 0; a < 3; ++a) {
+        g[a] = (float)((x[a] - d.origin_m[a]) / d.voxel_m);
+        if (!(g[a] >= 0.0f) || !(g[a] < (float)n[a])) return false;
+    }
+    return true;
+}
+
 // Validates the query state and fills the geometry part of RayArgs.
 rmpc_status setup_query(rmpc_ctx *ctx, int32_t map_id, const double x[3], int32_t n_rays,
                         const rmpc_params *params, const rmpc_launch_config &cfg, rmpc::RayArgs &A)
@@ -166,9 +176,10 @@ rmpc_status setup_query(rmpc_ctx *ctx, int32_t map_id, const double x[3], int32_
     const int32_t n[3] = {me.desc.nx, me.desc.ny, me.desc.nz};
     std::memset(&A, 0, sizeof A);
     uint32_t start_flags = 0;
+    float gc[3];
+    if (!grid_coords(me.desc, x, gc)) return fail(RMPC_E_OUT_OF_BOUNDS, "position outside the grid");
     for (int a = 0; a < 3; ++a) {
-        const float g = (float)((x[a] - me.desc.origin_m[a]) / me.desc.voxel_m);
-        if (!(g >= 0.0f) || !(g < (float)n[a])) return fail(RMPC_E_OUT_OF_BOUNDS, "position outside the grid");
+        const float g = gc[a];
         A.g[a] = g;
         A.v0[a] = (int32_t)std::floor(g);
         const double fr = (double)g - std::floor((double)g);

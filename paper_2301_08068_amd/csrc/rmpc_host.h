@@ -106,6 +106,9 @@ bool finite3(const double *p);
 rmpc_status check_params(const rmpc_params *p);
 rmpc_status check_config(const rmpc_launch_config *c);
 rmpc::PolicyF policy_f(const rmpc_params *p, const double v[3]);
+// Grid coordinates of a world position, (x - origin) / voxel rounded to float32 per axis;
+// false when one falls outside [0, n) (or is NaN).  The test every map query applies.
+bool grid_coords(const rmpc_map_desc &d, const double x[3], float g[3]);
 // Validate a map query and fill the geometry and policy-independent part of RayArgs.
 rmpc_status setup_query(rmpc_ctx *ctx, int32_t map_id, const double x[3], int32_t n_rays,
                         const rmpc_params *params, const rmpc_launch_config &cfg, rmpc::RayArgs &A);

@@ -162,15 +162,15 @@ def tiny_map(seed: int = 1) -> VoxelMap:
     return VoxelMap("tiny64", tsdf, h, np.zeros(3), prims, 0.3)
 
 
-def _random_obstacles(rng, n: int, lo: float, hi: float) -> List[Primitive]:
+def _random_obstacles(rng, n: int, lo: float, hi: float, size_scale: float = 1.0) -> List[Primitive]:
     prims: List[Primitive] = []
     for _ in range(n):
         c = rng.uniform(lo, hi, size=3)
         if rng.uniform() < 0.5:
-            r = rng.uniform(0.15, 1.0)
+            r = rng.uniform(0.15, 1.0) * size_scale
             prims.append(("sphere", float(c[0]), float(c[1]), float(c[2]), float(r)))
         else:
-            side = rng.uniform(0.3, 2.0, size=3)
+            side = rng.uniform(0.3, 2.0, size=3) * size_scale
             prims.append(("box", float(c[0]), float(c[1]), float(c[2]),
                           float(side[0] / 2), float(side[1] / 2), float(side[2] / 2)))
     return prims
@@ -194,6 +194,40 @@ def paper_map(seed: int = 2, n_cells: int = 400, voxel_m: float = 0.05,
     prims = _walls(extent, 0.25) + _random_obstacles(rng, n_prims, 0.05 * extent, 0.95 * extent)
     tsdf = build_tsdf((n_cells,) * 3, voxel_m, (0.0, 0.0, 0.0), prims, 0.3)
     return VoxelMap(f"paper{n_cells}_s{seed}", tsdf, voxel_m, np.zeros(3), prims, 0.3)
+
+
+def eval_map(seed: int, n_prims: int, n_cells: int = 200, voxel_m: float = 0.05,
+             size_scale: float = 1.3) -> VoxelMap:
+    """Map of the closed-loop evaluation (after Sec. IV-A: random spheres and boxes merged in a
+    10 m cube, up to 200 obstacles, about 45 % of the voxels occupied at 200).
+
+    200^3 voxels of 0.05 m, no walls; ``n_prims`` obstacles drawn as in ``paper_map`` with
+    every size multiplied by ``size_scale`` (1.3 gives about 0.45 occupied at 200 obstacles),
+    centres uniform in [0.5, 9.5]^3 m.
+    """
+    rng = np.random.default_rng(seed)
+    extent = n_cells * voxel_m
+    prims = _random_obstacles(rng, n_prims, 0.05 * extent, 0.95 * extent, size_scale)
+    tsdf = build_tsdf((n_cells,) * 3, voxel_m, (0.0, 0.0, 0.0), prims, 0.3)
+    return VoxelMap(f"eval{n_cells}_n{n_prims}_s{seed}", tsdf, voxel_m, np.zeros(3), prims, 0.3)
+
+
+def eval_pair(m: VoxelMap, seed: int, clearance_m: float = 0.3) -> Tuple[np.ndarray, np.ndarray]:
+    """Start and goal of one evaluation flight, on opposite sides of the cube: start x in
+    [3 %, 10 %] of the extent, goal x in [90 %, 97 %], y and z in [10 %, 90 %]; each redrawn
+    until its voxel is free and the analytic clearance is at least ``clearance_m``."""
+    rng = np.random.default_rng(seed)
+    ext = m.extent_m
+
+    def draw(lo_x, hi_x):
+        while True:
+            f = np.array([rng.uniform(lo_x, hi_x), rng.uniform(0.1, 0.9), rng.uniform(0.1, 0.9)])
+            x = m.origin_m + f * ext
+            if _is_free(m, x) and sdf_union(m.prims, x[None, :])[0] >= clearance_m:
+                return x
+
+    start = draw(0.03, 0.10)
+    return start, draw(0.90, 0.97)
 
 
 def occ_source_map(seed: int, n_cells: int = 256, voxel_m: float = 0.05,

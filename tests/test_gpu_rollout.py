@@ -107,6 +107,47 @@ def test_collision_matches_oracle(ctx):
         ctx.release(mid)
 
 
+def test_batch_equals_single_flights_bitwise(ctx, tiny_map):
+    """A batch of flights with different ray counts, weights, strides and outcomes (goal, grid
+    exit, zero steps, timeout) gives each flight exactly what rmpc_rollout gives it alone when
+    the batch launch uses the query launch configuration."""
+    from paper_2301_08068_amd import binding as B
+    qcfg = ctx.config(B.CONFIG_QUERY)
+    ctx.config(B.CONFIG_BATCH, lane_target_log2=qcfg["lane_target_log2"], lookahead=qcfg["lookahead"], use_graph=0)
+    mid = ctx.upload(tiny_map.tsdf, tiny_map.voxel_m, tiny_map.origin_m, "f32")
+    try:
+        flights = []
+        for k, seed in enumerate(range(70, 82)):
+            x0, v0 = W.free_state(tiny_map, seed)
+            goal, _ = W.free_state(tiny_map, seed + 500)
+            flights.append(dict(map_id=mid, n_rays=[64, 256, 1024, 4096][k % 4], x0=x0, v0=0.3 * v0, goal=goal,
+                                alpha=ALPHA, beta=BETA, dt=DT, max_steps=[300, 120, 0, 300][k % 4], goal_tol=0.1,
+                                ray_weight=[1.0, 0.25, 2.0][k % 3], smooth_every=[1, 5][k % 2]))
+        # a start outside the grid, and a start at the goal
+        flights.append(dict(flights[0], x0=[-0.5, 0.5, 0.5]))
+        flights.append(dict(flights[1], goal=flights[1]["x0"]))
+        res = ctx.rollout_batch(flights, P)
+        kinds = set()
+        for f, r in zip(flights, res):
+            a = ctx.rollout(f["map_id"], f["x0"], f["v0"], f["n_rays"], P, f["goal"], f["alpha"], f["beta"], f["dt"],
+                            f["max_steps"], f["goal_tol"], ray_weight=f["ray_weight"], smooth_every=f["smooth_every"])
+            assert r["status"] == a["status"] and r["n_steps"] == a["n_steps"], (f, r, a)
+            assert np.array_equal(r["x_final"], a["x_final"]) and np.array_equal(r["v_final"], a["v_final"])
+            assert r["smoothness"] == a["smoothness"] and r["path_length"] == a["path_length"]
+            kinds.add(r["status"])
+        assert {B.ROLLOUT_GOAL, B.ROLLOUT_LEFT_GRID, B.ROLLOUT_TIMEOUT} <= kinds
+        # an invalid flight fails the call and names its index
+        bad = flights[:3] + [dict(flights[3], n_rays=0)]
+        with pytest.raises(B.RmpcError) as e:
+            ctx.rollout_batch(bad, P)
+        assert e.value.status == B.RMPC_E_INVALID and "flight 3" in str(e.value)
+        with pytest.raises(B.RmpcError) as e:
+            ctx.rollout_batch([dict(flights[0], map_id=mid + 999)], P)
+        assert e.value.status == B.RMPC_E_NOMAP
+    finally:
+        ctx.release(mid)
+
+
 def test_rollout_edge_cases(ctx, tiny_map):
     from paper_2301_08068_amd import binding as B
     mid = ctx.upload(tiny_map.tsdf, tiny_map.voxel_m, tiny_map.origin_m, "f32")
@@ -123,7 +164,7 @@ def test_rollout_edge_cases(ctx, tiny_map):
         assert r["status"] == B.ROLLOUT_LEFT_GRID and r["n_steps"] == 0
         # invalid parameters are refused
         for kw in (dict(alpha=0.0), dict(beta=-1.0), dict(dt=0.0), dict(max_steps=-1), dict(goal_tol=float("nan")),
-                   dict(ray_weight=-1.0)):
+                   dict(ray_weight=-1.0), dict(smooth_every=0)):
             args = dict(alpha=ALPHA, beta=BETA, dt=DT, max_steps=10, goal_tol=0.01)
             args.update(kw)
             with pytest.raises(B.RmpcError) as e:

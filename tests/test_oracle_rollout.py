@@ -93,3 +93,14 @@ def test_zero_ray_weight_ignores_obstacles():
     f = oracle.rollout(free, x0, [0, 0, 0], 256, P, goal, ALPHA, BETA, DT, r["n_steps"], 0.05)
     assert r["status"] == oracle.ROLLOUT_COLLISION
     assert np.array_equal(r["x"], f["x"][: r["n_steps"] + 1])
+
+
+def test_smoothness_sampling_stride():
+    # a zigzag of right angles at every point is straight when every second point is kept
+    zig = [[0, 0, 0], [1, 1, 0], [2, 0, 0], [3, 1, 0], [4, 0, 0]]
+    assert oracle.smoothness(zig) == pytest.approx(0.5, abs=1e-15)
+    assert oracle.smoothness(zig, every=2) == 1.0
+    # a trailing partial stride is not sampled: 0, 3 and 6 are kept, the turn at 7 is not seen
+    pts = [[i, 0, 0] for i in range(7)] + [[6, 5, 0]]
+    assert oracle.smoothness(pts, every=3) == 1.0
+    assert oracle.smoothness(pts) < 1.0
