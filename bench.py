@@ -310,7 +310,7 @@ def rollout_bench(args):
     from paper_2301_08068_amd import binding
     from paper_2301_08068_amd import workloads as W
     params = W.params("static")
-    alpha, beta, dt, horizon_s, tol, every = 10.0, 15.0, 0.001, 90.0, 0.2, 10
+    alpha, beta, dt, horizon_s, tol, every = 10.0, 15.0, 0.001, args.rollout_horizon, 0.2, 10
     n_ref = 4.0     # averaged reading: ray sums times n_ref / N
     max_steps = int(round(horizon_s / dt))
     rays = [int(r) for r in args.rollout_rays.split(",")]
@@ -336,6 +336,10 @@ def rollout_bench(args):
                                         beta=beta, dt=dt, max_steps=max_steps, goal_tol=tol, ray_weight=w,
                                         smooth_every=every))
                     tags.append((weighting, n))
+        # launch configuration of the per-step batches, tuned on the batch of the start states
+        tuned = binding.rmpc_tune_batch(ctx.ptr, binding.query_descs(
+            [dict(kind="map", map_id=f["map_id"], n=f["n_rays"], x=f["x0"], v=f["v0"]) for f in flights]),
+            params, None, stream=ctx.stream)
         t0 = time.perf_counter()
         res = ctx.rollout_batch(flights, params)
         el = time.perf_counter() - t0
@@ -354,6 +358,7 @@ def rollout_bench(args):
             rows.append(row)
             print(json.dumps({"progress": row}), file=sys.stderr, flush=True)
         level = {"obstacles": n_prims, "occupied_fraction_mean": float(np.mean(occ)), "flights": len(flights),
+                 "batch_config": tuned,
                  "batched_steps": launches, "ms_per_batched_step": 1e3 * el / launches,
                  "flight_steps_per_s": sum(r["n_steps"] for r in res) / el}
         rows.append(level)
@@ -389,6 +394,8 @@ def main():
     ap.add_argument("--config", default="paper", choices=sorted(CONFIGS) + ["batch", "serve", "rollout"])
     ap.add_argument("--rollouts", type=int, default=32,
                     help="rollout config: flights per clutter level and ray count")
+    ap.add_argument("--rollout-horizon", type=float, default=90.0,
+                    help="rollout config: seconds of flight before a timeout")
     ap.add_argument("--rollout-rays", default="16,64,256,1024,4096",
                     help="rollout config: comma-separated rays per query")
     ap.add_argument("--serve-requests", type=int, default=20000)
