@@ -28,7 +28,7 @@ class _Map(C.Structure):
 class _Params(C.Structure):
     _fields_ = [(k, C.c_double) for k in
                 ("c", "eta_rep", "nu_rep", "eta_damp", "nu_damp", "radius",
-                 "eps", "max_range", "rank_tol", "min_range")]
+                 "eps", "max_range", "rank_tol", "min_range", "subvoxel")]
 
 
 class _Result(C.Structure):
@@ -71,6 +71,10 @@ def lib():
         L.orc_query.restype = C.c_int32
         L.orc_query.argtypes = [P(_Map), P(C.c_double), P(C.c_double), C.c_int32,
                                 P(C.c_float), P(_Params), C.c_int32, P(_Result)]
+        L.orc_field.restype = C.c_double
+        L.orc_field.argtypes = [P(_Map), P(C.c_double)]
+        L.orc_subvoxel.restype = C.c_double
+        L.orc_subvoxel.argtypes = [P(_Map), P(C.c_float), P(C.c_float), C.c_double]
         L.orc_scan.restype = C.c_int32
         L.orc_scan.argtypes = [P(C.c_float), C.c_int32, P(C.c_double), P(_Params), P(_Result)]
         _lib = L
@@ -102,7 +106,7 @@ class OracleMap:
 
 
 def params_struct(p: Dict[str, float]) -> _Params:
-    return _Params(*[float(p[k]) for k, _ in _Params._fields_])
+    return _Params(*[float(p.get(k, 0.0)) if k == "subvoxel" else float(p[k]) for k, _ in _Params._fields_])
 
 
 def radical_inverse(i: int, base: int) -> float:
@@ -136,6 +140,19 @@ def trace(m: OracleMap, g, dirs: np.ndarray, max_range: float, nthreads: int = 1
     if rc < 0:
         raise ValueError("start outside the grid")
     return out
+
+
+def field(m: OracleMap, p) -> float:
+    """Trilinear interpolation of the stored TSDF values (at voxel centres) at grid point p."""
+    return lib().orc_field(C.byref(m.s), _ptr(_d3(p), C.c_double))
+
+
+def subvoxel(m: OracleMap, g, r, d: float) -> float:
+    """Refined hit distance (reading R20): one secant step on the field across the entry
+    point of the hit voxel at walk distance d (metres) from grid start g along r."""
+    g = np.ascontiguousarray(np.asarray(g, dtype=np.float32).reshape(3))
+    r = np.ascontiguousarray(np.asarray(r, dtype=np.float32).reshape(3))
+    return lib().orc_subvoxel(C.byref(m.s), _ptr(g, C.c_float), _ptr(r, C.c_float), float(d))
 
 
 def soft_normalize(v, c: float) -> np.ndarray:

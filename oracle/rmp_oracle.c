@@ -28,7 +28,10 @@
  *   R8  the pseudo-inverse drops eigenvalues <= rank_tol * lambda_max;
  *   R9  nothing within max_range, or leaving the grid, is a miss and contributes 0;
  *   R14 exact DDA ties step the lowest axis index; near-ties (< 1e-5 voxel) are flagged
- *       and both orders are enumerated into an admissible set.
+ *       and both orders are enumerated into an admissible set;
+ *   R20 optional sub-voxel distance: one secant step on the trilinearly interpolated TSDF
+ *       across the entry point of the hit voxel (the paper's raycaster steps a continuous
+ *       distance field; the walk's voxel-face distance is its voxel-exact stand-in).
  *
  * Parity unpinned: the constants epsilon, rank_tol and min_range, and readings R1-R3,
  * which nothing printed in the paper can confirm.
@@ -57,6 +60,7 @@ typedef struct {
 typedef struct {
     double c, eta_rep, nu_rep, eta_damp, nu_damp, radius;   /* Table I columns */
     double eps, max_range, rank_tol, min_range;             /* readings R4, R9, R8, R11 */
+    double subvoxel;      /* non-zero: refine each hit distance (R20) before the policy */
 } orc_params;
 
 typedef struct {
@@ -354,6 +358,73 @@ int32_t orc_trace(const orc_map *m, const float g[3], const float *dirs, int32_t
 }
 
 /* ---------------------------------------------------------------------------------- */
+/* sub-voxel hit distance (reading R20)                                                 */
+/* ---------------------------------------------------------------------------------- */
+
+/* Stored TSDF value of voxel (i, j, k), indices clamped into the grid, as float64. */
+static double stored_value(const orc_map *m, int64_t i, int64_t j, int64_t k)
+{
+    i = i < 0 ? 0 : (i >= m->nx ? m->nx - 1 : i);
+    j = j < 0 ? 0 : (j >= m->ny ? m->ny - 1 : j);
+    k = k < 0 ? 0 : (k >= m->nz ? m->nz - 1 : k);
+    const int64_t lin = i + (int64_t)m->nx * (j + (int64_t)m->ny * k);
+    if (m->dtype == 0) return (double)((const float *)m->data)[lin];
+    return half_to_double(((const uint16_t *)m->data)[lin]);
+}
+
+/* The continuous field: trilinear interpolation of the stored values, which sit at the voxel
+ * centres (grid coordinates i + 1/2).  p is in grid coordinates. */
+double orc_field(const orc_map *m, const double p[3])
+{
+    double u[3], f[3];
+    int64_t i0[3];
+    for (int a = 0; a < 3; ++a) {
+        u[a] = p[a] - 0.5;
+        i0[a] = (int64_t)floor(u[a]);
+        f[a] = u[a] - (double)i0[a];
+    }
+    double c[2][2];
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy) {
+            const double a0 = stored_value(m, i0[0], i0[1] + dy, i0[2] + dz);
+            const double a1 = stored_value(m, i0[0] + 1, i0[1] + dy, i0[2] + dz);
+            c[dz][dy] = a0 + f[0] * (a1 - a0);          /* along x */
+        }
+    const double e0 = c[0][0] + f[1] * (c[0][1] - c[0][0]);   /* along y, z = 0 */
+    const double e1 = c[1][0] + f[1] * (c[1][1] - c[1][0]);   /* along y, z = 1 */
+    return e0 + f[2] * (e1 - e0);                              /* along z */
+}
+
+/*
+ * Refined distance of a hit (R20).  d is the exact walk's distance in metres to where the ray
+ * from grid start g along r enters its first occupied voxel.  With t = d / h (grid units), the
+ * field is sampled along the ray at t_k = max(t + k/2 - 3/2, 0), k = 0..7 (from 1.5 voxels
+ * before the entry to 2 voxels after it: the field's zero crossing lies within that window
+ * for any surface the walk can report).  At the first k with phi_k > 0 >= phi_k+1 one secant
+ * step gives t* = t_k + (t_k+1 - t_k) phi_k / (phi_k - phi_k+1), and the result is t* h.
+ * Without such a sign change (and for misses and d = 0) d is returned unchanged.
+ */
+double orc_subvoxel(const orc_map *m, const float g[3], const float r[3], double d)
+{
+    if (!(d > 0.0) || isinf(d) || m->dtype == 2) return d;
+    const double t = d / m->h;
+    double tk[8], phi[8];
+    for (int k = 0; k < 8; ++k) {
+        const double s = t + 0.5 * (double)k - 1.5;
+        tk[k] = s > 0.0 ? s : 0.0;
+        double p[3];
+        for (int a = 0; a < 3; ++a) p[a] = (double)g[a] + tk[k] * (double)r[a];
+        phi[k] = orc_field(m, p);
+    }
+    for (int k = 0; k < 7; ++k)
+        if (phi[k] > 0.0 && phi[k + 1] <= 0.0) {
+            const double ts = tk[k] + (tk[k + 1] - tk[k]) * (phi[k] / (phi[k] - phi[k + 1]));
+            return ts * m->h;
+        }
+    return d;
+}
+
+/* ---------------------------------------------------------------------------------- */
 /* per-ray obstacle policy (Sec. III-C, Eqs. 4-9; readings R1-R4)                      */
 /* ---------------------------------------------------------------------------------- */
 
@@ -543,6 +614,8 @@ int32_t orc_query(const orc_map *m, const double x[3], const double v[3], int32_
     int32_t *vis = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
     double *rh = (double *)malloc(sizeof(double) * 3 * (size_t)n);
     orc_trace(m, g, dirs, n, p->max_range, hit, d, fl, vis, NULL, NULL, NULL, nthreads);
+    if (p->subvoxel != 0.0)
+        for (int32_t i = 0; i < n; ++i) d[i] = orc_subvoxel(m, g, dirs + 3 * (int64_t)i, d[i]);
     int64_t visits = 0;
     int32_t n_tie = 0;
     for (int32_t i = 0; i < n; ++i) {

@@ -420,13 +420,14 @@ def synth_scan(m: VoxelMap, x: np.ndarray, seed: int, n_elev: int = 64, n_azim: 
 
 # ----------------------------------------------------------------------------------------
 # policy parameter sets: Table I ("Static Map" and "LiDAR" columns) plus the constants the
-# paper leaves open (epsilon, max range, pseudo-inverse cut, minimum LiDAR range)
+# paper leaves open (epsilon, max range, pseudo-inverse cut, minimum LiDAR range) and the
+# sub-voxel distance switch (0: the walk's voxel-face distance)
 # ----------------------------------------------------------------------------------------
 
 STATIC_MAP_PARAMS = dict(c=0.2, eta_rep=88.0, nu_rep=1.4, eta_damp=140.0, nu_damp=1.2,
-                         radius=2.4, eps=1e-3, max_range=10.0, rank_tol=1e-6, min_range=0.1)
+                         radius=2.4, eps=1e-3, max_range=10.0, rank_tol=1e-6, min_range=0.1, subvoxel=0.0)
 LIDAR_PARAMS = dict(c=1.0, eta_rep=1.2, nu_rep=1.5, eta_damp=3.0, nu_damp=1.0,
-                    radius=1.3, eps=1e-3, max_range=20.0, rank_tol=1e-6, min_range=0.1)
+                    radius=1.3, eps=1e-3, max_range=20.0, rank_tol=1e-6, min_range=0.1, subvoxel=0.0)
 
 
 def params(preset: str = "static", **overrides) -> dict:
