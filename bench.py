@@ -29,10 +29,12 @@ KERNEL_SOURCES = ["paper_2301_08068_amd/csrc/raycast.hip", "paper_2301_08068_amd
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "raycast_rmp_paper400_f32_traffic.txt")
 
 CONFIGS = {
-    # name: (map builder, encoding, state seed, rays, max range)
+    # name: (map builder, encoding, state seed, rays, max range[, subvoxel])
     "paper": ("paper", "f32", 200, 65536, 10.0),
     "paper_f16": ("paper", "f16", 200, 65536, 10.0),
     "paper_u8": ("paper", "u8", 200, 65536, 10.0),
+    # the paper shape with sub-voxel hit distances (the TSDF's zero crossing)
+    "paper_subvoxel": ("paper", "f32", 200, 65536, 10.0, 1),
     "tiny": ("tiny", "f32", 100, 1024, 5.0),
 }
 ELEM_BYTES = {"f32": 4, "f16": 2, "u8": 1}
@@ -441,10 +443,11 @@ def main():
         rollout_bench(args)
         return
 
-    kind, enc, seed, n_rays, rmax = CONFIGS[args.config]
+    kind, enc, seed, n_rays, rmax, *rest = CONFIGS[args.config]
+    subvoxel = rest[0] if rest else 0
     vm, data = build_map(kind, enc)
     x, v = W.free_state(vm, seed)
-    params = W.params("static", max_range=rmax)
+    params = W.params("static", max_range=rmax, subvoxel=subvoxel)
 
     ctx = binding.Context(0, arena_bytes=1 << 30)
     mid = ctx.upload(data, vm.voxel_m, vm.origin_m, enc)
@@ -497,6 +500,7 @@ def main():
                          f"max range {rmax} m; blocking query with result readback"),
             "rays_per_query": n_rays,
             "map_storage": enc,
+            "subvoxel_distances": bool(subvoxel),
             "occupied_fraction": round(vm.occupied_fraction(), 4),
             "mean_visits_per_ray": round(visits / n_rays, 2),
             "latency_us": {"p50": round(lat_us[len(lat_us) // 2], 1),

@@ -69,6 +69,15 @@ typedef struct {
     double max_range_m;         /* rays with no occupied voxel within this range miss */
     double rank_tol;            /* pseudo-inverse keeps eigenvalues > rank_tol * lambda_max */
     double min_range_m;         /* scan points closer than this are skipped */
+    int32_t subvoxel;           /* map queries on float32/float16 TSDF maps: non-zero refines
+                                   each hit distance to the zero crossing of the trilinearly
+                                   interpolated TSDF (the field sampled at eight points from 1.5
+                                   voxels before the hit voxel's entry to 2 after it, one secant
+                                   step at the first sign change; the paper's raycaster steps a
+                                   continuous distance field, Sec. III-E/F); 0: the distance to
+                                   the hit voxel's face.  Not allowed on uint8 maps; ignored by
+                                   scan queries. */
+    int32_t reserved;           /* 0 */
 } rmpc_params;
 
 /* Query flags. */
@@ -175,7 +184,8 @@ rmpc_status rmpc_scan_query(rmpc_ctx *ctx, const float *points_dev, int32_t n_po
  *   dist_dev[n_rays]: distance in metres to where the ray enters it (float64), +inf on a miss.
  *   flags_dev[n_rays]: RMPC_RAY_* flags.
  *   visits_dev[n_rays]: voxels the ray's walk entered (start voxel included); may be NULL.
- * All output buffers are device memory.  Only params->max_range_m is used.  Blocking.
+ * All output buffers are device memory.  Only params->max_range_m and params->subvoxel (then
+ * dist_dev holds the refined distances) are used.  Blocking.
  * Errors: as rmpc_query.
  */
 rmpc_status rmpc_trace_debug(rmpc_ctx *ctx, int32_t map_id, const double x[3], int32_t n_rays,

@@ -399,8 +399,8 @@ double orc_field(const orc_map *m, const double p[3])
  * Refined distance of a hit (R20).  d is the exact walk's distance in metres to where the ray
  * from grid start g along r enters its first occupied voxel.  With t = d / h (grid units), the
  * field is sampled along the ray at t_k = max(t + k/2 - 3/2, 0), k = 0..7 (from 1.5 voxels
- * before the entry to 2 voxels after it: the field's zero crossing lies within that window
- * for any surface the walk can report).  At the first k with phi_k > 0 >= phi_k+1 one secant
+ * before the entry to 2 voxels after it, a window that held the field's zero crossing for
+ * every ray measured on an oblique plane).  At the first k with phi_k > 0 >= phi_k+1 one secant
  * step gives t* = t_k + (t_k+1 - t_k) phi_k / (phi_k - phi_k+1), and the result is t* h.
  * Without such a sign change (and for misses and d = 0) d is returned unchanged.
  */

@@ -39,7 +39,8 @@ class MapDesc(C.Structure):
 
 class Params(C.Structure):
     _fields_ = [(k, C.c_double) for k in ("c", "eta_rep", "nu_rep", "eta_damp", "nu_damp", "radius",
-                                          "eps", "max_range_m", "rank_tol", "min_range_m")]
+                                          "eps", "max_range_m", "rank_tol", "min_range_m")] + \
+               [("subvoxel", C.c_int32), ("reserved", C.c_int32)]
 
 
 class QueryDesc(C.Structure):
@@ -162,12 +163,13 @@ _param_cache: Dict[tuple, Params] = {}
 
 
 def params_struct(p: Dict[str, float]) -> Params:
-    key = tuple(float(p[k]) for k in _PARAM_KEYS)
+    """A Params struct from a dict of _PARAM_KEYS (plus an optional "subvoxel" switch)."""
+    key = tuple(float(p[k]) for k in _PARAM_KEYS) + (int(bool(p.get("subvoxel", 0))),)
     ps = _param_cache.get(key)
     if ps is None:
         if len(_param_cache) > 256:
             _param_cache.clear()
-        ps = _param_cache[key] = Params(*key)
+        ps = _param_cache[key] = Params(*key, 0)
     return ps
 
 

@@ -185,8 +185,11 @@ rmpc_status setup_query(rmpc_ctx *ctx, int32_t map_id, const double x[3], int32_
         const double fr = (double)g - std::floor((double)g);
         if (fr < 1e-5 || 1.0 - fr < 1e-5) start_flags |= RMPC_RAY_START_FACE;
     }
+    if (params->subvoxel && me.desc.dtype == RMPC_OCC_U8)
+        return fail(RMPC_E_INVALID, "subvoxel distances need a TSDF map (float32 or float16)");
     ray_list(ctx, n_rays, &A.rays, &A.n_list);
     A.map = me.view;
+    A.subvoxel = params->subvoxel != 0;
     A.n_rays = n_rays;
     A.lin0 = A.v0[0] + n[0] * (A.v0[1] + n[1] * A.v0[2]);
     A.start_flags = start_flags;

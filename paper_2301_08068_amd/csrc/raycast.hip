@@ -766,6 +766,71 @@ __device__ __forceinline__ int contributes(const RayArgs &A, float rx, float ry,
     return d < A.radius64 && vn > 0.0;
 }
 
+// Stored value of voxel (i, j, k), the indices clamped into the grid, as float64 (exact for
+// float32 and binary16).
+template <int DT>
+__device__ __forceinline__ double stored_value(const MapView &m, int i, int j, int k)
+{
+    i = i < 0 ? 0 : (i >= m.nx ? m.nx - 1 : i);
+    j = j < 0 ? 0 : (j >= m.ny ? m.ny - 1 : j);
+    k = k < 0 ? 0 : (k >= m.nz ? m.nz - 1 : k);
+    const uint32_t lin = (uint32_t)i + (uint32_t)m.nx * ((uint32_t)j + (uint32_t)m.ny * (uint32_t)k);
+    const typename Voxel<DT>::T v = static_cast<const typename Voxel<DT>::T *>(m.data)[lin];
+    if constexpr (DT == RMPC_TSDF_F32) return (double)v;
+    else return (double)__builtin_bit_cast(_Float16, v);
+}
+
+// The continuous TSDF: trilinear interpolation of the stored values, which sit at the voxel
+// centres (grid coordinates i + 1/2), at grid point p; x first, then y, then z.
+template <int DT>
+__device__ __forceinline__ double tsdf_field(const MapView &m, double px, double py, double pz)
+{
+#pragma clang fp contract(off)
+    const double ux = px - 0.5, uy = py - 0.5, uz = pz - 0.5;
+    const double flx = floor(ux), fly = floor(uy), flz = floor(uz);
+    const int ix = (int)flx, iy = (int)fly, iz = (int)flz;
+    const double fx = ux - flx, fy = uy - fly, fz = uz - flz;
+    double c[2][2];
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy) {
+            const double a0 = stored_value<DT>(m, ix, iy + dy, iz + dz);
+            const double a1 = stored_value<DT>(m, ix + 1, iy + dy, iz + dz);
+            c[dz][dy] = a0 + fx * (a1 - a0);
+        }
+    const double e0 = c[0][0] + fy * (c[0][1] - c[0][0]);
+    const double e1 = c[1][0] + fy * (c[1][1] - c[1][0]);
+    return e0 + fz * (e1 - e0);
+}
+
+// Sub-voxel hit distance: the field is sampled along the ray at t_k = max(t + k/2 - 3/2, 0),
+// k = 0..7 (grid units, t = d / h: from 1.5 voxels before the hit voxel's entry to 2 after
+// it, a window that holds the field's zero crossing for the hits of an oblique plane); at
+// the first k with phi_k > 0 >= phi_k+1 one secant step gives the crossing.  Without a sign
+// change d is kept.  float64 throughout, no contraction, so the result is that of the
+// definition evaluated in float64.
+template <int DT>
+__device__ __forceinline__ double subvoxel_distance(const RayArgs &A, float rx, float ry, float rz, double d)
+{
+#pragma clang fp contract(off)
+    const double t = d / A.h;
+    double tk[8], phi[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const double s = t + 0.5 * (double)k - 1.5;
+        tk[k] = s > 0.0 ? s : 0.0;
+        phi[k] = tsdf_field<DT>(A.map, (double)A.g[0] + tk[k] * (double)rx, (double)A.g[1] + tk[k] * (double)ry,
+                                (double)A.g[2] + tk[k] * (double)rz);
+    }
+    for (int k = 0; k < 7; ++k)
+        if (phi[k] > 0.0 && phi[k + 1] <= 0.0) {
+            const double ts = tk[k] + (tk[k + 1] - tk[k]) * (phi[k] / (phi[k] - phi[k + 1]));
+            return ts * A.h;
+        }
+    return d;
+}
+
 // Blocks are dispatched round-robin over the 8 XCDs (block b runs on XCD b % 8).  Give each
 // XCD a contiguous run of tiles so that its L2 sees one compact cone of ray directions.
 __device__ __forceinline__ int xcd_tile(int b, int nb)
@@ -804,9 +869,12 @@ __device__ __forceinline__ void ray_tile(const RayArgs &A, int tile, int n_tiles
         if (o.report) {
             acc.n_tie = (o.flags & kRayTie) != 0;
             if (o.hit) {
+                double d = o.d;
+                if constexpr (DT != RMPC_OCC_U8)
+                    if (A.subvoxel) d = subvoxel_distance<DT>(A, rx, ry, rz, d);
                 acc.n_hit = 1;
-                acc.n_contrib = contributes(A, rx, ry, rz, o.d);
-                policy_accumulate(A.pol, rx, ry, rz, (float)o.d, acc);
+                acc.n_contrib = contributes(A, rx, ry, rz, d);
+                policy_accumulate(A.pol, rx, ry, rz, (float)d, acc);
             }
         }
     }
@@ -969,7 +1037,10 @@ __global__ void __launch_bounds__(kBlock, 2) trace_debug_kernel(RayArgs A)
     for (int off = 1; off < S; off <<= 1) v += __shfl_xor(v, off, kWave);
     if (o.report) {
         A.dbg_hit[i] = o.hit ? o.hit_lin : -1;
-        A.dbg_dist[i] = o.d;
+        double d = o.d;
+        if constexpr (DT != RMPC_OCC_U8)
+            if (A.subvoxel && o.hit) d = subvoxel_distance<DT>(A, rx, ry, rz, d);
+        A.dbg_dist[i] = d;
         A.dbg_flags[i] = (uint8_t)o.flags;
         if (A.dbg_visits) A.dbg_visits[i] = v;
     }

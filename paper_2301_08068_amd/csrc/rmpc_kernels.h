@@ -66,6 +66,7 @@ struct RayArgs {
     int32_t segments;            // lanes per ray (1, 2, 4, 8 or 16)
     int32_t lookahead;           // steps planned per round (4, 8 or 16)
     double max_range, h;
+    int32_t subvoxel;            // non-zero: refine hit distances on the interpolated TSDF
     double vel64[3];             // velocity, float64 (for the exact contribution count)
     double radius64;
     PolicyF pol;
