@@ -1086,10 +1086,13 @@ int ray_grid_blocks(int lanes)
     return b < 1 ? 1 : (b > kMaxBlocks ? kMaxBlocks : b);
 }
 
+// At most 128 blocks: every block pays a ticket with an agent-scope release and acquire at the
+// end, which costs more than looping over a few more points per thread (measured: 262,144
+// points take 19.5 us with 128 blocks against 43 us with 1024; 65,536 points 13.6 against 17.6).
 int scan_grid_blocks(int n_points)
 {
     int b = (n_points + kBlock - 1) / kBlock;
-    return b < 1 ? 1 : (b > 1024 ? 1024 : b);
+    return b < 1 ? 1 : (b > 128 ? 128 : b);
 }
 
 hipError_t launch_scan(const ScanArgs &A, hipStream_t s, hipEvent_t e0, hipEvent_t e1)

@@ -400,15 +400,15 @@ def lidar_directions(n_elev: int = 64, n_azim: int = 1024, fov_deg: float = 45.0
 
 
 def synth_scan(m: VoxelMap, x: np.ndarray, seed: int, n_elev: int = 64, n_azim: int = 1024,
-               max_range_m: float = 20.0, noise_m: float = 0.02, dropout: float = 0.1
-               ) -> np.ndarray:
+               max_range_m: float = 20.0, noise_m: float = 0.02, dropout: float = 0.1,
+               fov_deg: float = 45.0) -> np.ndarray:
     """Robot-relative, world-aligned float32 points [n_elev*n_azim, 3].
 
     Range = the analytic first entry into the primitives' union plus N(0, noise^2);
     beams with no return within ``max_range_m`` and Bernoulli(dropout) beams are (0, 0, 0).
     """
     rng = np.random.default_rng(seed)
-    u = lidar_directions(n_elev, n_azim)
+    u = lidar_directions(n_elev, n_azim, fov_deg)
     t = np.full(u.shape[0], np.inf)
     for prim in m.prims:
         t = np.minimum(t, _ray_enter(prim, np.asarray(x, dtype=np.float64), u))

@@ -161,6 +161,19 @@ def test_scan_parity(ctx, tiny_map, paper_map):
         assert g["n_rays"] == pts.shape[0]
 
 
+def test_scan_os0_scale_parity(ctx, paper_map):
+    """A 128 x 2048 beam scan over a 90-degree vertical field of view (262,144 points, the
+    size of the largest common spinning LiDAR frames)."""
+    L = W.params("lidar")
+    for seed in (610, 611):
+        x, v = W.free_state(paper_map, seed)
+        pts = W.synth_scan(paper_map, x, seed, n_elev=128, n_azim=2048, fov_deg=90.0)
+        g = ctx.scan_query(pts, v, L)
+        o = oracle.scan(pts, v, L)
+        compare_query(g, o, f"os0 scan seed {seed}")
+        assert g["n_rays"] == pts.shape[0] == 262144 and g["n_hit"] == o["n_hit"]
+
+
 def test_scan_reproduces_grid_query(ctx, tiny, tiny_map):
     mid, om = tiny
     dirs = oracle.directions(1024)
