@@ -75,6 +75,8 @@ def lib():
         L.orc_field.argtypes = [P(_Map), P(C.c_double)]
         L.orc_subvoxel.restype = C.c_double
         L.orc_subvoxel.argtypes = [P(_Map), P(C.c_float), P(C.c_float), C.c_double]
+        L.orc_edt.restype = C.c_int32
+        L.orc_edt.argtypes = [P(_Map), P(C.c_int32)]
         L.orc_scan.restype = C.c_int32
         L.orc_scan.argtypes = [P(C.c_float), C.c_int32, P(C.c_double), P(_Params), P(_Result)]
         _lib = L
@@ -153,6 +155,16 @@ def subvoxel(m: OracleMap, g, r, d: float) -> float:
     g = np.ascontiguousarray(np.asarray(g, dtype=np.float32).reshape(3))
     r = np.ascontiguousarray(np.asarray(r, dtype=np.float32).reshape(3))
     return lib().orc_subvoxel(C.byref(m.s), _ptr(g, C.c_float), _ptr(r, C.c_float), float(d))
+
+
+def edt(m: OracleMap) -> np.ndarray:
+    """Squared centre-to-centre distance (voxels^2) from every voxel to the nearest occupied
+    voxel, shaped like the map's array (z, y, x); -1 everywhere when nothing is occupied."""
+    nz, ny, nx = m.data.shape[:3]
+    out = np.empty((nz, ny, nx), np.int32)
+    if lib().orc_edt(C.byref(m.s), _ptr(out, C.c_int32)) != 0:
+        raise MemoryError("orc_edt")
+    return out
 
 
 def soft_normalize(v, c: float) -> np.ndarray:

@@ -29,6 +29,7 @@
  *   R9  nothing within max_range, or leaving the grid, is a miss and contributes 0;
  *   R14 exact DDA ties step the lowest axis index; near-ties (< 1e-5 voxel) are flagged
  *       and both orders are enumerated into an admissible set;
+ *   R21 the ESDF is the exact centre-to-centre Euclidean distance transform of the occupancy;
  *   R20 optional sub-voxel distance: one secant step on the trilinearly interpolated TSDF
  *       across the entry point of the hit voxel (the paper's raycaster steps a continuous
  *       distance field; the walk's voxel-face distance is its voxel-exact stand-in).
@@ -422,6 +423,64 @@ double orc_subvoxel(const orc_map *m, const float g[3], const float r[3], double
             return ts * m->h;
         }
     return d;
+}
+
+/* ---------------------------------------------------------------------------------- */
+/* exact Euclidean distance transform of the occupancy (the ESDF of Sec. III-D, R21)    */
+/* ---------------------------------------------------------------------------------- */
+
+/*
+ * out[lin] = min over occupied voxels o of |c(lin) - c(o)|^2 in voxel units (centre to
+ * centre, an integer), 0 on occupied voxels, -1 everywhere when no voxel is occupied.  The
+ * squared distance separates over the axes: first the distance to the nearest occupied voxel
+ * of the same x row, then min over j of (g_j + (i - j)^2) along y and along z, each minimum
+ * taken over every j of the line (no envelope tricks).
+ */
+int32_t orc_edt(const orc_map *m, int32_t *out)
+{
+    const int64_t nx = m->nx, ny = m->ny, nz = m->nz, n = nx * ny * nz;
+    const int64_t INF = (int64_t)1 << 40;
+    int64_t *g = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    int64_t *line = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nx > ny ? (nx > nz ? nx : nz) : (ny > nz ? ny : nz)));
+    if (!g || !line) { free(g); free(line); return -1; }
+    int any = 0;
+    for (int64_t k = 0; k < nz; ++k)
+        for (int64_t j = 0; j < ny; ++j) {
+            const int64_t row = nx * (j + ny * k);
+            for (int64_t i = 0; i < nx; ++i) {
+                int64_t best = INF;
+                for (int64_t o = 0; o < nx; ++o)
+                    if (occupied(m, row + o)) {
+                        const int64_t dd = (i - o) * (i - o);
+                        if (dd < best) best = dd;
+                    }
+                g[row + i] = best;
+                any |= best == 0;
+            }
+        }
+    /* along y, then along z */
+    for (int pass = 0; pass < 2; ++pass) {
+        const int64_t len = pass == 0 ? ny : nz, stride = pass == 0 ? nx : nx * ny;
+        const int64_t n_lines = n / len;
+        for (int64_t l = 0; l < n_lines; ++l) {
+            /* line l: base index of its first element */
+            const int64_t base = pass == 0 ? (l % nx) + nx * ny * (l / nx) : l;
+            for (int64_t i = 0; i < len; ++i) line[i] = g[base + i * stride];
+            for (int64_t i = 0; i < len; ++i) {
+                int64_t best = INF;
+                for (int64_t j2 = 0; j2 < len; ++j2) {
+                    if (line[j2] >= INF) continue;
+                    const int64_t v = line[j2] + (i - j2) * (i - j2);
+                    if (v < best) best = v;
+                }
+                g[base + i * stride] = best;
+            }
+        }
+    }
+    for (int64_t q = 0; q < n; ++q) out[q] = any ? (int32_t)g[q] : -1;
+    free(g);
+    free(line);
+    return 0;
 }
 
 /* ---------------------------------------------------------------------------------- */
