@@ -262,6 +262,36 @@ def scan_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def edt_bench(args):
+    """Exact distance transform of the 400^3 paper-shaped map's occupancy (rmpc_edt): the
+    distance field of the ESDF policy, rebuilt after a map update."""
+    import torch
+    from paper_2301_08068_amd import binding
+    from paper_2301_08068_amd import workloads as W
+    vm = W.paper_map(2)
+    ctx = binding.Context(0, arena_bytes=1 << 30)
+    mid = ctx.upload(vm.tsdf, vm.voxel_m, vm.origin_m, "f32")
+    out = torch.empty(vm.tsdf.shape, dtype=torch.int32, device="cuda:0")
+    args_c = (binding.C.c_void_p(ctx.ptr), mid, binding.C.c_void_p(out.data_ptr()), binding.C.c_void_p(ctx.stream))
+    for _ in range(min(args.warmup, 3)):
+        binding._check(binding._lib.rmpc_edt(*args_c), "rmpc_edt")
+    steps = min(args.steps, 20)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        binding._check(binding._lib.rmpc_edt(*args_c), "rmpc_edt")
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    n = vm.tsdf.size
+    print(json.dumps({"metric": "distance-transform voxels/sec (exact squared EDT of the occupancy)",
+                      "value": n * steps / el, "unit": "voxels/s", "n_gpus": 1, "steps": steps,
+                      "warmup": min(args.warmup, 3), "ms_per_step": 1e3 * el / steps, "higher_is_better": True,
+                      "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+                      "config": {"workload": "400^3 paper-shaped f32 map (0.05 m, map seed 2), 10.6 % occupied"}}),
+          flush=True)
+    ctx.close()
+
+
 def serve_bench(args):
     """Serving: an open-loop Poisson stream of half grid-raycast requests (ray counts
     log-uniform in [4096, 65536]) and half 64 x 1024 LiDAR-scan requests (points staged from
@@ -448,7 +478,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=30)
-    ap.add_argument("--config", default="paper", choices=sorted(CONFIGS) + ["batch", "serve", "rollout", "scan_os0"])
+    ap.add_argument("--config", default="paper", choices=sorted(CONFIGS) + ["batch", "serve", "rollout", "scan_os0", "edt"])
     ap.add_argument("--rollouts", type=int, default=32,
                     help="rollout config: flights per clutter level and ray count")
     ap.add_argument("--rollout-horizon", type=float, default=90.0,
@@ -493,6 +523,9 @@ def main():
         return
     if args.config == "serve":
         serve_bench(args)
+        return
+    if args.config == "edt":
+        edt_bench(args)
         return
     if args.config == "scan_os0":
         scan_bench(args)

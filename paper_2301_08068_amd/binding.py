@@ -136,6 +136,7 @@ _SIGS = {
     "rmpc_rollout": [C.c_void_p, C.c_int32, _P(C.c_double), _P(C.c_double), C.c_int32, _P(Params),
                      _P(RolloutParams), C.c_void_p, _P(C.c_double), _P(RolloutResult)],
     "rmpc_rollout_batch": [C.c_void_p, _P(Flight), C.c_int32, _P(Params), C.c_void_p, _P(RolloutResult)],
+    "rmpc_edt": [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p],
 }
 for _name, _args in _SIGS.items():
     getattr(_lib, _name).argtypes = _args
@@ -504,6 +505,15 @@ class Context:
         return rmpc_rollout(self.ptr, map_id, x0, v0, n_rays, params, goal, alpha, beta, dt, max_steps,
                             goal_tol, trajectory, stream=self.stream, ray_weight=ray_weight,
                             smooth_every=smooth_every)
+
+    def edt(self, map_id: int, shape) -> "torch.Tensor":
+        """Squared distance transform of a resident map (rmpc_edt) as a cuda int32 tensor of
+        the map's array shape (z, y, x)."""
+        import torch
+        out = torch.empty(tuple(shape), dtype=torch.int32, device=f"cuda:{self.device}")
+        _check(_lib.rmpc_edt(C.c_void_p(self.ptr), int(map_id), C.c_void_p(out.data_ptr()),
+                             C.c_void_p(_stream_ptr(self.stream))), "rmpc_edt")
+        return out
 
     def rollout_batch(self, flights, params: Dict[str, float]) -> list:
         return rmpc_rollout_batch(self.ptr, flights, params, stream=self.stream)

@@ -555,6 +555,18 @@ rmpc_status rmpc_get_profile(rmpc_ctx *ctx, double *kernel_ms, int64_t *launches
     return RMPC_OK;
 }
 
+rmpc_status rmpc_edt(rmpc_ctx *ctx, int32_t map_id, int32_t *sqdist_dev, void *hip_stream)
+{
+    if (!ctx || !sqdist_dev) return fail(RMPC_E_INVALID, "NULL argument");
+    auto it = ctx->maps.find(map_id);
+    if (it == ctx->maps.end()) return fail(RMPC_E_NOMAP, "unknown map id");
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    RMPC_HIP(rmpc::launch_edt(it->second.view, sqdist_dev, s));
+    RMPC_HIP(hipStreamSynchronize(s));
+    return RMPC_OK;
+}
+
 rmpc_status rmpc_directions(rmpc_ctx *ctx, int32_t n, float *out_host)
 {
     if (!ctx || !out_host) return fail(RMPC_E_INVALID, "NULL argument");

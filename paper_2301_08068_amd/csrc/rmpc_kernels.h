@@ -171,6 +171,8 @@ hipError_t launch_directions(const DirsArgs &a, hipStream_t s);
 hipError_t launch_map_summaries(const SummaryArgs &a, hipStream_t s);
 hipError_t launch_compact(const CompactArgs &a, hipStream_t s);
 hipError_t launch_gather(const GatherArgs &a, hipStream_t s);
+// Exact squared Euclidean distance transform of the map's occupancy into out (x fastest).
+hipError_t launch_edt(const MapView &m, int32_t *out, hipStream_t s);
 // Persistent fused batch: `blocks` resident blocks pull tiles from a counter.
 hipError_t launch_batch(const BatchArgs &a, int blocks, int lookahead, hipStream_t s);
 // Resident blocks per CU of the batch kernel for a lookahead.

@@ -1,0 +1,65 @@
+"""GPU exact distance transform (rmpc_edt) against the oracle's: every voxel bit for bit on the
+tiny map in all three encodings and on ragged random grids; sampled voxels of the 400^3 map
+against brute force over all its occupied voxels; empty and full grids."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from paper_2301_08068_amd import workloads as W  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2301_08068_amd import binding
+    c = binding.Context(0, arena_bytes=1 << 30)
+    yield c
+    c.close()
+
+
+def _gpu_edt(ctx, data, h, enc):
+    mid = ctx.upload(data, h, np.zeros(3), enc)
+    try:
+        return ctx.edt(mid, data.shape).cpu().numpy()
+    finally:
+        ctx.release(mid)
+
+
+@pytest.mark.parametrize("enc", ["f32", "f16", "u8"])
+def test_tiny_map_bitwise(ctx, tiny_map, enc):
+    data = {"f32": tiny_map.tsdf, "f16": W.encode_f16(tiny_map.tsdf), "u8": W.encode_u8(tiny_map.tsdf)}[enc]
+    g = _gpu_edt(ctx, data, tiny_map.voxel_m, enc)
+    o = oracle.edt(oracle.OracleMap(data, tiny_map.voxel_m, tiny_map.origin_m, enc))
+    assert np.array_equal(g, o)
+
+
+@pytest.mark.parametrize("shape,p", [((37, 23, 51), 0.002), ((5, 300, 7), 0.01), ((64, 1, 130), 0.05)])
+def test_ragged_random_grids(ctx, shape, p):
+    rng = np.random.default_rng(sum(shape))
+    occ = rng.uniform(size=shape) < p
+    occ[0, 0, 0] = True
+    t = np.where(occ, -0.05, 0.3).astype(np.float32)
+    g = _gpu_edt(ctx, t, 0.1, "f32")
+    assert np.array_equal(g, oracle.edt(oracle.OracleMap(t, 0.1, np.zeros(3), "f32")))
+
+
+def test_empty_and_full(ctx):
+    free = np.full((9, 10, 11), 0.3, np.float32)
+    assert np.all(_gpu_edt(ctx, free, 0.1, "f32") == -1)
+    assert np.all(_gpu_edt(ctx, -free, 0.1, "f32") == 0)
+
+
+def test_paper_map_sampled(ctx, paper_map):
+    g = _gpu_edt(ctx, paper_map.tsdf, paper_map.voxel_m, "f32")
+    occ = paper_map.tsdf <= 0
+    assert np.all(g[occ] == 0) and np.all(g[~occ] > 0)
+    pts = np.argwhere(occ).astype(np.int64)               # (k, j, i)
+    rng = np.random.default_rng(12)
+    for _ in range(48):
+        k, j, i = (int(v) for v in rng.integers(0, 400, size=3))
+        best = int(np.min((pts[:, 0] - k) ** 2 + (pts[:, 1] - j) ** 2 + (pts[:, 2] - i) ** 2))
+        assert g[k, j, i] == best, (k, j, i)
