@@ -77,6 +77,8 @@ def lib():
         L.orc_subvoxel.argtypes = [P(_Map), P(C.c_float), P(C.c_float), C.c_double]
         L.orc_edt.restype = C.c_int32
         L.orc_edt.argtypes = [P(_Map), P(C.c_int32)]
+        L.orc_esdf_query.restype = C.c_int32
+        L.orc_esdf_query.argtypes = [P(_Map), P(C.c_int32), P(C.c_double), P(C.c_double), P(_Params), P(_Result)]
         L.orc_scan.restype = C.c_int32
         L.orc_scan.argtypes = [P(C.c_float), C.c_int32, P(C.c_double), P(_Params), P(_Result)]
         _lib = L
@@ -165,6 +167,17 @@ def edt(m: OracleMap) -> np.ndarray:
     if lib().orc_edt(C.byref(m.s), _ptr(out, C.c_int32)) != 0:
         raise MemoryError("orc_edt")
     return out
+
+
+def esdf_query(m: OracleMap, sq: np.ndarray, x, v, p: Dict[str, float]) -> Dict:
+    """Single-lookup ESDF policy (reading R22) on the squared distance transform sq."""
+    sq = np.ascontiguousarray(sq, dtype=np.int32)
+    r = _Result()
+    ps = params_struct(p)
+    if lib().orc_esdf_query(C.byref(m.s), _ptr(sq, C.c_int32), _ptr(_d3(x), C.c_double), _ptr(_d3(v), C.c_double),
+                            C.byref(ps), C.byref(r)) < 0:
+        raise ValueError("start outside the grid")
+    return _result_dict(r)
 
 
 def soft_normalize(v, c: float) -> np.ndarray:

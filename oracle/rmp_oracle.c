@@ -30,6 +30,8 @@
  *   R14 exact DDA ties step the lowest axis index; near-ties (< 1e-5 voxel) are flagged
  *       and both orders are enumerated into an admissible set;
  *   R21 the ESDF is the exact centre-to-centre Euclidean distance transform of the occupancy;
+ *   R22 the ESDF policy reads the distance of x's voxel and central differences of its six
+ *       neighbours, and evaluates the obstacle policy once for that (direction, distance);
  *   R20 optional sub-voxel distance: one secant step on the trilinearly interpolated TSDF
  *       across the entry point of the hit voxel (the paper's raycaster steps a continuous
  *       distance field; the walk's voxel-face distance is its voxel-exact stand-in).
@@ -713,5 +715,57 @@ int32_t orc_scan(const float *pts, int32_t n, const double v[3], const orc_param
     }
     orc_combine(p, rh, d, hit, n, v, out);
     free(rh); free(d); free(hit);
+    return 0;
+}
+
+/* ---------------------------------------------------------------------------------- */
+/* single-lookup ESDF policy (Sec. III-D, reading R22)                                 */
+/* ---------------------------------------------------------------------------------- */
+
+/* Distance in metres at voxel (i, j, k) (indices clamped into the grid) from the squared
+ * distance transform sq; -1 when the grid holds no occupied voxel. */
+static double esdf_at(const orc_map *m, const int32_t *sq, int64_t i, int64_t j, int64_t k)
+{
+    i = i < 0 ? 0 : (i >= m->nx ? m->nx - 1 : i);
+    j = j < 0 ? 0 : (j >= m->ny ? m->ny - 1 : j);
+    k = k < 0 ? 0 : (k >= m->nz ? m->nz - 1 : k);
+    const int32_t q = sq[i + (int64_t)m->nx * (j + (int64_t)m->ny * k)];
+    return q < 0 ? -1.0 : m->h * sqrt((double)q);
+}
+
+/*
+ * The ESDF policy at x: d = the distance stored for x's voxel, its gradient by central
+ * differences over the six neighbour voxels (clamped at the grid edge, divided by 2h), the
+ * obstacle direction r = -grad / |grad|, and the obstacle policy of Eqs. 4-9 for that one
+ * (r, d), resolved like a query.  No occupied voxel in the grid, or a zero gradient: no
+ * policy (all sums zero).  An occupied voxel at x sets ORC_Q_IN_COLLISION.
+ */
+int32_t orc_esdf_query(const orc_map *m, const int32_t *sq, const double x[3], const double v[3],
+                       const orc_params *p, orc_result *out)
+{
+    memset(out, 0, sizeof *out);
+    float g[3];
+    if (!orc_grid_start(m, x, g)) return -1;
+    const int64_t c[3] = {(int64_t)floorf(g[0]), (int64_t)floorf(g[1]), (int64_t)floorf(g[2])};
+    const double d = esdf_at(m, sq, c[0], c[1], c[2]);
+    if (d < 0.0) return 0;
+    if (d == 0.0) out->flags |= ORC_Q_IN_COLLISION;
+    double grad[3];
+    for (int a = 0; a < 3; ++a) {
+        int64_t hi[3] = {c[0], c[1], c[2]}, lo[3] = {c[0], c[1], c[2]};
+        hi[a] += 1;
+        lo[a] -= 1;
+        grad[a] = (esdf_at(m, sq, hi[0], hi[1], hi[2]) - esdf_at(m, sq, lo[0], lo[1], lo[2])) / (2.0 * m->h);
+    }
+    const double gn = sqrt(grad[0] * grad[0] + grad[1] * grad[1] + grad[2] * grad[2]);
+    if (!(gn > 0.0)) return 0;
+    const double rhat[3] = {-grad[0] / gn, -grad[1] / gn, -grad[2] / gn};
+    double A[9], b[3];
+    orc_rmp_ray(p, rhat, d, v, A, b);
+    memcpy(out->S, A, sizeof A);
+    memcpy(out->b, b, sizeof b);
+    out->n_hit = 1;
+    out->n_contrib = d < p->radius && (v[0] * rhat[0] + v[1] * rhat[1] + v[2] * rhat[2]) > 0.0;
+    orc_resolve(out->S, out->b, p->rank_tol, out->f, out->lam, &out->rank, &out->flags);
     return 0;
 }
