@@ -419,6 +419,20 @@ rmpc_status rmpc_rollout(rmpc_ctx *ctx, int32_t map_id, const double x0[3], cons
  */
 rmpc_status rmpc_edt(rmpc_ctx *ctx, int32_t map_id, int32_t *sqdist_dev, void *hip_stream);
 
+/*
+ * rmpc_esdf_query -- the single-lookup ESDF policy of Sec. III-D (the paper's baseline): at
+ * x, the distance d of x's voxel read from sqdist_dev (rmpc_edt of this map: d = h sqrt(q)),
+ * the gradient by central differences over the six neighbour voxels (indices clamped at the
+ * grid edge, divided by 2h), the obstacle direction r = -grad / |grad|, and one obstacle
+ * policy (Eqs. 4-9, params as for map queries) for (r, d), resolved as a query is.  out: the
+ * result (A, b, f, lambda, rank; n_hit = 1 when a policy was evaluated, n_contrib as for a
+ * ray; n_rays = 1; RMPC_Q_IN_COLLISION when x's voxel is occupied).  A grid with nothing
+ * occupied, or a zero gradient, gives zero sums.  float64 on the device.  Blocking.
+ * Errors: RMPC_E_INVALID, RMPC_E_NOMAP, RMPC_E_OUT_OF_BOUNDS, RMPC_E_HIP.
+ */
+rmpc_status rmpc_esdf_query(rmpc_ctx *ctx, int32_t map_id, const int32_t *sqdist_dev, const double x[3],
+                            const double v[3], const rmpc_params *params, void *hip_stream, rmpc_result *out);
+
 /* A flight of a batched rollout. */
 typedef struct {
     int32_t map_id;

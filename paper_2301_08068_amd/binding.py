@@ -137,6 +137,8 @@ _SIGS = {
                      _P(RolloutParams), C.c_void_p, _P(C.c_double), _P(RolloutResult)],
     "rmpc_rollout_batch": [C.c_void_p, _P(Flight), C.c_int32, _P(Params), C.c_void_p, _P(RolloutResult)],
     "rmpc_edt": [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p],
+    "rmpc_esdf_query": [C.c_void_p, C.c_int32, C.c_void_p, _P(C.c_double), _P(C.c_double), _P(Params), C.c_void_p,
+                        _P(Result)],
 }
 for _name, _args in _SIGS.items():
     getattr(_lib, _name).argtypes = _args
@@ -514,6 +516,14 @@ class Context:
         _check(_lib.rmpc_edt(C.c_void_p(self.ptr), int(map_id), C.c_void_p(out.data_ptr()),
                              C.c_void_p(_stream_ptr(self.stream))), "rmpc_edt")
         return out
+
+    def esdf_query(self, map_id: int, sqdist, x, v, params: Dict[str, float]) -> Dict:
+        """Single-lookup ESDF policy (rmpc_esdf_query) on a distance transform from edt()."""
+        r = Result()
+        _check(_lib.rmpc_esdf_query(C.c_void_p(self.ptr), int(map_id), C.c_void_p(sqdist.data_ptr()), _d3(x), _d3(v),
+                                    C.byref(params_struct(params)), C.c_void_p(_stream_ptr(self.stream)),
+                                    C.byref(r)), "rmpc_esdf_query")
+        return result_dict(r)
 
     def rollout_batch(self, flights, params: Dict[str, float]) -> list:
         return rmpc_rollout_batch(self.ptr, flights, params, stream=self.stream)

@@ -567,6 +567,46 @@ rmpc_status rmpc_edt(rmpc_ctx *ctx, int32_t map_id, int32_t *sqdist_dev, void *h
     return RMPC_OK;
 }
 
+rmpc_status rmpc_esdf_query(rmpc_ctx *ctx, int32_t map_id, const int32_t *sqdist_dev, const double x[3],
+                            const double v[3], const rmpc_params *params, void *hip_stream, rmpc_result *out)
+{
+    if (!ctx || !sqdist_dev || !out) return fail(RMPC_E_INVALID, "NULL argument");
+    if (!finite3(x) || !finite3(v)) return fail(RMPC_E_INVALID, "state is NULL or not finite");
+    if (rmpc_status st = check_params(params)) return st;
+    auto it = ctx->maps.find(map_id);
+    if (it == ctx->maps.end()) return fail(RMPC_E_NOMAP, "unknown map id");
+    const rmpc_map_desc &d = it->second.desc;
+    float g[3];
+    if (!grid_coords(d, x, g)) return fail(RMPC_E_OUT_OF_BOUNDS, "position outside the grid");
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    rmpc::EsdfArgs A;
+    std::memset(&A, 0, sizeof A);
+    A.sq = sqdist_dev;
+    A.nx = d.nx;
+    A.ny = d.ny;
+    A.nz = d.nz;
+    for (int a = 0; a < 3; ++a) {
+        A.v0[a] = (int32_t)std::floor(g[a]);
+        A.vel[a] = v[a];
+    }
+    A.h = d.voxel_m;
+    A.c = params->c;
+    A.eta_rep = params->eta_rep;
+    A.nu_rep = params->nu_rep;
+    A.eta_damp = params->eta_damp;
+    A.nu_damp = params->nu_damp;
+    A.radius = params->radius;
+    A.eps = params->eps;
+    A.rank_tol = params->rank_tol;
+    // the result goes through the context's partial-sum buffer (a query's scratch, idle here)
+    A.out = reinterpret_cast<rmpc_result *>(ctx->partials);
+    RMPC_HIP(rmpc::launch_esdf(A, s));
+    RMPC_HIP(hipMemcpyAsync(out, A.out, sizeof(rmpc_result), hipMemcpyDeviceToHost, s));
+    RMPC_HIP(hipStreamSynchronize(s));
+    return RMPC_OK;
+}
+
 rmpc_status rmpc_directions(rmpc_ctx *ctx, int32_t n, float *out_host)
 {
     if (!ctx || !out_host) return fail(RMPC_E_INVALID, "NULL argument");

@@ -76,7 +76,81 @@ hipError_t launch_edt_dt(const MapView &m, int32_t *out, hipStream_t s)
     return hipGetLastError();
 }
 
+// Distance in metres at voxel (i, j, k), indices clamped into the grid; -1 when the grid has
+// no occupied voxel.
+__device__ double esdf_at(const EsdfArgs &A, int i, int j, int k)
+{
+    i = i < 0 ? 0 : (i >= A.nx ? A.nx - 1 : i);
+    j = j < 0 ? 0 : (j >= A.ny ? A.ny - 1 : j);
+    k = k < 0 ? 0 : (k >= A.nz ? A.nz - 1 : k);
+    const int32_t q = A.sq[(int64_t)i + (int64_t)A.nx * ((int64_t)j + (int64_t)A.ny * k)];
+    return q < 0 ? -1.0 : A.h * sqrt((double)q);
+}
+
+// Single-lookup ESDF policy (Sec. III-D): the distance of the position's voxel, its gradient by
+// central differences over the six neighbours (divided by 2h), the obstacle direction
+// r = -grad / |grad|, one obstacle policy (Eqs. 4-9) for (r, d) in float64, resolved.  Nothing
+// occupied or a zero gradient: all sums zero.  One thread.
+__global__ void esdf_policy_kernel(EsdfArgs A)
+{
+#pragma clang fp contract(off)
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    rmpc_result r = {};
+    r.n_rays = 1;
+    const int c0 = A.v0[0], c1 = A.v0[1], c2 = A.v0[2];
+    const double d = esdf_at(A, c0, c1, c2);
+    double S[3][3] = {}, b[3] = {}, f[3] = {}, lam[3] = {};
+    int32_t rank = 0;
+    uint32_t flags = d == 0.0 ? RMPC_Q_IN_COLLISION : 0u;
+    double grad[3] = {0.0, 0.0, 0.0};
+    if (d >= 0.0) {
+        grad[0] = (esdf_at(A, c0 + 1, c1, c2) - esdf_at(A, c0 - 1, c1, c2)) / (2.0 * A.h);
+        grad[1] = (esdf_at(A, c0, c1 + 1, c2) - esdf_at(A, c0, c1 - 1, c2)) / (2.0 * A.h);
+        grad[2] = (esdf_at(A, c0, c1, c2 + 1) - esdf_at(A, c0, c1, c2 - 1)) / (2.0 * A.h);
+    }
+    const double gn = sqrt(grad[0] * grad[0] + grad[1] * grad[1] + grad[2] * grad[2]);
+    if (d >= 0.0 && gn > 0.0) {
+        const double rh[3] = {-grad[0] / gn, -grad[1] / gn, -grad[2] / gn};
+        const double n[3] = {-rh[0], -rh[1], -rh[2]};            // away from the obstacle
+        const double erep = A.eta_rep * exp(-d / A.nu_rep);
+        const double vn = -(A.vel[0] * n[0] + A.vel[1] * n[1] + A.vel[2] * n[2]);
+        const double mx = vn > 0.0 ? vn : 0.0;
+        const double kd = A.eta_damp / (d / A.nu_damp + A.eps);
+        double fd[3], fo[3];
+        for (int a = 0; a < 3; ++a) {
+            fd[a] = kd * (mx * mx * n[a]);
+            fo[a] = erep * n[a] + fd[a];
+        }
+        const double nf = sqrt(fd[0] * fd[0] + fd[1] * fd[1] + fd[2] * fd[2]);
+        const double den = nf + A.c * log1p(exp(-2.0 * A.c * nf));
+        const double w = d > A.radius ? 0.0 : d * d / (A.radius * A.radius) - 2.0 * d / A.radius + 1.0;
+        double sv[3];
+        for (int a = 0; a < 3; ++a) sv[a] = fd[a] / den;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) S[i][j] = w * sv[i] * sv[j];
+        for (int i = 0; i < 3; ++i) b[i] = S[i][0] * fo[0] + S[i][1] * fo[1] + S[i][2] * fo[2];
+        r.n_hit = 1;
+        r.n_contrib = d < A.radius && (A.vel[0] * rh[0] + A.vel[1] * rh[1] + A.vel[2] * rh[2]) > 0.0;
+        resolve3(S, b, A.rank_tol, f, lam, rank, flags);
+    }
+    for (int i = 0; i < 3; ++i) {
+        r.f[i] = f[i];
+        r.b[i] = b[i];
+        r.lambda[i] = lam[i];
+        for (int j = 0; j < 3; ++j) r.A[3 * i + j] = S[i][j];
+    }
+    r.rank = rank;
+    r.flags = flags;
+    *A.out = r;
+}
+
 }  // namespace
+
+hipError_t launch_esdf(const EsdfArgs &a, hipStream_t s)
+{
+    esdf_policy_kernel<<<1, 64, 0, s>>>(a);
+    return hipGetLastError();
+}
 
 hipError_t launch_edt(const MapView &m, int32_t *out, hipStream_t s)
 {

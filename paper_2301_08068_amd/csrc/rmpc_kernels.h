@@ -173,6 +173,18 @@ hipError_t launch_compact(const CompactArgs &a, hipStream_t s);
 hipError_t launch_gather(const GatherArgs &a, hipStream_t s);
 // Exact squared Euclidean distance transform of the map's occupancy into out (x fastest).
 hipError_t launch_edt(const MapView &m, int32_t *out, hipStream_t s);
+
+// The single-lookup ESDF policy at one position.
+struct EsdfArgs {
+    const int32_t *sq;           // squared distance transform, x fastest
+    int32_t nx, ny, nz;
+    int32_t v0[3];               // the position's voxel
+    double h;
+    double vel[3];
+    double c, eta_rep, nu_rep, eta_damp, nu_damp, radius, eps, rank_tol;
+    rmpc_result *out;            // device memory
+};
+hipError_t launch_esdf(const EsdfArgs &a, hipStream_t s);
 // Persistent fused batch: `blocks` resident blocks pull tiles from a counter.
 hipError_t launch_batch(const BatchArgs &a, int blocks, int lookahead, hipStream_t s);
 // Resident blocks per CU of the batch kernel for a lookahead.

@@ -63,3 +63,33 @@ def test_paper_map_sampled(ctx, paper_map):
         k, j, i = (int(v) for v in rng.integers(0, 400, size=3))
         best = int(np.min((pts[:, 0] - k) ** 2 + (pts[:, 1] - j) ** 2 + (pts[:, 2] - i) ** 2))
         assert g[k, j, i] == best, (k, j, i)
+
+
+def test_esdf_policy_matches_oracle(ctx, tiny_map):
+    """The single-lookup ESDF policy at many states of the tiny map: counts and flags exact,
+    sums and the resolved acceleration to 1e-9 of their size (float64 on both sides; only the
+    exp and log1p of the policy round differently)."""
+    from paper_2301_08068_amd import binding as B
+    mid = ctx.upload(tiny_map.tsdf, tiny_map.voxel_m, tiny_map.origin_m, "f32")
+    om = oracle.OracleMap.from_voxelmap(tiny_map)
+    p = W.params("static")
+    try:
+        sq = ctx.edt(mid, tiny_map.tsdf.shape)
+        osq = oracle.edt(om)
+        n_contrib = 0
+        for seed in range(900, 1000):
+            x, v = W.free_state(tiny_map, seed)
+            g = ctx.esdf_query(mid, sq, x, v, p)
+            o = oracle.esdf_query(om, osq, x, v, p)
+            for k in ("n_hit", "n_contrib", "flags", "rank"):
+                assert g[k] == o[k], (seed, k, g[k], o[k])
+            for k in ("S", "b", "f"):
+                scale = max(np.abs(o[k]).max(), 1e-300)
+                assert np.abs(g[k] - o[k]).max() <= 1e-9 * scale, (seed, k, g[k], o[k])
+            n_contrib += o["n_contrib"]
+        assert n_contrib > 20
+        with pytest.raises(B.RmpcError) as e:
+            ctx.esdf_query(mid, sq, [-1.0, 0.5, 0.5], [0, 0, 0], p)
+        assert e.value.status == B.RMPC_E_OUT_OF_BOUNDS
+    finally:
+        ctx.release(mid)
