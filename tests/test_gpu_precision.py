@@ -2,7 +2,7 @@
 float16 TSDF and the uint8 occupancy give the same occupancy voxel for voxel, so the GPU walks,
 hits and distances are identical across the three, and each result's error against the
 float64 oracle comes from the float32 compensated sums alone.  Prints a per-result error table
-(written to gpurun_out/precision_report.txt when that folder exists)."""
+(also written to the file named by RMPC_PRECISION_REPORT, when that is set)."""
 import os
 
 import numpy as np
@@ -88,8 +88,9 @@ def test_precision_report(ctx, paper_map):
     lines.append("results flagged ILL: " + ", ".join(f"{e}={n}" for e, n in sorted(n_ill.items())))
     text = "\n".join(lines)
     print(text)
-    if os.path.isdir("gpurun_out"):
-        with open(os.path.join("gpurun_out", "precision_report.txt"), "w") as f:
+    report = os.environ.get("RMPC_PRECISION_REPORT")
+    if report:
+        with open(report, "w") as f:
             f.write(text + "\n")
     for e in encs:
         assert worst[(e, "mis")] == 0 and worst[(e, "d")] == 0.0
