@@ -1,8 +1,8 @@
 // edt.hip -- exact Euclidean distance transform of a resident map's occupancy, the distance
 // field behind the single-lookup ESDF policy of Sec. III-D: for every voxel the squared
 // centre-to-centre distance, in voxels, to the nearest occupied voxel.  The squared distance
-// separates over the axes, so three passes of min over j of g_j + (i - j)^2 along x, then y,
-// then z (g starts as 0 on occupied voxels and "far" elsewhere).  All integer arithmetic.
+// separates over the axes, so three passes: the squared distance to the nearest occupied voxel
+// of each x row, then min over j of g_j + (i - j)^2 along y and along z.  Integer arithmetic.
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -16,36 +16,63 @@ namespace {
 
 constexpr int32_t kFar = 1 << 30;   // larger than any squared distance of an allowed grid
 
-// One block per line of len elements, `stride` apart, starting at `base`.  The first pass
-// (x rows, contiguous) stages 0 for occupied voxels and kFar for free ones; the others stage
-// the previous pass's values.  Every element then takes min over j of line_j + (i - j)^2,
-// searching outward from j = i and stopping once (i - j)^2 alone reaches the best value found
-// (every line_j is >= 0, so no farther j can be smaller): the same minimum as the full scan.
-// The last pass writes -1 where nothing was found (a grid without occupied voxels).
-template <int DT, bool FIRST>
-__global__ void __launch_bounds__(256) edt_lines_kernel(MapView m, int32_t *g, int32_t len, int64_t stride,
-                                                        int pass, int last_pass)
+// The x pass: one wave per row.  Per chunk of 64 voxels a ballot marks the occupied ones; the
+// nearest occupied voxel at or left of each lane is the highest set bit up to the lane (else
+// the last one of earlier chunks), found in a forward sweep over the chunks, and the nearest
+// at or right of it the lowest set bit from the lane on, in a backward sweep.  The row's
+// value is the square of the nearer of the two, kFar when the row has none.
+template <int DT>
+__global__ void __launch_bounds__(256) edt_rows_kernel(MapView m, int32_t *g)
+{
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= (int64_t)m.ny * m.nz) return;             // the same for the whole wave
+    using T = typename Voxel<DT>::T;
+    const T *data = static_cast<const T *>(m.data);
+    const int lane = threadIdx.x & 63;
+    const int32_t nx = m.nx;
+    const int64_t base = row * nx;
+    int32_t carry = -1;                                   // last occupied index of earlier chunks
+    for (int32_t c0 = 0; c0 < nx; c0 += 64) {
+        const int32_t i = c0 + lane;
+        const uint64_t mask = __ballot(i < nx && Voxel<DT>::occ(data[base + i]));
+        const uint64_t upto = lane == 63 ? mask : mask & ((2ull << lane) - 1ull);
+        if (i < nx) g[base + i] = upto ? c0 + 63 - __clzll(upto) : carry;
+        if (mask) carry = c0 + 63 - __clzll(mask);
+    }
+    carry = -1;                                           // first occupied index of later chunks
+    for (int32_t c0 = ((nx - 1) / 64) * 64; c0 >= 0; c0 -= 64) {
+        const int32_t i = c0 + lane;
+        const uint64_t mask = __ballot(i < nx && Voxel<DT>::occ(data[base + i]));
+        const uint64_t from = mask & (~0ull << lane);
+        const int32_t right = from ? c0 + __ffsll((unsigned long long)from) - 1 : carry;
+        if (i < nx) {
+            const int32_t left = g[base + i];
+            int32_t d = kFar;
+            if (left >= 0) d = i - left;
+            if (right >= 0 && right - i < d) d = right - i;
+            g[base + i] = d >= kFar ? kFar : d * d;
+        }
+        if (mask) carry = c0 + __ffsll((unsigned long long)mask) - 1;
+    }
+}
+
+// The y and z passes: one block per line of len elements, `stride` apart; line l starts at
+// (l % nx) + nx ny (l / nx) for y and at l for z.  The line is staged in LDS and every element
+// takes min over j of line_j + (i - j)^2, searching outward from j = i and stopping once
+// (i - j)^2 alone reaches the best value found (every line_j is >= 0, so no farther j can be
+// smaller): the same minimum as the full scan.  The last pass writes -1 where nothing was found
+// (a grid without occupied voxels).
+__global__ void __launch_bounds__(256) edt_lines_kernel(int32_t *g, int32_t len, int64_t stride, int32_t nx,
+                                                        int64_t plane, int y_pass, int last_pass)
 {
     extern __shared__ int32_t line[];
     const int64_t l = blockIdx.x;
-    const int64_t nx = m.nx, plane = (int64_t)m.nx * m.ny;
-    // pass 0: x rows; pass 1: y lines over (x, z); pass 2: z lines over (x, y)
-    const int64_t base = pass == 0 ? l * nx : (pass == 1 ? (l % nx) + plane * (l / nx) : l);
+    const int64_t base = y_pass ? (l % nx) + plane * (l / nx) : l;
     int found = 0;
-    if constexpr (FIRST) {
-        using T = typename Voxel<DT>::T;
-        const T *data = static_cast<const T *>(m.data);
-        for (int32_t i = threadIdx.x; i < len; i += blockDim.x) {
-            const int32_t v = Voxel<DT>::occ(data[base + i * stride]) ? 0 : kFar;
-            line[i] = v;
-            found |= v < kFar;
-        }
-    } else {
-        for (int32_t i = threadIdx.x; i < len; i += blockDim.x) {
-            const int32_t v = g[base + i * stride];
-            line[i] = v;
-            found |= v < kFar;
-        }
+    for (int32_t i = threadIdx.x; i < len; i += blockDim.x) {
+        const int32_t v = g[base + i * stride];
+        line[i] = v;
+        found |= v < kFar;
     }
     // a line with nothing finite stays "far" (the search below would scan all of it per element)
     if (!__syncthreads_or(found)) {
@@ -66,13 +93,12 @@ __global__ void __launch_bounds__(256) edt_lines_kernel(MapView m, int32_t *g, i
 template <int DT>
 hipError_t launch_edt_dt(const MapView &m, int32_t *out, hipStream_t s)
 {
-    const int64_t plane = (int64_t)m.nx * m.ny;
-    edt_lines_kernel<DT, true><<<(unsigned)((int64_t)m.ny * m.nz), 256, sizeof(int32_t) * (size_t)m.nx, s>>>(
-        m, out, m.nx, 1, 0, 0);
-    edt_lines_kernel<DT, false><<<(unsigned)((int64_t)m.nx * m.nz), 256, sizeof(int32_t) * (size_t)m.ny, s>>>(
-        m, out, m.ny, m.nx, 1, 0);
-    edt_lines_kernel<DT, false><<<(unsigned)plane, 256, sizeof(int32_t) * (size_t)m.nz, s>>>(m, out, m.nz, plane, 2,
-                                                                                           1);
+    const int64_t rows = (int64_t)m.ny * m.nz, plane = (int64_t)m.nx * m.ny;
+    edt_rows_kernel<DT><<<(unsigned)((rows + 3) / 4), 256, 0, s>>>(m, out);
+    edt_lines_kernel<<<(unsigned)((int64_t)m.nx * m.nz), 256, sizeof(int32_t) * (size_t)m.ny, s>>>(
+        out, m.ny, m.nx, m.nx, plane, 1, 0);
+    edt_lines_kernel<<<(unsigned)plane, 256, sizeof(int32_t) * (size_t)m.nz, s>>>(out, m.nz, plane, m.nx, plane, 0,
+                                                                                1);
     return hipGetLastError();
 }
 
