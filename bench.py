@@ -27,6 +27,8 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_2301_08068_amd/csrc/raycast.hip", "paper_2301_08068_amd/csrc/rmpc_device.h",
                   "paper_2301_08068_amd/csrc/rmpc_kernels.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "raycast_rmp_paper400_f32_traffic.txt")
+L2_FILE = os.path.join(ROOT, "profiles", "raycast_rmp_paper400_f32_instmix_l2.txt")
+L2_LINE_BYTES = 128
 
 CONFIGS = {
     # name: (map builder, encoding, state seed, rays, max range[, subvoxel])
@@ -48,21 +50,39 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on
-    the current kernel sources; None otherwise."""
-    if not os.path.exists(TRAFFIC_FILE):
+def _profile_values(path):
+    """key: value lines of a committed profile summary, or None when the file is missing or was
+    taken on other kernel sources than the current ones."""
+    if not os.path.exists(path):
         return None
     vals = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
+        line = line.lstrip("# ")
         if ":" in line:
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
+    return vals
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on
+    the current kernel sources; None otherwise."""
+    vals = _profile_values(TRAFFIC_FILE)
     try:
         return float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"])
-    except (KeyError, ValueError):
+    except (TypeError, KeyError, ValueError):
+        return None
+
+
+def measured_l2():
+    """L2 requests (TCC_HIT + TCC_MISS) and hit rate per launch from the committed rocprofv3
+    counter summary, if it was taken on the current kernel sources; None otherwise."""
+    vals = _profile_values(L2_FILE)
+    try:
+        return float(vals["l2_hits_per_launch"]) + float(vals["l2_misses_per_launch"]), float(vals["l2_hit_rate"])
+    except (TypeError, KeyError, ValueError):
         return None
 
 
@@ -73,32 +93,63 @@ def build_map(kind: str, enc: str):
     return vm, data
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (lscpu's "Model name", else /proc/cpuinfo's "model name")."""
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(vm, data, enc, x, v, n_rays, params, budget_s):
-    """The float64 oracle as it stands, all usable host cores, bounded wall time."""
+    """The float64 oracle as it stands, on every core of this process's affinity set and on one
+    core: each figure is the median of 5 runs (each run: full queries for about budget_s / 10 s
+    of wall time) after one warm-up query."""
     import oracle
     try:
-        threads = min(len(os.sched_getaffinity(0)), 16)
+        cores = len(os.sched_getaffinity(0))
     except AttributeError:
-        threads = min(os.cpu_count() or 1, 16)
+        cores = os.cpu_count() or 1
     om = oracle.OracleMap(data, vm.voxel_m, vm.origin_m, enc)
     dirs = oracle.directions(n_rays)
-    oracle.query(om, x, v, n_rays, params, nthreads=threads, dirs=dirs)   # warm-up
-    done, t0 = 0, time.perf_counter()
-    while True:
-        oracle.query(om, x, v, n_rays, params, nthreads=threads, dirs=dirs)
-        done += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s:
-            break
-    return {"value": done * n_rays / el, "unit": "rays/s", "cores": threads, "kind": "oracle",
-            "sample": f"{done} full queries of {n_rays} rays on the same map and state "
-                      f"({el:.1f} s wall, float64 C oracle, OpenMP over rays)"}
+    run_s = budget_s / 10.0
+
+    def one_run(threads):
+        done, t0 = 0, time.perf_counter()
+        while True:
+            oracle.query(om, x, v, n_rays, params, nthreads=threads, dirs=dirs)
+            done += 1
+            el = time.perf_counter() - t0
+            if el >= run_s:
+                return done, done * n_rays / el
+
+    rates = {}
+    for threads in (cores, 1):
+        oracle.query(om, x, v, n_rays, params, nthreads=threads, dirs=dirs)   # warm-up
+        runs = [one_run(threads) for _ in range(5)]
+        rates[threads] = (statistics.median(r for _, r in runs), sum(d for d, _ in runs))
+    return {"value": rates[cores][0], "unit": "rays/s", "cores": cores, "kind": "oracle",
+            "value_1_core": rates[1][0], "nproc": os.cpu_count(), "cpu_model": cpu_model(),
+            "sample": f"full queries of {n_rays} rays on the same map and state, float64 C oracle, OpenMP "
+                      f"over rays; median of 5 runs of ~{run_s:.1f} s after a warm-up query, on {cores} "
+                      f"cores ({rates[cores][1]} queries) and on 1 core ({rates[1][1]} queries)"}
 
 
-def batch_bench(args):
-    """Batched form (512 states along 8 trajectories, ray counts log-uniform in
-    [4096, 65536]): one tuned persistent launch per step, against 512 blocking queries."""
-    import numpy as np
+def batch_compare(steps, warmup, plain_repeats=1):
+    """Batched form (512 states along 8 trajectories, ray counts log-uniform in [4096, 65536]):
+    one tuned persistent launch per step replayed from a hipGraph, against the same 512 states
+    as blocking single queries (the plain path).  Returns rays/s of both and the tuned launch."""
     import torch
     from paper_2301_08068_amd import binding
     from paper_2301_08068_amd import workloads as W
@@ -107,38 +158,51 @@ def batch_bench(args):
     counts = W.ray_counts(len(xs), seed=399)
     params = W.params("static", max_range=10.0)
     ctx = binding.Context(0, arena_bytes=1 << 30)
-    mid = ctx.upload(vm.tsdf, vm.voxel_m, vm.origin_m, "f32")
-    qs = [dict(kind="map", map_id=mid, n=int(n), x=x, v=v) for x, v, n in zip(xs, vs, counts)]
-    descs = binding.query_descs(qs)
-    tuned = binding.rmpc_tune_batch(ctx.ptr, descs, params, None)
-    ctx.config(binding.CONFIG_BATCH, use_graph=1)
-    total = int(counts.sum())
-    for _ in range(args.warmup):
-        binding.rmpc_query_batch(ctx.ptr, descs, params, None, stream=ctx.stream)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        binding.rmpc_query_batch(ctx.ptr, descs, params, None, stream=ctx.stream)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    # the plain path: one blocking query per state
-    for q in qs[:16]:
-        ctx.query(mid, q["x"], q["v"], q["n"], params)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for q in qs:
-        ctx.query(mid, q["x"], q["v"], q["n"], params)
-    plain = time.perf_counter() - t1
+    try:
+        mid = ctx.upload(vm.tsdf, vm.voxel_m, vm.origin_m, "f32")
+        qs = [dict(kind="map", map_id=mid, n=int(n), x=x, v=v) for x, v, n in zip(xs, vs, counts)]
+        descs = binding.query_descs(qs)
+        tuned = binding.rmpc_tune_batch(ctx.ptr, descs, params, None)
+        ctx.config(binding.CONFIG_BATCH, use_graph=1)
+        total = int(counts.sum())
+        for _ in range(warmup):
+            binding.rmpc_query_batch(ctx.ptr, descs, params, None, stream=ctx.stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            binding.rmpc_query_batch(ctx.ptr, descs, params, None, stream=ctx.stream)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        # the plain path: one blocking query per state
+        preps = [binding.PreparedQuery(ctx.ptr, mid, q["x"], q["v"], q["n"], params, stream=ctx.stream)
+                 for q in qs]
+        for pq in preps[:16]:
+            pq()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(plain_repeats):
+            for pq in preps:
+                pq()
+        plain = (time.perf_counter() - t1) / plain_repeats
+    finally:
+        ctx.close()
+    return {"rays_per_step": total, "states": len(qs), "batch_ms": 1e3 * el / steps,
+            "batch_rays_per_s": total * steps / el, "plain_ms": 1e3 * plain, "plain_rays_per_s": total / plain,
+            "tuned": tuned}
+
+
+def batch_bench(args):
+    """The batched form as its own bench line."""
+    r = batch_compare(args.steps, args.warmup, plain_repeats=3)
     out = {"metric": "rays/sec (raycast+RMP+resolve), 512 states of uneven ray counts per launch",
-           "value": total * args.steps / el, "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps, "higher_is_better": True,
+           "value": r["batch_rays_per_s"], "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": r["batch_ms"], "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "512 states on 8 seeded trajectories through the 400^3 f32 map; "
                                   "ray counts log-uniform in [4096, 65536]; one persistent launch per "
                                   "step replayed from a hipGraph",
-                      "rays_per_step": total, "tuned": tuned,
-                      "plain_rays_per_s": total / plain, "plain_ms": 1e3 * plain}}
-    ctx.close()
+                      "rays_per_step": r["rays_per_step"], "tuned": r["tuned"],
+                      "plain_rays_per_s": r["plain_rays_per_s"], "plain_ms": r["plain_ms"]}}
     print(json.dumps(out), flush=True)
 
 
@@ -292,12 +356,13 @@ def edt_bench(args):
     ctx.close()
 
 
-def serve_bench(args):
+def serve_compare(n_requests, rates, slots, check_alone=True):
     """Serving: an open-loop Poisson stream of half grid-raycast requests (ray counts
     log-uniform in [4096, 65536]) and half 64 x 1024 LiDAR-scan requests (points staged from
     pinned host memory) over four resident maps (two 400^3 fp16 TSDF, two 256^3 u8
     occupancy), continuous batching over several launch slots against a one-request-per-launch
-    server on the same stream."""
+    server.  Returns one row per rate, the resident map bytes, the launch configuration and how
+    many sampled results equal the result of the same request alone."""
     import numpy as np
     import torch
     from paper_2301_08068_amd import binding
@@ -305,74 +370,87 @@ def serve_bench(args):
     vms = [("f16", W.paper_map(10)), ("f16", W.paper_map(11)), ("u8", W.occ_source_map(12)),
            ("u8", W.occ_source_map(13))]
     ctx = binding.Context(0, arena_bytes=2 << 30)
-    mids, resident = [], 0
-    for enc, vm in vms:
-        data = W.encode_f16(vm.tsdf) if enc == "f16" else W.encode_u8(vm.tsdf)
-        resident += data.nbytes
-        mids.append(ctx.upload(data, vm.voxel_m, vm.origin_m, enc))
-    n_states, n_scans = 64, 2
-    states = [[W.free_state(vm, 1000 * m + k) for k in range(n_states)] for m, (_, vm) in enumerate(vms)]
-    scans = [[torch.from_numpy(W.synth_scan(vm, states[m][k][0], 600 + 10 * m + k)).pin_memory()
-              for k in range(n_scans)] for m, (_, vm) in enumerate(vms)]
-    mp, sp = W.params("static", max_range=10.0), W.params("lidar")
-    n = args.serve_requests
-    rng = np.random.default_rng(501)
-    is_grid = rng.uniform(size=n) < 0.5
-    m_idx = rng.integers(0, len(vms), size=n)
-    s_idx = rng.integers(0, n_states, size=n)
-    c_idx = rng.integers(0, n_scans, size=n)
-    counts = W.ray_counts(n, seed=399)
-    reqs, units = [], np.zeros(n)
-    for j in range(n):
-        m, (x, v) = int(m_idx[j]), states[int(m_idx[j])][int(s_idx[j])]
-        if is_grid[j]:
-            q = dict(kind="map", map_id=mids[m], n=int(counts[j]), x=x, v=v)
-            reqs.append(binding.request(q))
-            units[j] = counts[j]
-        else:
-            pts = scans[m][int(c_idx[j])]
-            reqs.append(binding.request(dict(kind="scan", n=pts.shape[0], v=states[m][int(c_idx[j])][1]),
-                                        pts.data_ptr()))
-            units[j] = pts.shape[0]
-    launch = ctx.config(binding.CONFIG_BATCH)
-    scan_bytes = 12 * 65536
-    modes = {
-        "continuous": dict(n_slots=args.serve_slots, max_batch=256, map_params=mp, scan_params=sp,
-                           launch=launch, staging_bytes=64 * scan_bytes),
-        "one_per_launch": dict(n_slots=1, max_batch=1, map_params=mp, scan_params=sp, launch=launch,
-                               staging_bytes=2 * scan_bytes),
-    }
-    # equality with the alone result on a sample of the mix
-    sample = list(range(0, n, max(1, n // 48)))[:48]
-    rows = []
-    for rate in SERVE_RATES:
-        arrivals = W.poisson_arrivals(rate, n, seed=500)
-        row = {"rate_req_s": rate}
-        for name, kw in modes.items():
-            row[name] = _serve_rate(binding, ctx, reqs, units, is_grid, arrivals, kw, reqs[:64])
-            print(json.dumps({"progress": f"rate {rate} {name}", **row[name]}), file=sys.stderr, flush=True)
-        rows.append(row)
-    binding.rmpc_server_start(ctx.ptr, **modes["continuous"])
     try:
-        tks = [binding.rmpc_submit(ctx.ptr, reqs[j]) for j in sample]
-        got = {}
-        while len(got) < len(tks):
-            for t, r, _ in binding.rmpc_poll_completed(ctx.ptr, 64):
-                got[t] = r
+        mids, resident = [], 0
+        for enc, vm in vms:
+            data = W.encode_f16(vm.tsdf) if enc == "f16" else W.encode_u8(vm.tsdf)
+            resident += data.nbytes
+            mids.append(ctx.upload(data, vm.voxel_m, vm.origin_m, enc))
+        n_states, n_scans = 64, 2
+        states = [[W.free_state(vm, 1000 * m + k) for k in range(n_states)] for m, (_, vm) in enumerate(vms)]
+        scans = [[torch.from_numpy(W.synth_scan(vm, states[m][k][0], 600 + 10 * m + k)).pin_memory()
+                  for k in range(n_scans)] for m, (_, vm) in enumerate(vms)]
+        mp, sp = W.params("static", max_range=10.0), W.params("lidar")
+        n = n_requests
+        rng = np.random.default_rng(501)
+        is_grid = rng.uniform(size=n) < 0.5
+        m_idx = rng.integers(0, len(vms), size=n)
+        s_idx = rng.integers(0, n_states, size=n)
+        c_idx = rng.integers(0, n_scans, size=n)
+        counts = W.ray_counts(n, seed=399)
+        reqs, units = [], np.zeros(n)
+        for j in range(n):
+            m, (x, v) = int(m_idx[j]), states[int(m_idx[j])][int(s_idx[j])]
+            if is_grid[j]:
+                q = dict(kind="map", map_id=mids[m], n=int(counts[j]), x=x, v=v)
+                reqs.append(binding.request(q))
+                units[j] = counts[j]
+            else:
+                pts = scans[m][int(c_idx[j])]
+                reqs.append(binding.request(dict(kind="scan", n=pts.shape[0], v=states[m][int(c_idx[j])][1]),
+                                            pts.data_ptr()))
+                units[j] = pts.shape[0]
+        launch = ctx.config(binding.CONFIG_BATCH)
+        scan_bytes = 12 * 65536
+        modes = {
+            "continuous": dict(n_slots=slots, max_batch=256, map_params=mp, scan_params=sp,
+                               launch=launch, staging_bytes=64 * scan_bytes),
+            "one_per_launch": dict(n_slots=1, max_batch=1, map_params=mp, scan_params=sp, launch=launch,
+                                   staging_bytes=2 * scan_bytes),
+        }
+        rows = []
+        for rate in rates:
+            arrivals = W.poisson_arrivals(rate, n, seed=500)
+            row = {"rate_req_s": rate}
+            for name, kw in modes.items():
+                row[name] = _serve_rate(binding, ctx, reqs, units, is_grid, arrivals, kw, reqs[:64])
+                print(json.dumps({"progress": f"rate {rate} {name}", **row[name]}), file=sys.stderr, flush=True)
+            rows.append(row)
+        equal, sample = 0, []
+        if check_alone:
+            # equality with the alone result on a sample of the mix
+            sample = list(range(0, n, max(1, n // 48)))[:48]
+            binding.rmpc_server_start(ctx.ptr, **modes["continuous"])
+            try:
+                tks = [binding.rmpc_submit(ctx.ptr, reqs[j]) for j in sample]
+                got = {}
+                while len(got) < len(tks):
+                    for t, r, _ in binding.rmpc_poll_completed(ctx.ptr, 64):
+                        got[t] = r
+            finally:
+                binding.rmpc_server_stop(ctx.ptr)
+            for t, j in zip(tks, sample):
+                q = reqs[j].q
+                if q.kind == binding.KIND_MAP:
+                    alone = ctx.query_batch([dict(kind="map", map_id=q.map_id, n=q.n, x=list(q.x), v=list(q.v))],
+                                            map_params=mp)[0]
+                else:
+                    m = int(m_idx[j])
+                    alone = ctx.query_batch([dict(kind="scan", points=scans[m][int(c_idx[j])].cuda(), v=list(q.v))],
+                                            scan_params=sp)[0]
+                equal += int(np.array_equal(got[t]["f"], alone["f"]) and np.array_equal(got[t]["S"], alone["S"]))
     finally:
-        binding.rmpc_server_stop(ctx.ptr)
-    equal = 0
-    for t, j in zip(tks, sample):
-        q = reqs[j].q
-        if q.kind == binding.KIND_MAP:
-            alone = ctx.query_batch([dict(kind="map", map_id=q.map_id, n=q.n, x=list(q.x), v=list(q.v))],
-                                    map_params=mp)[0]
-        else:
-            m = int(m_idx[j])
-            alone = ctx.query_batch([dict(kind="scan", points=scans[m][int(c_idx[j])].cuda(), v=list(q.v))],
-                                    scan_params=sp)[0]
-        equal += int(np.array_equal(got[t]["f"], alone["f"]) and np.array_equal(got[t]["S"], alone["S"]))
+        ctx.close()
+    return {"rows": rows, "resident_map_bytes": resident, "launch": launch,
+            "sample_equal_alone": f"{equal}/{len(sample)}"}
+
+
+def serve_bench(args):
+    """The serving loop as its own bench line (four rates, args.serve_requests each)."""
+    r = serve_compare(args.serve_requests, SERVE_RATES, args.serve_slots)
+    rows = r["rows"]
     top = rows[-1]["continuous"]
+    n = args.serve_requests
     out = {"metric": METRIC, "value": top["evals_per_s"], "unit": "ray-policy evaluations/s (grid rays + scan points)",
            "n_gpus": 1, "steps": n, "warmup": 64, "ms_per_step": None, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f16/u8 maps, f32 sums, f64 resolve",
@@ -381,9 +459,8 @@ def serve_bench(args):
                                   "queries (rays log-uniform in [4096, 65536]) and 50 % 64x1024 LiDAR scans "
                                   "(pinned host points, staged by the server); 4 resident maps (two 400^3 fp16 "
                                   "TSDF, two 256^3 u8 occupancy)",
-                      "resident_map_bytes": resident, "launch": launch, "slots": args.serve_slots,
-                      "rates": rows, "sample_equal_alone": f"{equal}/{len(sample)}"}}
-    ctx.close()
+                      "resident_map_bytes": r["resident_map_bytes"], "launch": r["launch"], "slots": args.serve_slots,
+                      "rates": rows, "sample_equal_alone": r["sample_equal_alone"]}}
     print(json.dumps(out), flush=True)
 
 
@@ -491,6 +568,10 @@ def main():
     ap.add_argument("--lane-target", type=int, default=0, help="query launch: log2 of the lanes a query aims for")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="paper config: skip the batched-vs-plain and served-latency passes")
+    ap.add_argument("--extras-requests", type=int, default=2000,
+                    help="paper config: requests per rate of the served-latency pass")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device copy of this many bytes 20 times (counter "
                          "calibration for HBM traffic) and exit")
@@ -562,16 +643,62 @@ def main():
     elapsed = clock() - t0
     # kernel duration: a separate pass with each dispatch's own start/stop events
     binding.rmpc_set_profiling(ctx.ptr, True)
-    for _ in range(min(args.steps, 100)):
+    for _ in range(max(args.steps, 100)):
         step()
     kms, nl = binding.rmpc_get_profile(ctx.ptr)
     binding.rmpc_set_profiling(ctx.ptr, False)
+    ctx.close()
 
     kern_s = kms / 1e3 / max(nl, 1)
     alg_bytes = visits * ELEM_BYTES[enc] + 12 * n_rays
     achieved = alg_bytes / kern_s / 1e9
     traffic = measured_traffic() if args.config == "paper" else None
+    l2 = measured_l2() if args.config == "paper" else None
     lat_us = sorted(1e6 * t for t in lat)
+    shape = "400^3 0.05 m, 200 primitives + walls, seed 2" if kind == "paper" else "64^3 0.1 m, 20 spheres + floor, seed 1"
+    config = {
+        "workload": f"{shape}; {enc} map; 1 state (seed {seed}); {n_rays} Halton rays, {rmax:g} m; blocking query",
+        "rays_per_query": n_rays,
+        "map_storage": enc,
+        "subvoxel_distances": bool(subvoxel),
+        "occupied_fraction": round(vm.occupied_fraction(), 4),
+        "mean_visits_per_ray": round(visits / n_rays, 2),
+        "latency_p50_us": round(lat_us[len(lat_us) // 2], 1),
+        "latency_p99_us": round(lat_us[min(len(lat_us) - 1, int(0.99 * len(lat_us)))], 1),
+        "kernel_us": round(kern_s * 1e6, 2),
+        "kernel_launches_timed": nl,
+        "launch_lookahead": launch["lookahead"],
+        "launch_lane_target_log2": launch["lane_target_log2"],
+    }
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "kernel": "raycast_rmp_kernel",
+                "algorithmic_bytes_per_launch": alg_bytes,
+                "limiter": "latency: the dependent round chain of the slowest waves, then the reduction tail"}
+    if l2 is not None:
+        req, hit_rate = l2
+        roofline["l2_bytes_per_launch"] = int(req * L2_LINE_BYTES)
+        roofline["l2_gbs"] = round(req * L2_LINE_BYTES / kern_s / 1e9, 1)
+        roofline["l2_hit_rate"] = hit_rate
+    if args.config == "paper" and not args.no_extras:
+        # the metric's second half: the batched form against the plain path, and served p50/p99
+        b = batch_compare(steps=5, warmup=2)
+        config["batch_states"] = b["states"]
+        config["batch_rays_per_s"] = round(b["batch_rays_per_s"])
+        config["plain_rays_per_s"] = round(b["plain_rays_per_s"])
+        config["batch_over_plain"] = round(b["batch_rays_per_s"] / b["plain_rays_per_s"], 2)
+        sv = serve_compare(args.extras_requests, (2000, 20000), args.serve_slots, check_alone=True)
+        for row in sv["rows"]:
+            r = row["rate_req_s"]
+            for mode, tag in (("continuous", "served"), ("one_per_launch", "one_per_launch")):
+                m = row[mode]
+                config[f"{tag}_{r}_p50_ms"] = m["p50_ms"]
+                config[f"{tag}_{r}_p99_ms"] = m["p99_ms"]
+                if mode == "continuous":
+                    config[f"{tag}_{r}_mean_batch"] = m["mean_batch"]
+                    config[f"{tag}_{r}_evals_per_s"] = round(m["evals_per_s"])
+        config["served_requests_per_rate"] = args.extras_requests
+        config["served_equal_alone"] = sv["sample_equal_alone"]
     out = {
         "metric": METRIC,
         "value": n_rays * args.steps / elapsed,
@@ -585,28 +712,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {
-            "workload": (f"{'paper-shaped 400^3 (0.05 m, 200 spheres/boxes + walls, map seed 2)' if kind == 'paper' else 'tiny 64^3 (0.1 m, 20 spheres + floor, map seed 1)'} "
-                         f"{enc} voxel map; one state (seed {seed}); {n_rays} Halton rays per query; "
-                         f"max range {rmax} m; blocking query with result readback"),
-            "rays_per_query": n_rays,
-            "map_storage": enc,
-            "subvoxel_distances": bool(subvoxel),
-            "occupied_fraction": round(vm.occupied_fraction(), 4),
-            "mean_visits_per_ray": round(visits / n_rays, 2),
-            "latency_us": {"p50": round(lat_us[len(lat_us) // 2], 1),
-                           "p99": round(lat_us[min(len(lat_us) - 1, int(0.99 * len(lat_us)))], 1)},
-            "kernel_us": round(kern_s * 1e6, 2),
-            "launch": launch,
-        },
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "raycast_rmp_kernel",
-                     "algorithmic_bytes_per_launch": alg_bytes},
+        "config": config,
+        "roofline": roofline,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(vm, data, enc, x, v, n_rays, params, args.cpu_seconds)
-    ctx.close()
     print(json.dumps(out), flush=True)
 
 

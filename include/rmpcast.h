@@ -151,6 +151,15 @@ rmpc_status rmpc_map_upload(rmpc_ctx *ctx, const rmpc_map_desc *desc, const void
 rmpc_status rmpc_map_release(rmpc_ctx *ctx, int32_t map_id);
 
 /*
+ * rmpc_map_footprint -- arena bytes that rmpc_map_upload of this grid takes (the grid plus its
+ * cell and brick summaries, before the arena's 256-byte rounding), for sizing an arena.  Makes
+ * no GPU call.  The same descriptor checks as rmpc_map_upload apply; in particular the grid
+ * must hold fewer than 2^31 voxels (linear indices are int32).
+ * Errors: RMPC_E_INVALID.
+ */
+rmpc_status rmpc_map_footprint(const rmpc_map_desc *desc, size_t *bytes);
+
+/*
  * rmpc_query -- the raycasting policy P_ray of one robot state (Sec. III-E Eq. 11).
  *   x, v: position (world, metres) and velocity, float64 host arrays of 3.
  *   n_rays: 1 <= n_rays <= RMPC_MAX_RAYS; rays are Halton indices 0 .. n_rays-1.
@@ -358,8 +367,8 @@ rmpc_status rmpc_server_stats(rmpc_ctx *ctx, rmpc_server_counters *out);
 rmpc_status rmpc_server_stop(rmpc_ctx *ctx);
 
 /* ------------------------------------------------------------------------------------------
- * Closed-loop rollout: the ray policy summed with the goal attractor of Sec. III-B (Eq. 2,
- * metric I; s of Eq. 3 with params->c), resolved (Eq. 1) and integrated step by step, as the
+ * Closed-loop rollout: the ray policy summed with the goal attractor of Sec. III-C (Eq. 3,
+ * metric I; s of Eq. 4 with params->c), resolved (Eq. 1) and integrated step by step, as the
  * paper's simulated flights do (Sec. IV-A).
  * ------------------------------------------------------------------------------------------ */
 

@@ -257,7 +257,7 @@ def scan(points: np.ndarray, v, p: Dict[str, float]) -> Dict:
 
 
 # ------------------------------------------------------------------------------------------
-# closed-loop rollout (Sec. III-A Eq. 1 with the goal attractor of Sec. III-B): the ray policy
+# closed-loop rollout (Sec. III-A Eq. 1 with the goal attractor of Sec. III-C): the ray policy
 # summed with the attractor (metric I), resolved and integrated step by step
 # ------------------------------------------------------------------------------------------
 
@@ -265,7 +265,7 @@ ROLLOUT_GOAL, ROLLOUT_COLLISION, ROLLOUT_LEFT_GRID, ROLLOUT_TIMEOUT = 1, 2, 3, 4
 
 
 def attractor(goal, x, v, alpha: float, beta: float, c: float) -> np.ndarray:
-    """Goal attractor force (Sec. III-B Eq. 2): alpha s(goal - x) - beta v, s of Eq. 3."""
+    """Goal attractor force (Sec. III-C Eq. 3): alpha s(goal - x) - beta v, s of Eq. 4."""
     return alpha * soft_normalize(np.asarray(goal, np.float64) - np.asarray(x, np.float64), c) \
         - beta * np.asarray(v, np.float64)
 

@@ -111,6 +111,7 @@ _SIGS = {
     "rmpc_destroy": [C.c_void_p],
     "rmpc_map_upload": [C.c_void_p, _P(MapDesc), C.c_void_p, C.c_int, C.c_void_p, _P(C.c_int32)],
     "rmpc_map_release": [C.c_void_p, C.c_int32],
+    "rmpc_map_footprint": [_P(MapDesc), _P(C.c_size_t)],
     "rmpc_query": [C.c_void_p, C.c_int32, _P(C.c_double), _P(C.c_double), C.c_int32, _P(Params),
                    C.c_void_p, _P(Result)],
     "rmpc_scan_query": [C.c_void_p, C.c_void_p, C.c_int32, _P(C.c_double), _P(Params), C.c_void_p,
@@ -209,6 +210,13 @@ def rmpc_map_upload(ctx: int, nx: int, ny: int, nz: int, dtype: str, voxel_m: fl
                                 int(bool(on_device)), C.c_void_p(_stream_ptr(stream)), C.byref(mid)),
            "rmpc_map_upload")
     return mid.value
+
+
+def rmpc_map_footprint(nx: int, ny: int, nz: int, dtype: str, voxel_m: float, origin_m) -> int:
+    d = MapDesc(nx, ny, nz, DTYPES[dtype], voxel_m, _d3(origin_m))
+    out = C.c_size_t()
+    _check(_lib.rmpc_map_footprint(C.byref(d), C.byref(out)), "rmpc_map_footprint")
+    return out.value
 
 
 def rmpc_map_release(ctx: int, map_id: int) -> None:

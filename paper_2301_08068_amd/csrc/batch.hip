@@ -95,7 +95,7 @@ rmpc_status batch_describe(rmpc_ctx *ctx, const rmpc_query_desc &d, int k, const
         Q.n_tiles = (Q.ray.n_list * Q.ray.segments + rmpc::kBlockThreads - 1) / rmpc::kBlockThreads;
     } else if (d.kind == RMPC_KIND_SCAN) {
         if (!finite3(d.v)) return fail(RMPC_E_INVALID, where + "velocity not finite");
-        if (d.n < 0 || d.n > (1 << 24)) return fail(RMPC_E_INVALID, where + "n_points out of [0, 2^24]");
+        if (d.n < 0 || d.n > kMaxScanPoints) return fail(RMPC_E_INVALID, where + "n_points out of [0, 2^24]");
         if (d.n > 0 && !d.points_dev) return fail(RMPC_E_INVALID, where + "points_dev is NULL");
         if (rmpc_status st = check_params(sp)) {
             g_last_error = where + g_last_error;

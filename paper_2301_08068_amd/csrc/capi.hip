@@ -191,7 +191,8 @@ rmpc_status setup_query(rmpc_ctx *ctx, int32_t map_id, const double x[3], int32_
     A.map = me.view;
     A.subvoxel = params->subvoxel != 0;
     A.n_rays = n_rays;
-    A.lin0 = A.v0[0] + n[0] * (A.v0[1] + n[1] * A.v0[2]);
+    // below 2^31 for every accepted grid (rmpc_map_upload refuses larger ones)
+    A.lin0 = (int32_t)((int64_t)A.v0[0] + (int64_t)n[0] * ((int64_t)A.v0[1] + (int64_t)n[1] * A.v0[2]));
     A.start_flags = start_flags;
     const double tmax = params->max_range_m / me.desc.voxel_m;
     A.tmax_lo = (float)(tmax * (1.0 - 1e-6) - 2e-5);
@@ -248,6 +249,56 @@ rmpc_status account_profile(rmpc_ctx *ctx)
 }
 
 
+// Validates a dense map's descriptor and lays it out: the grid, then one summary element per
+// whole 8^3 cell and one per whole 2^3 brick, each at an offset rounded up to 256 elements.
+// Linear voxel indices must fit int32 (the per-ray debug output and the query's start index are
+// int32), and every element offset uint32.
+rmpc_status dense_layout(const rmpc_map_desc &d, rmpc::MapView &v, uint64_t &n_all)
+{
+    if (d.nx < 1 || d.ny < 1 || d.nz < 1 || d.nx > kMaxDim || d.ny > kMaxDim || d.nz > kMaxDim)
+        return fail(RMPC_E_INVALID, "grid dimensions out of [1, 4096]");
+    if (d.dtype != RMPC_TSDF_F32 && d.dtype != RMPC_TSDF_F16 && d.dtype != RMPC_OCC_U8)
+        return fail(RMPC_E_INVALID, "unknown dtype");
+    if (!(d.voxel_m > 0) || !std::isfinite(d.voxel_m) || !finite3(d.origin_m))
+        return fail(RMPC_E_INVALID, "voxel size or origin invalid");
+    const uint64_t n_log = (uint64_t)d.nx * d.ny * d.nz;
+    if (n_log >= (1ull << 31)) return fail(RMPC_E_INVALID, "grid has 2^31 voxels or more (linear indices are int32)");
+    std::memset(&v, 0, sizeof v);
+    v.nx = d.nx; v.ny = d.ny; v.nz = d.nz; v.dtype = d.dtype;
+    v.ncx = d.nx >> rmpc::kCellLog2;
+    v.ncy = d.ny >> rmpc::kCellLog2;
+    v.ncz = d.nz >> rmpc::kCellLog2;
+    v.nbx = d.nx >> rmpc::kBrickLog2;
+    v.nby = d.ny >> rmpc::kBrickLog2;
+    v.nbz = d.nz >> rmpc::kBrickLog2;
+    const uint64_t cell_base = (n_log + 255) / 256 * 256;
+    const uint64_t brick_base = (cell_base + (uint64_t)v.ncx * v.ncy * v.ncz + 255) / 256 * 256;
+    n_all = brick_base + (uint64_t)v.nbx * v.nby * v.nbz;
+    if (n_all >= (1ull << 32)) return fail(RMPC_E_INVALID, "grid too large for 32-bit voxel offsets");
+    v.cell_base = (uint32_t)cell_base;
+    v.brick_base = (uint32_t)brick_base;
+    return RMPC_OK;
+}
+
+// Validates a scan query and fills everything of ScanArgs but its reduction slots.
+rmpc_status setup_scan(const float *points_dev, int32_t n_points, const double v[3], const rmpc_params *params,
+                       rmpc::ScanArgs &A)
+{
+    if (n_points < 0 || n_points > kMaxScanPoints) return fail(RMPC_E_INVALID, "n_points out of [0, 2^24]");
+    if (n_points > 0 && !points_dev) return fail(RMPC_E_INVALID, "points_dev is NULL");
+    if (!finite3(v)) return fail(RMPC_E_INVALID, "velocity is NULL or not finite");
+    if (rmpc_status st = check_params(params)) return st;
+    std::memset(&A, 0, sizeof A);
+    A.points = points_dev;
+    A.n_points = n_points;
+    A.min_range2 = params->min_range_m * params->min_range_m;
+    for (int a = 0; a < 3; ++a) A.vel64[a] = v[a];
+    A.radius64 = params->radius;
+    A.pol = policy_f(params, v);
+    A.rank_tol = params->rank_tol;
+    return RMPC_OK;
+}
+
 }  // namespace rmpc_host
 
 using namespace rmpc_host;
@@ -279,25 +330,33 @@ rmpc_status rmpc_create(int device, void *arena_dev, size_t arena_bytes, rmpc_ct
     c->ev_dep = nullptr;
     c->server = nullptr;
     c->cu_count = 0;
-    if (hipDeviceGetAttribute(&c->cu_count, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
-        c->cu_count < 1) {
-        delete c;
-        return fail(RMPC_E_HIP, "cannot read the device's compute-unit count");
-    }
     c->profiling = false;
     c->ev0 = c->ev1 = nullptr;
     c->prof_ms = 0.0;
     c->prof_n = 0;
+    c->result_host = nullptr;
+    c->done_host = nullptr;
+    c->seq = 0;
+    // every failure below ends here: work already queued on the null stream may still write
+    // into the caller's arena, so it is waited for before the pinned buffers and the context go
+    auto abandon = [c](rmpc_status st, const std::string &msg) {
+        (void)hipStreamSynchronize(nullptr);
+        if (c->result_host) (void)hipHostFree(c->result_host);
+        if (c->done_host) (void)hipHostFree(c->done_host);
+        delete c;
+        return fail(st, msg);
+    };
+    if (hipDeviceGetAttribute(&c->cu_count, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+        c->cu_count < 1)
+        return abandon(RMPC_E_HIP, "cannot read the device's compute-unit count");
     size_t o_dirs, o_part, o_ticket, o_order, o_counts, o_tmp;
     if (!c->alloc.alloc(sizeof(float) * 3 * RMPC_MAX_RAYS, &o_dirs) ||
         !c->alloc.alloc(sizeof(int32_t) * RMPC_MAX_RAYS, &o_order) ||
         !c->alloc.alloc(sizeof(int32_t) * RMPC_MAX_RAYS, &o_tmp) ||
         !c->alloc.alloc(sizeof(int32_t) * 1024, &o_counts) ||
         !c->alloc.alloc(sizeof(float) * rmpc::kMaxPartialSlots * rmpc::kPartialWords, &o_part) ||
-        !c->alloc.alloc(256, &o_ticket)) {
-        delete c;
-        return fail(RMPC_E_NOMEM, "arena too small for the context tables");
-    }
+        !c->alloc.alloc(256, &o_ticket))
+        return abandon(RMPC_E_NOMEM, "arena too small for the context tables");
     c->dirs = reinterpret_cast<float *>(c->arena + o_dirs);
     c->order = reinterpret_cast<int32_t *>(c->arena + o_order);
     c->counts = reinterpret_cast<int32_t *>(c->arena + o_counts);
@@ -307,18 +366,16 @@ rmpc_status rmpc_create(int device, void *arena_dev, size_t arena_bytes, rmpc_ct
     hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&c->result_host), sizeof(rmpc_result),
                                  hipHostMallocCoherent);
     if (e != hipSuccess) {
-        delete c;
-        return fail(RMPC_E_HIP, std::string("hipHostMalloc: ") + hipGetErrorString(e));
+        c->result_host = nullptr;
+        return abandon(RMPC_E_HIP, std::string("hipHostMalloc: ") + hipGetErrorString(e));
     }
     std::memset(c->result_host, 0, sizeof(rmpc_result));
     e = hipHostMalloc(reinterpret_cast<void **>(&c->done_host), 64, hipHostMallocCoherent);
     if (e != hipSuccess) {
-        (void)hipHostFree(c->result_host);
-        delete c;
-        return fail(RMPC_E_HIP, std::string("hipHostMalloc: ") + hipGetErrorString(e));
+        c->done_host = nullptr;
+        return abandon(RMPC_E_HIP, std::string("hipHostMalloc: ") + hipGetErrorString(e));
     }
     *c->done_host = 0;
-    c->seq = 0;
     rmpc::DirsArgs da{c->dirs, RMPC_MAX_RAYS};
     e = hipMemsetAsync(c->ticket, 0, 256, nullptr);
     if (e == hipSuccess) e = rmpc::launch_directions(da, nullptr);
@@ -335,12 +392,8 @@ rmpc_status rmpc_create(int device, void *arena_dev, size_t arena_bytes, rmpc_ct
     for (size_t k = 0; k < c->ladder.size() && e == hipSuccess; ++k) {
         const int32_t n = c->ladder[k];
         size_t off;
-        if (!c->alloc.alloc(sizeof(rmpc::RayRec) * (size_t)n, &off)) {
-            (void)hipHostFree(c->result_host);
-            (void)hipHostFree(c->done_host);
-            delete c;
-            return fail(RMPC_E_NOMEM, "arena too small for the ray lists");
-        }
+        if (!c->alloc.alloc(sizeof(rmpc::RayRec) * (size_t)n, &off))
+            return abandon(RMPC_E_NOMEM, "arena too small for the ray lists");
         rmpc::RayRec *list = reinterpret_cast<rmpc::RayRec *>(c->arena + off);
         const int32_t *idx = c->order;
         if (n < RMPC_MAX_RAYS) {
@@ -353,11 +406,7 @@ rmpc_status rmpc_create(int device, void *arena_dev, size_t arena_bytes, rmpc_ct
         c->ladder_lists.push_back(list);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
-    if (e != hipSuccess) {
-        (void)hipHostFree(c->result_host);
-        delete c;
-        return fail(RMPC_E_HIP, std::string("context setup: ") + hipGetErrorString(e));
-    }
+    if (e != hipSuccess) return abandon(RMPC_E_HIP, std::string("context setup: ") + hipGetErrorString(e));
     *out = c;
     return RMPC_OK;
 }
@@ -378,36 +427,27 @@ rmpc_status rmpc_destroy(rmpc_ctx *ctx)
     return RMPC_OK;
 }
 
+rmpc_status rmpc_map_footprint(const rmpc_map_desc *desc, size_t *bytes)
+{
+    if (!desc || !bytes) return fail(RMPC_E_INVALID, "NULL argument");
+    rmpc::MapView v;
+    uint64_t n_all;
+    if (rmpc_status st = dense_layout(*desc, v, n_all)) return st;
+    *bytes = (size_t)(n_all * elem_bytes(desc->dtype));
+    return RMPC_OK;
+}
+
 rmpc_status rmpc_map_upload(rmpc_ctx *ctx, const rmpc_map_desc *desc, const void *voxels,
                             int voxels_on_device, void *hip_stream, int32_t *map_id_out)
 {
     if (!ctx || !desc || !voxels || !map_id_out) return fail(RMPC_E_INVALID, "NULL argument");
     if (ctx->server) return fail(RMPC_E_INVALID, "maps cannot change while the server runs");
-    if (desc->nx < 1 || desc->ny < 1 || desc->nz < 1 || desc->nx > kMaxDim || desc->ny > kMaxDim ||
-        desc->nz > kMaxDim)
-        return fail(RMPC_E_INVALID, "grid dimensions out of [1, 4096]");
-    if (desc->dtype != RMPC_TSDF_F32 && desc->dtype != RMPC_TSDF_F16 && desc->dtype != RMPC_OCC_U8)
-        return fail(RMPC_E_INVALID, "unknown dtype");
-    if (!(desc->voxel_m > 0) || !std::isfinite(desc->voxel_m) || !finite3(desc->origin_m))
-        return fail(RMPC_E_INVALID, "voxel size or origin invalid");
+    rmpc::MapView v;
+    uint64_t n_all;
+    if (rmpc_status st = dense_layout(*desc, v, n_all)) return st;
     DeviceGuard dg(ctx->device);
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    rmpc::MapView v;
-    std::memset(&v, 0, sizeof v);
-    v.nx = desc->nx; v.ny = desc->ny; v.nz = desc->nz; v.dtype = desc->dtype;
     const uint64_t n_log = (uint64_t)desc->nx * desc->ny * desc->nz;
-    v.ncx = desc->nx >> rmpc::kCellLog2;
-    v.ncy = desc->ny >> rmpc::kCellLog2;
-    v.ncz = desc->nz >> rmpc::kCellLog2;
-    v.nbx = desc->nx >> rmpc::kBrickLog2;
-    v.nby = desc->ny >> rmpc::kBrickLog2;
-    v.nbz = desc->nz >> rmpc::kBrickLog2;
-    const uint64_t cell_base = (n_log + 255) / 256 * 256;
-    const uint64_t brick_base = (cell_base + (uint64_t)v.ncx * v.ncy * v.ncz + 255) / 256 * 256;
-    const uint64_t n_all = brick_base + (uint64_t)v.nbx * v.nby * v.nbz;
-    if (n_all >= (1ull << 32)) return fail(RMPC_E_INVALID, "grid too large for 32-bit voxel offsets");
-    v.cell_base = (uint32_t)cell_base;
-    v.brick_base = (uint32_t)brick_base;
     const size_t eb = elem_bytes(desc->dtype);
     size_t off;
     if (!ctx->alloc.alloc(n_all * eb, &off)) return fail(RMPC_E_NOMEM, "arena full (map)");
@@ -418,6 +458,7 @@ rmpc_status rmpc_map_upload(rmpc_ctx *ctx, const rmpc_map_desc *desc, const void
     if (e == hipSuccess) e = rmpc::launch_map_summaries(rmpc::SummaryArgs{v}, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
+        (void)hipStreamSynchronize(s);
         ctx->alloc.release(off);
         return fail(RMPC_E_HIP, std::string("map upload: ") + hipGetErrorString(e));
     }
@@ -488,21 +529,10 @@ rmpc_status rmpc_scan_query(rmpc_ctx *ctx, const float *points_dev, int32_t n_po
                             rmpc_result *out)
 {
     if (!ctx || !out) return fail(RMPC_E_INVALID, "NULL argument");
-    if (n_points < 0 || n_points > (1 << 24)) return fail(RMPC_E_INVALID, "n_points out of [0, 2^24]");
-    if (n_points > 0 && !points_dev) return fail(RMPC_E_INVALID, "points_dev is NULL");
-    if (!finite3(v)) return fail(RMPC_E_INVALID, "velocity is NULL or not finite");
-    if (rmpc_status st = check_params(params)) return st;
+    rmpc::ScanArgs A;
+    if (rmpc_status st = setup_scan(points_dev, n_points, v, params, A)) return st;
     DeviceGuard dg(ctx->device);
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    rmpc::ScanArgs A;
-    std::memset(&A, 0, sizeof A);
-    A.points = points_dev;
-    A.n_points = n_points;
-    A.min_range2 = params->min_range_m * params->min_range_m;
-    for (int a = 0; a < 3; ++a) A.vel64[a] = v[a];
-    A.radius64 = params->radius;
-    A.pol = policy_f(params, v);
-    A.rank_tol = params->rank_tol;
     A.partials = ctx->partials;
     A.ticket = ctx->ticket;
     A.result = ctx->result_host;

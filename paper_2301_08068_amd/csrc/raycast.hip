@@ -926,7 +926,6 @@ __device__ __forceinline__ FinishSlots single_slots(float *partials, uint32_t *t
 
 // One map query per launch; block b takes tile xcd_tile(b).
 template <int DT, int K>
-// 4 waves per SIMD keep every block of a 2^18-lane query resident at once
 // One 65,536-ray query at the default lane target has 2 waves per SIMD, so the kernel is built
 // for 2: the register budget then fits lookahead 16 without spills (lookahead 4 and 8 still
 // stay within 128 registers, 4 waves per SIMD).
@@ -1092,7 +1091,7 @@ int ray_grid_blocks(int lanes)
 int scan_grid_blocks(int n_points)
 {
     int b = (n_points + kBlock - 1) / kBlock;
-    return b < 1 ? 1 : (b > 128 ? 128 : b);
+    return b < 1 ? 1 : (b > kScanMaxBlocks ? kScanMaxBlocks : b);
 }
 
 hipError_t launch_scan(const ScanArgs &A, hipStream_t s, hipEvent_t e0, hipEvent_t e1)

@@ -320,7 +320,7 @@ struct FinishSlots {
     rmpc_result *out;
     uint32_t *finished;          // null for a single query
     int32_t n_queries;
-    uint64_t *done;
+    uint64_t *done;              // null: nothing is published
     uint64_t seq;
 };
 
@@ -374,8 +374,9 @@ __device__ inline void grid_finish(const Acc &a, int b, int nb, const FinishSlot
             publish = prev == (uint32_t)(F.n_queries - 1);
             if (publish) __hip_atomic_store(F.finished, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        // publish: the results are visible to the host before the sequence number
-        if (publish) __hip_atomic_store(F.done, F.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        // publish: the results are visible to the host before the sequence number (no word to
+        // publish to: the result stays in device memory, ordered by the stream)
+        if (publish && F.done) __hip_atomic_store(F.done, F.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 

@@ -112,6 +112,11 @@ bool grid_coords(const rmpc_map_desc &d, const double x[3], float g[3]);
 // Validate a map query and fill the geometry and policy-independent part of RayArgs.
 rmpc_status setup_query(rmpc_ctx *ctx, int32_t map_id, const double x[3], int32_t n_rays,
                         const rmpc_params *params, const rmpc_launch_config &cfg, rmpc::RayArgs &A);
+// Largest scan query (points).
+constexpr int32_t kMaxScanPoints = 1 << 24;
+// Validate a scan query and fill ScanArgs except partials, ticket, result, done and seq.
+rmpc_status setup_scan(const float *points_dev, int32_t n_points, const double v[3], const rmpc_params *params,
+                       rmpc::ScanArgs &A);
 // Spin until *done == seq (the kernel's publication), checking the stream for errors.
 rmpc_status wait_done(const uint64_t *done, hipStream_t s, uint64_t seq);
 

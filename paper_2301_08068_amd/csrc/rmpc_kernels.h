@@ -21,6 +21,10 @@ constexpr int kMaxPartialSlots = 4096;
 // Words of one block partial in device memory: 18 floats + 4 integers, padded.
 constexpr int kPartialWords = 32;
 
+// Blocks of one scan query (each block's ticket costs a release/acquire, so the points are
+// looped over instead of adding blocks).
+constexpr int kScanMaxBlocks = 128;
+
 // A resident map: the voxel grid x-fastest (element offset x + nx (y + ny z)), then, at
 // element offset cell_base, one summary element per cell of 8 x 8 x 8 voxels, also x-fastest:
 // "occupied" when any voxel of the cell is, "free" when none is.  Only whole cells inside the
@@ -94,8 +98,8 @@ struct ScanArgs {
     double rank_tol;
     float *partials;
     uint32_t *ticket;
-    rmpc_result *result;
-    uint64_t *done;
+    rmpc_result *result;         // host (pinned) or device memory
+    uint64_t *done;              // host-visible completion word, or null (result left on the stream)
     uint64_t seq;
 };
 

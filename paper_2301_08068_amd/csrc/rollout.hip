@@ -1,5 +1,5 @@
-// rollout.hip -- closed-loop rollout (Sec. III-A Eq. 1 with the goal attractor of Sec. III-B
-// Eqs. 2-3): every state's ray policy comes from a query launch; the attractor, the 3x3 solve
+// rollout.hip -- closed-loop rollout (Sec. III-A Eq. 1 with the goal attractor of Sec. III-C
+// Eqs. 3-4): every state's ray policy comes from a query launch; the attractor, the 3x3 solve
 // and the integration are a few float64 operations on the host around it.  A single flight
 // runs one rmpc_query per step; a batch of flights runs one rmpc_query_batch per step over the
 // flights still flying.  Both drive the same per-flight state machine, so their outcomes agree
@@ -19,7 +19,7 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 
-// Eq. 3: s(u) = u / (|u| + c log(1 + exp(-2 c |u|))).
+// Eq. 4: s(u) = u / (|u| + c log(1 + exp(-2 c |u|))).
 void soft_normalize(const double u[3], double c, double out[3])
 {
     const double m = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
@@ -129,7 +129,7 @@ struct Flight {
             end(RMPC_ROLLOUT_COLLISION);
             return RMPC_OK;
         }
-        // f_a = alpha s(goal - x) - beta v (Eq. 2), metric I; a = (I + w A)^-1 (f_a + w b) (Eq. 1)
+        // f_a = alpha s(goal - x) - beta v (Eq. 3), metric I; a = (I + w A)^-1 (f_a + w b) (Eq. 1)
         double u[3], s[3], r[3], a[3], wA[9];
         for (int i = 0; i < 3; ++i) u[i] = rp.goal[i] - x[i];
         soft_normalize(u, c, s);

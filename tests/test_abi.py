@@ -54,3 +54,25 @@ def test_library_has_no_oracle_dependency(lib_path):
         if f.endswith(".py"):
             src = open(os.path.join(ROOT, "paper_2301_08068_amd", f)).read()
             assert "import oracle" not in src and "from oracle" not in src, f
+
+
+def test_map_footprint_and_size_limits(lib_path):
+    """rmpc_map_footprint makes no GPU call: the dense layout is the grid, then one summary
+    element per whole 8^3 cell and per whole 2^3 brick, each section starting on a multiple of
+    256 elements; grids of 2^31 voxels or more are refused (int32 linear indices)."""
+    from paper_2301_08068_amd import binding
+    fp = binding.rmpc_map_footprint
+    n = 400 ** 3
+    cell_base = -(-n // 256) * 256
+    brick_base = -(-(cell_base + 50 ** 3) // 256) * 256
+    assert fp(400, 400, 400, "f32", 0.05, (0, 0, 0)) == 4 * (brick_base + 200 ** 3)
+    assert fp(400, 400, 400, "u8", 0.05, (0, 0, 0)) == brick_base + 200 ** 3
+    # ragged grid: partial cells and bricks have no summary
+    assert fp(13, 7, 9, "f16", 0.1, (0, 0, 0)) == 2 * (1024 + 6 * 3 * 4)     # 819 voxels, no whole cell
+    assert fp(1290, 1290, 1290, "u8", 0.01, (0, 0, 0)) > 0             # 2.147e9 - 1.2e6 voxels
+    with pytest.raises(binding.RmpcError, match="2\\^31"):
+        fp(1291, 1291, 1291, "u8", 0.01, (0, 0, 0))                     # 2.1518e9 voxels
+    with pytest.raises(binding.RmpcError, match="dimensions"):
+        fp(4097, 1, 1, "u8", 0.01, (0, 0, 0))
+    with pytest.raises(binding.RmpcError, match="voxel size"):
+        fp(8, 8, 8, "f32", float("nan"), (0, 0, 0))

@@ -1,5 +1,5 @@
 """Pins of the oracle's closed-loop rollout (ray policy + goal attractor, Sec. III-A Eq. 1 and
-Sec. III-B Eqs. 2-3, integrated step by step): closed forms of the integrator and the attractor,
+Sec. III-C Eqs. 3-4, integrated step by step): closed forms of the integrator and the attractor,
 geometric invariants of the path measure, and collision detection."""
 import numpy as np
 import pytest
