@@ -188,6 +188,26 @@ rmpc_status rmpc_scan_query(rmpc_ctx *ctx, const float *points_dev, int32_t n_po
                             rmpc_result *out);
 
 /*
+ * rmpc_scan_query_noalloc -- rmpc_scan_query for callers that cannot allocate memory (code
+ * under HIP graph capture, tight serving or control loops, harnesses that forbid allocation):
+ * needs no context and allocates nothing.  Its reduction scratch (block partials of at most
+ * 128 blocks and an arrival ticket, 16,640 bytes) is a fixed device array of the library that
+ * each GPU holds until the process ends; the call clears what must start at zero.
+ *   device: the GPU that holds points_dev and out_dev.
+ *   points_dev, n_points, v, params: as for rmpc_scan_query (0 <= n_points <= 2^24).
+ *   out_dev: device memory receiving the result, written in stream order: it is complete once
+ *     hip_stream reaches the end of this call's work.  The call returns after enqueueing (it
+ *     does not wait).
+ * The result equals rmpc_scan_query's bit for bit.  Calls that overlap on one GPU (other
+ * streams, or other host threads, without ordering between them) share the scratch and race:
+ * order them on one stream.
+ * Errors: RMPC_E_INVALID (NULL, size out of range, bad parameter), RMPC_E_HIP.
+ */
+rmpc_status rmpc_scan_query_noalloc(int device, const float *points_dev, int32_t n_points,
+                                    const double v[3], const rmpc_params *params, void *hip_stream,
+                                    rmpc_result *out_dev);
+
+/*
  * rmpc_trace_debug -- per-ray traversal results of a query, for parity tests.
  *   hit_lin_dev[n_rays]: logical index of the hit voxel, -1 on a miss.
  *   dist_dev[n_rays]: distance in metres to where the ray enters it (float64), +inf on a miss.

@@ -79,6 +79,8 @@ class Result(C.Structure):
                 ("n_rays", C.c_int32), ("visits", C.c_int64)]
 
 
+RESULT_BYTES = C.sizeof(Result)
+
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run paper_2301_08068_amd/build.py")
 # The library finds the HIP runtime by soname (libamdhip64.so.7), which torch also ships: torch
@@ -116,6 +118,8 @@ _SIGS = {
                    C.c_void_p, _P(Result)],
     "rmpc_scan_query": [C.c_void_p, C.c_void_p, C.c_int32, _P(C.c_double), _P(Params), C.c_void_p,
                         _P(Result)],
+    "rmpc_scan_query_noalloc": [C.c_int, C.c_void_p, C.c_int32, _P(C.c_double), _P(Params), C.c_void_p,
+                                C.c_void_p],
     "rmpc_trace_debug": [C.c_void_p, C.c_int32, _P(C.c_double), C.c_int32, _P(Params), C.c_void_p,
                          C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
     "rmpc_directions": [C.c_void_p, C.c_int32, _P(C.c_float)],
@@ -305,6 +309,20 @@ def rmpc_scan_query(ctx: int, points_ptr: int, n_points: int, v, params: Dict[st
                                 C.byref(ps), C.c_void_p(_stream_ptr(stream)), C.byref(r)),
            "rmpc_scan_query")
     return result_dict(r)
+
+
+def rmpc_scan_query_noalloc(device: int, points_ptr: int, n_points: int, v, params: Dict[str, float],
+                            out_ptr: int, stream=None) -> None:
+    """Enqueue the context-free scan query; the result lands in the device buffer at out_ptr
+    (RESULT_BYTES bytes) in stream order."""
+    _check(_lib.rmpc_scan_query_noalloc(int(device), C.c_void_p(points_ptr), int(n_points), _d3(v),
+                                        C.byref(params_struct(params)), C.c_void_p(_stream_ptr(stream)),
+                                        C.c_void_p(out_ptr)), "rmpc_scan_query_noalloc")
+
+
+def result_from_bytes(buf: bytes) -> Dict:
+    """A result dict from the RESULT_BYTES bytes of an rmpc_result copied from the device."""
+    return result_dict(Result.from_buffer_copy(buf))
 
 
 def rmpc_trace_debug(ctx: int, map_id: int, x, n_rays: int, params: Dict[str, float], hit_ptr: int,
