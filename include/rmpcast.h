@@ -150,6 +150,42 @@ rmpc_status rmpc_map_upload(rmpc_ctx *ctx, const rmpc_map_desc *desc, const void
 /* rmpc_map_release -- free a map's arena space.  Errors: RMPC_E_NOMAP. */
 rmpc_status rmpc_map_release(rmpc_ctx *ctx, int32_t map_id);
 
+/* A sparse map: 8 x 8 x 8-voxel blocks stored only where the world has content (every voxel
+ * outside a stored block is free, and the world has no edge), as in the GPU-resident block
+ * hash map the paper's system raycasts (Sec. III-E, III-F).  Block (bx, by, bz) covers voxels
+ * [8 bx, 8 bx + 8) x [8 by, 8 by + 8) x [8 bz, 8 bz + 8); voxel (i, j, k) has its centre at
+ * origin_m + (idx + 1/2) voxel_m, for negative indices too. */
+typedef struct {
+    int32_t n_blocks;           /* stored blocks, 1 .. 2^22 */
+    int32_t dtype;              /* rmpc_dtype of the voxel values */
+    double voxel_m;
+    double origin_m[3];         /* world position of the minimum corner of voxel (0, 0, 0) */
+} rmpc_sparse_desc;
+
+/*
+ * rmpc_sparse_map_upload -- make a sparse map resident on the GPU.
+ *   block_coords_host[3 n_blocks]: host int32 (bx, by, bz) of each stored block, each in
+ *     [-2^20, 2^20), no block twice.  Block k gets slot k.
+ *   values[512 n_blocks]: the voxel values of the dtype, block after block; within block k,
+ *     voxel (i, j, l) (0..7 each) at k * 512 + i + 8 j + 64 l.  Host memory when
+ *     values_on_device == 0, device memory otherwise.  Only read during the call.
+ *   map_id_out: receives the map's id (the same id space as dense maps).
+ * The library keeps the values, a 512-bit occupancy mask per block and an open-addressed hash
+ * table (a power of two of at least 2 n_blocks entries of 16 bytes, at least 1024) from block
+ * coordinates to slots: 16 capacity + 64 n_blocks + 512 elem_bytes n_blocks arena bytes.
+ * rmpc_query and rmpc_trace_debug accept sparse maps (one lane per ray; params->subvoxel must
+ * be 0; the start may lie anywhere whose voxels within max_range keep |index| < 2^23;
+ * RMPC_E_OUT_OF_BOUNDS otherwise); rmpc_trace_debug then reports a hit as
+ * slot * 512 + (i + 8 j + 64 l) of the hit voxel in its block.  rmpc_rollout flies on sparse
+ * maps.  Batched queries, the serving loop, batched rollouts and the distance transform take
+ * dense maps only (RMPC_E_INVALID).  Blocking.
+ * Errors: RMPC_E_INVALID (NULL, n_blocks, dtype, voxel size, coordinates, a repeated block),
+ * RMPC_E_NOMEM (arena full), RMPC_E_HIP.
+ */
+rmpc_status rmpc_sparse_map_upload(rmpc_ctx *ctx, const rmpc_sparse_desc *desc, const int32_t *block_coords_host,
+                                   const void *values, int values_on_device, void *hip_stream,
+                                   int32_t *map_id_out);
+
 /*
  * rmpc_map_footprint -- arena bytes that rmpc_map_upload of this grid takes (the grid plus its
  * cell and brick summaries, before the arena's 256-byte rounding), for sizing an arena.  Makes

@@ -37,6 +37,11 @@ class MapDesc(C.Structure):
                 ("voxel_m", C.c_double), ("origin_m", C.c_double * 3)]
 
 
+class SparseDesc(C.Structure):
+    _fields_ = [("n_blocks", C.c_int32), ("dtype", C.c_int32), ("voxel_m", C.c_double),
+                ("origin_m", C.c_double * 3)]
+
+
 class Params(C.Structure):
     _fields_ = [(k, C.c_double) for k in ("c", "eta_rep", "nu_rep", "eta_damp", "nu_damp", "radius",
                                           "eps", "max_range_m", "rank_tol", "min_range_m")] + \
@@ -113,6 +118,8 @@ _SIGS = {
     "rmpc_destroy": [C.c_void_p],
     "rmpc_map_upload": [C.c_void_p, _P(MapDesc), C.c_void_p, C.c_int, C.c_void_p, _P(C.c_int32)],
     "rmpc_map_release": [C.c_void_p, C.c_int32],
+    "rmpc_sparse_map_upload": [C.c_void_p, _P(SparseDesc), C.c_void_p, C.c_void_p, C.c_int, C.c_void_p,
+                               _P(C.c_int32)],
     "rmpc_map_footprint": [_P(MapDesc), _P(C.c_size_t)],
     "rmpc_query": [C.c_void_p, C.c_int32, _P(C.c_double), _P(C.c_double), C.c_int32, _P(Params),
                    C.c_void_p, _P(Result)],
@@ -213,6 +220,20 @@ def rmpc_map_upload(ctx: int, nx: int, ny: int, nz: int, dtype: str, voxel_m: fl
     _check(_lib.rmpc_map_upload(C.c_void_p(ctx), C.byref(desc), C.c_void_p(voxels_ptr),
                                 int(bool(on_device)), C.c_void_p(_stream_ptr(stream)), C.byref(mid)),
            "rmpc_map_upload")
+    return mid.value
+
+
+def rmpc_sparse_map_upload(ctx: int, coords: np.ndarray, values_ptr: int, n_blocks: int, dtype: str,
+                           voxel_m: float, origin_m, on_device: bool, stream=None) -> int:
+    """coords: int32 [n_blocks, 3] block coordinates (host); values_ptr: n_blocks * 512
+    elements of the dtype, block after block, x fastest within a block."""
+    c = np.ascontiguousarray(coords, dtype=np.int32).reshape(-1, 3)
+    assert c.shape[0] == n_blocks
+    d = SparseDesc(int(n_blocks), DTYPES[dtype], float(voxel_m), _d3(origin_m))
+    mid = C.c_int32(-1)
+    _check(_lib.rmpc_sparse_map_upload(C.c_void_p(ctx), C.byref(d), c.ctypes.data_as(C.c_void_p),
+                                       C.c_void_p(values_ptr), int(bool(on_device)),
+                                       C.c_void_p(_stream_ptr(stream)), C.byref(mid)), "rmpc_sparse_map_upload")
     return mid.value
 
 
@@ -496,6 +517,19 @@ class Context:
             del t
         else:
             mid = rmpc_map_upload(self.ptr, nx, ny, nz, dtype, voxel_m, origin_m, arr.ctypes.data, False)
+        return mid
+
+    def upload_sparse(self, coords: np.ndarray, values: np.ndarray, voxel_m: float, origin_m,
+                      dtype: str = "f32") -> int:
+        """Upload a sparse block map: coords int32 [n, 3], values [n, 8, 8, 8] indexed
+        (block, z, y, x) (float32 TSDF, uint16 binary16 bits or uint8)."""
+        import torch
+        want = {"f32": np.float32, "f16": np.uint16, "u8": np.uint8}[dtype]
+        arr = np.ascontiguousarray(values, dtype=want).reshape(-1, 8, 8, 8)
+        t = torch.from_numpy(arr.view(np.uint8).reshape(-1)).to(f"cuda:{self.device}")
+        mid = rmpc_sparse_map_upload(self.ptr, coords, t.data_ptr(), arr.shape[0], dtype, voxel_m, origin_m,
+                                     True, stream=self.stream)
+        del t
         return mid
 
     def release(self, map_id: int) -> None:

@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "librmpcast.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["capi.hip", "batch.hip", "server.hip", "rollout.hip", "raycast.hip", "setup_kernels.hip", "edt.hip", "noalloc.hip"]
+SOURCES = ["capi.hip", "batch.hip", "server.hip", "rollout.hip", "raycast.hip", "setup_kernels.hip", "edt.hip", "sparse.hip", "noalloc.hip"]
 ARCH = os.environ.get("RMPC_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -22,6 +22,7 @@ namespace rmpc_host {
 
 constexpr size_t kMinArena = 16u << 20;
 constexpr int kMaxDim = 4096;
+constexpr int32_t kMaxSparseBlocks = 1 << 22;   // slot * 512 + voxel fits int32
 
 thread_local std::string g_last_error;
 
@@ -162,6 +163,49 @@ bool grid_coords(const rmpc_map_desc &d, const double x[3], float g[3])
     return true;
 }
 
+// A map query on a sparse map: the world has no edge, so the start only has to keep every
+// voxel a ray can reach within the block coordinate range; one lane per ray.
+rmpc_status setup_sparse_query(rmpc_ctx *ctx, const MapEntry &me, const double x[3], int32_t n_rays,
+                               const rmpc_params *params, const rmpc_launch_config &cfg, rmpc::RayArgs &A)
+{
+    std::memset(&A, 0, sizeof A);
+    if (params->subvoxel) return fail(RMPC_E_INVALID, "subvoxel distances are not available on sparse maps");
+    const double tmax = params->max_range_m / me.desc.voxel_m;
+    // every voxel within tmax of the start keeps |coordinate| < 2^23 (block coordinates in 21 bits)
+    const double reach = (double)(1 << 23) - 16.0;
+    if (!(tmax < reach)) return fail(RMPC_E_INVALID, "max_range_m spans too many voxels for a sparse map");
+    uint32_t start_flags = 0;
+    for (int a = 0; a < 3; ++a) {
+        const float g = (float)((x[a] - me.desc.origin_m[a]) / me.desc.voxel_m);
+        if (!(std::fabs((double)g) + tmax < reach))
+            return fail(RMPC_E_OUT_OF_BOUNDS, "position too far from the sparse map's origin");
+        A.g[a] = g;
+        A.v0[a] = (int32_t)std::floor(g);
+        const double fr = (double)g - std::floor((double)g);
+        if (fr < 1e-5 || 1.0 - fr < 1e-5) start_flags |= RMPC_RAY_START_FACE;
+    }
+    ray_list(ctx, n_rays, &A.rays, &A.n_list);
+    A.sparse = 1;
+    A.sp = me.sview;
+    A.n_rays = n_rays;
+    A.start_flags = start_flags;
+    A.tmax_lo = (float)(tmax * (1.0 - 1e-6) - 2e-5);
+    A.tmax_hi = (float)(tmax * (1.0 + 1e-6) + 2e-5);
+    A.tmax_v = tmax;
+    A.segments = 1;
+    A.lookahead = cfg.lookahead;
+    A.max_range = params->max_range_m;
+    A.h = me.desc.voxel_m;
+    A.radius64 = params->radius;
+    A.rank_tol = params->rank_tol;
+    A.partials = ctx->partials;
+    A.ticket = ctx->ticket;
+    A.result = ctx->result_host;
+    A.done = ctx->done_host;
+    A.seq = 0;
+    return RMPC_OK;
+}
+
 // Validates the query state and fills the geometry part of RayArgs.
 rmpc_status setup_query(rmpc_ctx *ctx, int32_t map_id, const double x[3], int32_t n_rays,
                         const rmpc_params *params, const rmpc_launch_config &cfg, rmpc::RayArgs &A)
@@ -173,6 +217,7 @@ rmpc_status setup_query(rmpc_ctx *ctx, int32_t map_id, const double x[3], int32_
     auto it = ctx->maps.find(map_id);
     if (it == ctx->maps.end()) return fail(RMPC_E_NOMAP, "unknown map id");
     const MapEntry &me = it->second;
+    if (me.sparse) return setup_sparse_query(ctx, me, x, n_rays, params, cfg, A);
     const int32_t n[3] = {me.desc.nx, me.desc.ny, me.desc.nz};
     std::memset(&A, 0, sizeof A);
     uint32_t start_flags = 0;
@@ -463,7 +508,94 @@ rmpc_status rmpc_map_upload(rmpc_ctx *ctx, const rmpc_map_desc *desc, const void
         return fail(RMPC_E_HIP, std::string("map upload: ") + hipGetErrorString(e));
     }
     const int32_t id = ctx->next_map_id++;
-    ctx->maps[id] = MapEntry{*desc, v, off};
+    MapEntry me;
+    me.desc = *desc;
+    me.view = v;
+    me.off = off;
+    ctx->maps[id] = me;
+    *map_id_out = id;
+    return RMPC_OK;
+}
+
+rmpc_status rmpc_sparse_map_upload(rmpc_ctx *ctx, const rmpc_sparse_desc *desc, const int32_t *block_coords_host,
+                                   const void *values, int values_on_device, void *hip_stream, int32_t *map_id_out)
+{
+    if (!ctx || !desc || !block_coords_host || !values || !map_id_out) return fail(RMPC_E_INVALID, "NULL argument");
+    if (ctx->server) return fail(RMPC_E_INVALID, "maps cannot change while the server runs");
+    const int32_t n = desc->n_blocks;
+    if (n < 1 || n > kMaxSparseBlocks) return fail(RMPC_E_INVALID, "n_blocks out of [1, 2^22]");
+    if (desc->dtype != RMPC_TSDF_F32 && desc->dtype != RMPC_TSDF_F16 && desc->dtype != RMPC_OCC_U8)
+        return fail(RMPC_E_INVALID, "unknown dtype");
+    if (!(desc->voxel_m > 0) || !std::isfinite(desc->voxel_m) || !finite3(desc->origin_m))
+        return fail(RMPC_E_INVALID, "voxel size or origin invalid");
+    // the table: a power of two of at least twice the blocks, filled on the host by linear probing
+    uint32_t cap = 1024;
+    while (cap < 2u * (uint32_t)n) cap *= 2u;
+    std::vector<rmpc::HashEntry> table(cap, rmpc::HashEntry{rmpc::kEmptyKey, -1, 0u});
+    const uint32_t mask = cap - 1u;
+    for (int32_t k = 0; k < n; ++k) {
+        const int32_t *c = block_coords_host + 3 * (size_t)k;
+        for (int a = 0; a < 3; ++a)
+            if (c[a] < -rmpc::kBlockCoordBias || c[a] >= rmpc::kBlockCoordBias)
+                return fail(RMPC_E_INVALID, "block " + std::to_string(k) + ": coordinate out of [-2^20, 2^20)");
+        const uint64_t key = rmpc::block_key(c[0], c[1], c[2]);
+        uint32_t i = rmpc::block_hash(key, mask);
+        while (table[i].key != rmpc::kEmptyKey) {
+            if (table[i].key == key) return fail(RMPC_E_INVALID, "block " + std::to_string(k) + ": listed twice");
+            i = (i + 1u) & mask;
+        }
+        table[i] = rmpc::HashEntry{key, k, 0u};
+    }
+    const size_t eb = elem_bytes(desc->dtype);
+    size_t o_table, o_occ, o_vals;
+    if (!ctx->alloc.alloc(sizeof(rmpc::HashEntry) * (size_t)cap, &o_table))
+        return fail(RMPC_E_NOMEM, "arena full (sparse map table)");
+    if (!ctx->alloc.alloc(sizeof(uint64_t) * 8 * (size_t)n, &o_occ)) {
+        ctx->alloc.release(o_table);
+        return fail(RMPC_E_NOMEM, "arena full (sparse map occupancy)");
+    }
+    if (!ctx->alloc.alloc(eb * rmpc::kBlockVoxels * (size_t)n, &o_vals)) {
+        ctx->alloc.release(o_table);
+        ctx->alloc.release(o_occ);
+        return fail(RMPC_E_NOMEM, "arena full (sparse map values)");
+    }
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    rmpc::HashEntry *table_dev = reinterpret_cast<rmpc::HashEntry *>(ctx->arena + o_table);
+    rmpc::SparseView v;
+    std::memset(&v, 0, sizeof v);
+    v.table = table_dev;
+    v.table_mask = mask;
+    v.n_slots = n;
+    v.occ = reinterpret_cast<const uint64_t *>(ctx->arena + o_occ);
+    v.values = ctx->arena + o_vals;
+    v.dtype = desc->dtype;
+    hipError_t e = hipMemcpyAsync(table_dev, table.data(), sizeof(rmpc::HashEntry) * (size_t)cap,
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ctx->arena + o_vals, values, eb * rmpc::kBlockVoxels * (size_t)n,
+                           values_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = rmpc::launch_sparse_masks(v, table_dev, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        (void)hipStreamSynchronize(s);
+        ctx->alloc.release(o_table);
+        ctx->alloc.release(o_occ);
+        ctx->alloc.release(o_vals);
+        return fail(RMPC_E_HIP, std::string("sparse map upload: ") + hipGetErrorString(e));
+    }
+    MapEntry me;
+    std::memset(&me.desc, 0, sizeof me.desc);
+    me.desc.dtype = desc->dtype;
+    me.desc.voxel_m = desc->voxel_m;
+    for (int a = 0; a < 3; ++a) me.desc.origin_m[a] = desc->origin_m[a];
+    std::memset(&me.view, 0, sizeof me.view);
+    me.off = o_table;
+    me.sparse = true;
+    me.sview = v;
+    me.more = {o_occ, o_vals};
+    const int32_t id = ctx->next_map_id++;
+    ctx->maps[id] = me;
     *map_id_out = id;
     return RMPC_OK;
 }
@@ -477,6 +609,7 @@ rmpc_status rmpc_map_release(rmpc_ctx *ctx, int32_t map_id)
     DeviceGuard dg(ctx->device);
     RMPC_HIP(hipDeviceSynchronize());
     ctx->alloc.release(it->second.off);
+    for (size_t o : it->second.more) ctx->alloc.release(o);
     ctx->maps.erase(it);
     return RMPC_OK;
 }
@@ -496,7 +629,8 @@ rmpc_status rmpc_query(rmpc_ctx *ctx, int32_t map_id, const double x[3], const d
     A.seq = ++ctx->seq;
     A.pol = policy_f(params, v);
     for (int a = 0; a < 3; ++a) A.vel64[a] = v[a];
-    RMPC_HIP(rmpc::launch_raycast(A, s, false, ctx->profiling ? ctx->ev0 : nullptr, ctx->ev1));
+    if (A.sparse) RMPC_HIP(rmpc::launch_sparse(A, s, false, ctx->profiling ? ctx->ev0 : nullptr, ctx->ev1));
+    else RMPC_HIP(rmpc::launch_raycast(A, s, false, ctx->profiling ? ctx->ev0 : nullptr, ctx->ev1));
     if (rmpc_status st = wait_done(ctx->done_host, s, A.seq)) return st;
     std::memcpy(out, ctx->result_host, sizeof(rmpc_result));
     if (ctx->profiling) RMPC_HIP(hipEventSynchronize(ctx->ev1));
@@ -519,7 +653,8 @@ rmpc_status rmpc_trace_debug(rmpc_ctx *ctx, int32_t map_id, const double x[3], i
     A.dbg_dist = dist_dev;
     A.dbg_flags = flags_dev;
     A.dbg_visits = visits_dev;
-    RMPC_HIP(rmpc::launch_raycast(A, s, true));
+    if (A.sparse) RMPC_HIP(rmpc::launch_sparse(A, s, true));
+    else RMPC_HIP(rmpc::launch_raycast(A, s, true));
     RMPC_HIP(hipStreamSynchronize(s));
     return RMPC_OK;
 }
@@ -590,6 +725,7 @@ rmpc_status rmpc_edt(rmpc_ctx *ctx, int32_t map_id, int32_t *sqdist_dev, void *h
     if (!ctx || !sqdist_dev) return fail(RMPC_E_INVALID, "NULL argument");
     auto it = ctx->maps.find(map_id);
     if (it == ctx->maps.end()) return fail(RMPC_E_NOMAP, "unknown map id");
+    if (it->second.sparse) return fail(RMPC_E_INVALID, "the distance transform needs a dense map");
     DeviceGuard dg(ctx->device);
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     RMPC_HIP(rmpc::launch_edt(it->second.view, sqdist_dev, s));
@@ -605,6 +741,7 @@ rmpc_status rmpc_esdf_query(rmpc_ctx *ctx, int32_t map_id, const int32_t *sqdist
     if (rmpc_status st = check_params(params)) return st;
     auto it = ctx->maps.find(map_id);
     if (it == ctx->maps.end()) return fail(RMPC_E_NOMAP, "unknown map id");
+    if (it->second.sparse) return fail(RMPC_E_INVALID, "the ESDF policy needs a dense map");
     const rmpc_map_desc &d = it->second.desc;
     float g[3];
     if (!grid_coords(d, x, g)) return fail(RMPC_E_OUT_OF_BOUNDS, "position outside the grid");

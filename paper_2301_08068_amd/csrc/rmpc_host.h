@@ -30,9 +30,12 @@ using rmpc_sched::Arena;
 using rmpc_sched::kAlign;
 
 struct MapEntry {
-    rmpc_map_desc desc;
-    rmpc::MapView view;
-    size_t off;
+    rmpc_map_desc desc;          // sparse maps: nx = ny = nz = 0
+    rmpc::MapView view;          // dense maps
+    size_t off;                  // first arena allocation (dense: the grid; sparse: the table)
+    bool sparse = false;
+    rmpc::SparseView sview;      // sparse maps
+    std::vector<size_t> more;    // further arena allocations of a sparse map
 };
 
 // Everything one launch of the persistent batch kernel needs, on its own stream: device

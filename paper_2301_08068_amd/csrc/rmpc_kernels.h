@@ -42,6 +42,52 @@ struct MapView {
 constexpr int kCellLog2 = 3;
 constexpr int kBrickLog2 = 1;
 
+// A sparse map: 8 x 8 x 8-voxel blocks stored where the world has content (every other voxel
+// is free), found through an open-addressed hash table from block coordinates to slots.
+constexpr int kBlockLog2 = 3;
+constexpr int kBlockVoxels = 512;
+// Block coordinates are signed 21-bit integers (|voxel coordinate| < 2^23 voxels).
+constexpr int kBlockCoordBits = 21;
+constexpr int32_t kBlockCoordBias = 1 << (kBlockCoordBits - 1);
+constexpr uint64_t kEmptyKey = ~0ull;
+
+// One table entry (16 bytes, one load): the packed block coordinates, the block's slot and
+// whether any of its voxels is occupied.
+struct alignas(16) HashEntry {
+    uint64_t key;
+    int32_t slot;
+    uint32_t occupied;
+};
+
+// Key of block (bx, by, bz): the three biased 21-bit coordinates, x lowest.  Valid keys have
+// bit 63 clear, so they never equal kEmptyKey.
+__host__ __device__ inline uint64_t block_key(int32_t bx, int32_t by, int32_t bz)
+{
+    return (uint64_t)(uint32_t)(bx + kBlockCoordBias) | ((uint64_t)(uint32_t)(by + kBlockCoordBias) << 21) |
+           ((uint64_t)(uint32_t)(bz + kBlockCoordBias) << 42);
+}
+
+// First table index of a key: the 64-bit finaliser of MurmurHash3 (fmix64), masked.
+__host__ __device__ inline uint32_t block_hash(uint64_t k, uint32_t mask)
+{
+    k ^= k >> 33;
+    k *= 0xff51afd7ed558ccdull;
+    k ^= k >> 33;
+    k *= 0xc4ceb9fe1a85ec53ull;
+    k ^= k >> 33;
+    return (uint32_t)k & mask;
+}
+
+struct SparseView {
+    const HashEntry *table;      // table_mask + 1 entries (a power of two, at least twice the blocks)
+    uint32_t table_mask;
+    int32_t n_slots;
+    const uint64_t *occ;         // per slot 8 words: word z holds bit x + 8 y of the block's layer z
+    const void *values;          // per slot 512 elements, x fastest within the block
+    int32_t dtype;
+    int32_t pad;
+};
+
 // Policy constants in float32 (reciprocals precomputed on the host).
 struct PolicyF {
     float vx, vy, vz;            // robot velocity
@@ -57,7 +103,9 @@ struct alignas(16) RayRec {
 
 // Everything one map query needs.
 struct RayArgs {
-    MapView map;
+    MapView map;                 // dense maps
+    SparseView sp;               // sparse maps (then segments is 1)
+    int32_t sparse;
     const RayRec *rays;          // ordered ray list; entries with i >= n_rays are skipped
     int32_t n_list;              // length of `rays` (>= n_rays)
     int32_t n_rays;
@@ -189,6 +237,11 @@ struct EsdfArgs {
     rmpc_result *out;            // device memory
 };
 hipError_t launch_esdf(const EsdfArgs &a, hipStream_t s);
+// One map query on a sparse map (debug: per-ray outputs instead of the policy).
+hipError_t launch_sparse(const RayArgs &a, hipStream_t s, bool debug, hipEvent_t ev0 = nullptr,
+                         hipEvent_t ev1 = nullptr);
+// Occupancy masks of n sparse blocks from their values, and the tables' occupied flags.
+hipError_t launch_sparse_masks(const SparseView &v, HashEntry *table, hipStream_t s);
 // Persistent fused batch: `blocks` resident blocks pull tiles from a counter.
 hipError_t launch_batch(const BatchArgs &a, int blocks, int lookahead, hipStream_t s);
 // Resident blocks per CU of the batch kernel for a lookahead.

@@ -121,8 +121,9 @@ __device__ __forceinline__ bool crossed_first(int F, float gb, float rb, float i
 }
 
 // Coordinate along axis b (rb != 0) of the voxel the walk is in right after crossing face Ba
-// of axis a at float32 parameter T32, known to lie in [lo, hi]: the float32 estimate
-// floor(g + T r), confirmed on the face behind it and the face ahead of it.
+// of axis a at float32 parameter T32, known to lie in [lo, hi] (the entered element's extent,
+// cut at the start voxel): the float32 estimate floor(g + T r), confirmed on the face behind
+// it and the face ahead of it, except on the bounds of [lo, hi].
 __device__ __forceinline__ int entry_coord(int lo, int hi, float gb, float rb, float irb, int b, float T32, int Ba,
                                            float ga, float ra, int a, bool &tie)
 {
@@ -164,9 +165,15 @@ __device__ __forceinline__ void entry_voxel(const RayArgs &A, const RayF &R, int
     const float ra = a == 0 ? rx : (a == 1 ? ry : rz);
     const float ira = a == 0 ? irx : (a == 1 ? iry : irz);
     const float T32 = ((float)Ba - ga) * ira;
-    vx = a == 0 ? (px ? lx : lx + E - 1) : (rx != 0.0f ? entry_coord(lx, lx + E - 1, gx, rx, irx, 0, T32, Ba, ga, ra, a, tie) : A.v0[0]);
-    vy = a == 1 ? (py ? ly : ly + E - 1) : (ry != 0.0f ? entry_coord(ly, ly + E - 1, gy, ry, iry, 1, T32, Ba, ga, ra, a, tie) : A.v0[1]);
-    vz = a == 2 ? (pz ? lz : lz + E - 1) : (rz != 0.0f ? entry_coord(lz, lz + E - 1, gz, rz, irz, 2, T32, Ba, ga, ra, a, tie) : A.v0[2]);
+    // along each other axis the walk never moves back past its start voxel, so a face at or
+    // behind the start is no decision of the walk (a start on such a face is not a near-tie)
+    const int x0 = A.v0[0], y0 = A.v0[1], z0 = A.v0[2];
+    const int xlo = px ? max(lx, x0) : lx, xhi = px ? lx + E - 1 : min(lx + E - 1, x0);
+    const int ylo = py ? max(ly, y0) : ly, yhi = py ? ly + E - 1 : min(ly + E - 1, y0);
+    const int zlo = pz ? max(lz, z0) : lz, zhi = pz ? lz + E - 1 : min(lz + E - 1, z0);
+    vx = a == 0 ? (px ? lx : lx + E - 1) : (rx != 0.0f ? entry_coord(xlo, xhi, gx, rx, irx, 0, T32, Ba, ga, ra, a, tie) : x0);
+    vy = a == 1 ? (py ? ly : ly + E - 1) : (ry != 0.0f ? entry_coord(ylo, yhi, gy, ry, iry, 1, T32, Ba, ga, ra, a, tie) : y0);
+    vz = a == 2 ? (pz ? lz : lz + E - 1) : (rz != 0.0f ? entry_coord(zlo, zhi, gz, rz, irz, 2, T32, Ba, ga, ra, a, tie) : z0);
 }
 
 // Entry j of an ordered ray list as one 16-byte load: direction in x, y, z, Halton index bits in w.

@@ -218,6 +218,7 @@ rmpc_status rmpc_rollout_batch(rmpc_ctx *ctx, const rmpc_flight *flights, int32_
         const std::string where = "flight " + std::to_string(i) + ": ";
         auto it = ctx->maps.find(f.map_id);
         if (it == ctx->maps.end()) return fail(RMPC_E_NOMAP, where + "unknown map id");
+        if (it->second.sparse) return fail(RMPC_E_INVALID, where + "batched flights need dense maps (rmpc_rollout flies on sparse ones)");
         if (f.n_rays < 1 || f.n_rays > RMPC_MAX_RAYS) return fail(RMPC_E_INVALID, where + "n_rays out of [1, 65536]");
         if (!finite3(f.x0) || !finite3(f.v0)) return fail(RMPC_E_INVALID, where + "state not finite");
         if (rmpc_status st = check_rollout(&f.rp)) {

@@ -439,3 +439,156 @@ def params(preset: str = "static", **overrides) -> dict:
             raise KeyError(k)
         out[k] = float(v)
     return out
+
+
+# ----------------------------------------------------------------------------------------
+# sparse block maps (8^3-voxel blocks stored where a surface is within reach)
+# ----------------------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class SparseMap:
+    """A synthetic sparse map: float32 TSDF in 8^3-voxel blocks at integer block coordinates
+    (block (bx, by, bz) covers voxels 8 bx .. 8 bx + 7 along x, ...); every voxel outside a
+    stored block is free.  Voxel (i, j, k) has its centre at origin + (idx + 1/2) h."""
+
+    name: str
+    coords: np.ndarray        # int32 [n, 3]
+    values: np.ndarray        # float32 [n, 8, 8, 8], indexed (block, z, y, x)
+    voxel_m: float
+    origin_m: np.ndarray
+    prims: List[Primitive]
+    trunc_m: float
+
+    @property
+    def n_blocks(self) -> int:
+        return int(self.coords.shape[0])
+
+    def occupied_fraction(self) -> float:
+        """Occupied share of the stored voxels."""
+        return float(np.count_nonzero(self.values <= 0)) / self.values.size
+
+    def dense_crop(self, lo_vox, hi_vox) -> Tuple[np.ndarray, np.ndarray]:
+        """The voxels [lo, hi) (x, y, z) as a dense float32 TSDF array [z, y, x] (free voxels
+        +trunc) and the world origin of its minimum corner; lo and hi are multiples of 8."""
+        lo = np.asarray(lo_vox, dtype=np.int64)
+        hi = np.asarray(hi_vox, dtype=np.int64)
+        assert np.all(lo % 8 == 0) and np.all(hi % 8 == 0) and np.all(hi > lo)
+        n = hi - lo
+        out = np.full((n[2], n[1], n[0]), self.trunc_m, np.float32)
+        b = self.coords.astype(np.int64) * 8
+        sel = np.nonzero(np.all((b >= lo) & (b < hi), axis=1))[0]
+        for k in sel:
+            o = b[k] - lo
+            out[o[2]:o[2] + 8, o[1]:o[1] + 8, o[0]:o[0] + 8] = self.values[k]
+        return out, np.asarray(self.origin_m, dtype=np.float64) + lo * self.voxel_m
+
+
+def sparse_from_dense(m: VoxelMap, offset_blocks=(0, 0, 0), keep_free: float = 0.3, seed: int = 0,
+                      origin_m=None) -> SparseMap:
+    """The whole 8^3 blocks of a dense map as a sparse map: every block holding an occupied
+    voxel, and each free block with probability keep_free (seeded), stored in a seeded random
+    order at block coordinates shifted by offset_blocks.  The sparse frame's voxel (0, 0, 0)
+    sits at origin_m (default: where the shifted blocks line up with the dense grid)."""
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = m.tsdf.shape
+    coords, vals = [], []
+    for bz in range(nz // 8):
+        for by in range(ny // 8):
+            for bx in range(nx // 8):
+                blk = m.tsdf[8 * bz:8 * bz + 8, 8 * by:8 * by + 8, 8 * bx:8 * bx + 8]
+                if np.any(blk <= 0) or rng.uniform() < keep_free:
+                    coords.append((bx + offset_blocks[0], by + offset_blocks[1], bz + offset_blocks[2]))
+                    vals.append(blk)
+    order = rng.permutation(len(coords))
+    off = np.asarray(offset_blocks, dtype=np.float64)
+    origin = np.asarray(m.origin_m, dtype=np.float64) - 8 * off * m.voxel_m if origin_m is None else \
+        np.asarray(origin_m, dtype=np.float64)
+    return SparseMap(f"sparse({m.name})", np.asarray(coords, np.int32)[order],
+                     np.asarray(vals, np.float32)[order], m.voxel_m, origin, list(m.prims), m.trunc_m)
+
+
+def _block_voxel_centres(coords: np.ndarray, origin: np.ndarray, h: float) -> np.ndarray:
+    """World centres [n, 8, 8, 8, 3] (block, z, y, x) of the voxels of blocks `coords`."""
+    i = np.arange(8)
+    zz, yy, xx = np.meshgrid(i, i, i, indexing="ij")
+    local = np.stack([xx, yy, zz], axis=-1).astype(np.float64)          # [z, y, x, 3]
+    base = coords.astype(np.float64)[:, None, None, None, :] * 8.0
+    return origin + (base + local + 0.5) * h
+
+
+def sparse_world(seed: int = 20, side_m: float = 160.0, height_m: float = 12.8, voxel_m: float = 0.05,
+                 n_prims: int = 1500, ground_m: float = 0.5, trunc_m: float = 0.3) -> SparseMap:
+    """An outdoor-sized world stored sparsely: a side x side area (centred on the origin in x
+    and y) with a ground half-space below ground_m and n_prims random spheres and boxes (sizes
+    as in the paper-shaped map) resting on or above it.  Blocks are stored where a surface is
+    within trunc of the block (the ground's layers and the primitives' bounding boxes), as a
+    mapping system allocates blocks near observed surfaces; block coordinates are negative on
+    the lower half of each horizontal axis.  At 0.05 m the dense grid would be 3200 x 3200 x
+    256 voxels (2.6e9, 10.5 GB as float32)."""
+    rng = np.random.default_rng(seed)
+    h = voxel_m
+    nb_xy = int(round(side_m / (8 * h)))
+    origin = np.zeros(3)
+    prims: List[Primitive] = [("halfspace_below", 2, ground_m)]
+    for _ in range(n_prims):
+        c = np.array([rng.uniform(-side_m / 2 + 2, side_m / 2 - 2), rng.uniform(-side_m / 2 + 2, side_m / 2 - 2),
+                      rng.uniform(ground_m, 4.0)])
+        if rng.uniform() < 0.5:
+            prims.append(("sphere", *c, rng.uniform(0.15, 1.0)))
+        else:
+            prims.append(("box", *c, *(0.5 * rng.uniform(0.3, 2.0, size=3))))
+    # blocks within trunc of a surface
+    keys = set()
+    zlo = int(np.floor((ground_m - trunc_m) / (8 * h)))
+    zhi = int(np.floor((ground_m + trunc_m) / (8 * h)))
+    bxs = np.arange(-nb_xy // 2, nb_xy // 2)
+    for bz in range(zlo, zhi + 1):
+        for bx in bxs:
+            keys.update((int(bx), int(by), bz) for by in bxs)
+    for p in prims[1:]:
+        lo, hi = _bbox(p, np.zeros(3))
+        lo_b = np.floor((np.asarray(lo) - trunc_m - origin) / (8 * h)).astype(int)
+        hi_b = np.floor((np.asarray(hi) + trunc_m - origin) / (8 * h)).astype(int)
+        lo_b[:2] = np.maximum(lo_b[:2], -nb_xy // 2)
+        hi_b[:2] = np.minimum(hi_b[:2], nb_xy // 2 - 1)
+        for bz in range(lo_b[2], hi_b[2] + 1):
+            for by in range(lo_b[1], hi_b[1] + 1):
+                for bx in range(lo_b[0], hi_b[0] + 1):
+                    keys.add((bx, by, bz))
+    coords = np.array(sorted(keys), np.int32)
+    coords = coords[rng.permutation(len(coords))]
+    index = {tuple(c): k for k, c in enumerate(coords.tolist())}
+    # values: the ground (a function of z only), then each primitive over its blocks
+    n = len(coords)
+    zc = origin[2] + (coords[:, 2].astype(np.float64)[:, None] * 8 + np.arange(8) + 0.5) * h     # [n, 8]
+    vals = np.clip(zc - ground_m, -trunc_m, trunc_m)[:, :, None, None] * np.ones((1, 1, 8, 8))
+    vals = vals.astype(np.float64)
+    for p in prims[1:]:
+        lo, hi = _bbox(p, np.zeros(3))
+        lo_b = np.floor((np.asarray(lo) - trunc_m - origin) / (8 * h)).astype(int)
+        hi_b = np.floor((np.asarray(hi) + trunc_m - origin) / (8 * h)).astype(int)
+        ks = [index[(bx, by, bz)] for bz in range(lo_b[2], hi_b[2] + 1) for by in range(lo_b[1], hi_b[1] + 1)
+              for bx in range(lo_b[0], hi_b[0] + 1) if (bx, by, bz) in index]
+        if not ks:
+            continue
+        ks = np.asarray(ks)
+        P = _block_voxel_centres(coords[ks], origin, h)
+        vals[ks] = np.minimum(vals[ks], np.clip(_sdf(p, P), -trunc_m, trunc_m))
+    # blocks with no voxel within trunc of a surface are free throughout: not stored
+    keep = np.any(vals < trunc_m, axis=(1, 2, 3))
+    return SparseMap(f"sparse_world({seed})", coords[keep], vals[keep].astype(np.float32), h, origin, prims,
+                     trunc_m)
+
+
+def sparse_free_state(m: SparseMap, seed: int, height_m=(1.0, 3.0)) -> Tuple[np.ndarray, np.ndarray]:
+    """A position over the world's area at a height in height_m, redrawn until the analytic
+    clearance is at least one voxel and its voxel is free; velocity ~ N(0, I3) m/s."""
+    rng = np.random.default_rng(seed)
+    lo = m.coords.min(axis=0).astype(np.float64) * 8 * m.voxel_m + m.origin_m
+    hi = (m.coords.max(axis=0).astype(np.float64) + 1) * 8 * m.voxel_m + m.origin_m
+    while True:
+        x = np.array([rng.uniform(lo[0] + 12, hi[0] - 12), rng.uniform(lo[1] + 12, hi[1] - 12),
+                      rng.uniform(*height_m)])
+        if sdf_union(m.prims, x[None, :])[0] >= m.voxel_m:
+            break
+    return x, rng.normal(0.0, 1.0, size=3)

@@ -4,6 +4,8 @@ import os
 import re
 import subprocess
 
+import numpy as np
+
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -36,6 +38,14 @@ def test_library_exports_every_declared_symbol(lib_path):
     exported = set(re.findall(r"\sT\s(rmpc_\w+)$", out, re.M))
     missing = [n for n in _declared() if n not in exported]
     assert not missing, missing
+
+
+def test_library_resolves_its_own_symbols(lib_path):
+    """No entry point or kernel launcher is left undefined (a shared library links even when
+    one of its sources was not compiled in)."""
+    out = subprocess.run(["nm", "-D", "--undefined-only", lib_path], capture_output=True, text=True,
+                         check=True).stdout
+    assert not re.findall(r"rmpc", out), out
 
 
 def test_binding_loads_and_resolves(lib_path):
@@ -76,3 +86,21 @@ def test_map_footprint_and_size_limits(lib_path):
         fp(4097, 1, 1, "u8", 0.01, (0, 0, 0))
     with pytest.raises(binding.RmpcError, match="voxel size"):
         fp(8, 8, 8, "f32", float("nan"), (0, 0, 0))
+
+
+def test_sparse_workload_round_trip():
+    """The sparse-map inputs the GPU tests compare against the oracle: blocks cut from a dense
+    map and expanded again give back the dense occupancy (free blocks dropped or kept), at any
+    block offset, and stored values keep their block layout (block, z, y, x)."""
+    from paper_2301_08068_amd import workloads as W
+    m = W.tiny_map(1)
+    for off, keep in (((0, 0, 0), 0.0), ((-5, 3, -2), 0.5)):
+        sm = W.sparse_from_dense(m, offset_blocks=off, keep_free=keep, seed=4)
+        lo = np.asarray(off) * 8
+        dense, origin = sm.dense_crop(lo, lo + 64)
+        assert np.array_equal(dense <= 0, m.tsdf <= 0)
+        assert np.allclose(origin, m.origin_m)
+        assert np.all(np.any(sm.values <= 0, axis=(1, 2, 3)) | (keep > 0))
+    k = int(np.argmax(np.any(sm.values <= 0, axis=(1, 2, 3))))
+    bx, by, bz = sm.coords[k] - np.asarray((-5, 3, -2))
+    assert np.array_equal(sm.values[k], m.tsdf[8 * bz:8 * bz + 8, 8 * by:8 * by + 8, 8 * bx:8 * bx + 8])

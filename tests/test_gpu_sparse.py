@@ -1,0 +1,200 @@
+"""Sparse block maps on the GPU (rmpc_sparse_map_upload): the exact walk through the block hash
+against the float64 oracle walking the same voxels expanded into a dense grid large enough
+that no ray leaves it (hits and float64 distances bit for bit, flags and visits exact, TIE a
+subset), query sums, negative block coordinates, collision starts, error handling, and an
+outdoor-sized world at the bench's size checked on a dense crop around the robot."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from paper_2301_08068_amd import workloads as W  # noqa: E402
+from gpu_common import compare_query  # noqa: E402
+
+P_TINY = W.params("static", max_range=5.0)
+P_PAPER = W.params("static", max_range=10.0)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2301_08068_amd import binding
+    c = binding.Context(0, arena_bytes=3 << 30)
+    yield c
+    c.close()
+
+
+def _sparse_hits_as_lin(gpu, sm, lo_vox, dims):
+    """Hit (slot * 512 + x + 8 y + 64 z) -> linear index in the dense crop starting at lo_vox."""
+    nx, ny, _ = dims
+    h = gpu["hit"].astype(np.int64)
+    out = np.full(h.shape, -1, np.int64)
+    ok = h >= 0
+    slot, loc = h[ok] // 512, h[ok] % 512
+    b = sm.coords[slot].astype(np.int64) * 8 - np.asarray(lo_vox, np.int64)
+    vx, vy, vz = b[:, 0] + loc % 8, b[:, 1] + (loc // 8) % 8, b[:, 2] + loc // 64
+    out[ok] = vx + nx * (vy + ny * vz)
+    return out
+
+
+def _dyadic_state(m, sm, shift, seed):
+    """A free start of dense map m, moved so that its sparse grid coordinates are multiples of
+    1/1024 (exact in float32, and after any whole-voxel shift), and a velocity."""
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = m.tsdf.shape
+    while True:
+        k = rng.integers(0, np.array([nx, ny, nz]) * 1024)
+        v0 = k // 1024
+        if m.tsdf[v0[2], v0[1], v0[0]] > 0:
+            break
+    g = k / 1024.0 + 8.0 * np.asarray(shift)
+    x = sm.origin_m + g * sm.voxel_m
+    assert np.all(((x - sm.origin_m) / sm.voxel_m).astype(np.float32) == g)
+    return x, rng.normal(0.0, 1.0, size=3)
+
+
+def _dense_start(sm, x, lo_vox):
+    """The sparse query's start g = float32((x - origin) / h), moved into the dense crop's
+    frame (g - lo, exact in float32, checked)."""
+    g = ((np.asarray(x, np.float64) - sm.origin_m) / sm.voxel_m).astype(np.float32)
+    gd = g.astype(np.float64) - np.asarray(lo_vox, np.float64)
+    assert np.all(gd.astype(np.float32).astype(np.float64) == gd)
+    return gd.astype(np.float32)
+
+
+def _compare(gpu, orc, sm, lo_vox, dims, label):
+    hit_g = _sparse_hits_as_lin(gpu, sm, lo_vox, dims)
+    hit_o = orc["hit"].astype(np.int64)
+    flagged = (orc["flags"] & (oracle.TIE | oracle.RANGE_TIE)) != 0
+    same = hit_g == hit_o
+    bad = ~same & ~flagged
+    assert not bad.any(), f"{label}: {bad.sum()} unflagged rays differ, e.g. ray {np.argmax(bad)}"
+    for i in np.nonzero(~same)[0]:
+        assert hit_g[i] in orc["alt_hit"][i, :orc["alt_n"][i]], f"{label}: ray {i} not admissible"
+    hs = same & (hit_o >= 0)
+    assert np.array_equal(gpu["d"][hs], orc["d"][hs]), f"{label}: distances differ"
+    assert np.all(np.isinf(gpu["d"][same & (hit_o < 0)]))
+    gf, of = gpu["flags"][same].astype(np.uint32), orc["flags"][same].astype(np.uint32)
+    T = np.uint32(oracle.TIE)
+    assert np.array_equal(gf & ~T, of & ~T), f"{label}: flags differ"
+    assert not np.any(gf & ~of & T), f"{label}: TIE where the oracle has none"
+    assert np.array_equal(gpu["visits"][same], orc["visits"][same]), f"{label}: visits differ"
+    return int(same.sum()), int(flagged.sum())
+
+
+@pytest.mark.parametrize("shift,keep_free", [((7, 7, 7), 0.3), ((-40, -33, -9), 0.0)])
+def test_sparse_tiny_parity(ctx, tiny_map, shift, keep_free):
+    """The tiny map's blocks (all occupied ones, a seeded share of the free ones) at block
+    offset `shift`, against the oracle on a dense grid padded by 7 blocks (56 voxels > the
+    50-voxel range) on every side."""
+    sm = W.sparse_from_dense(tiny_map, offset_blocks=shift, keep_free=keep_free, seed=5)
+    mid = ctx.upload_sparse(sm.coords, sm.values, sm.voxel_m, sm.origin_m, "f32")
+    lo = (np.asarray(shift) - 7) * 8
+    hi = (np.asarray(shift) + 8 + 7) * 8
+    dense, o_dense = sm.dense_crop(lo, hi)
+    om = oracle.OracleMap(dense, sm.voxel_m, o_dense, "f32")
+    dirs = oracle.directions(1024)
+    n_same = n_flag = 0
+    try:
+        for seed in range(100, 160):
+            x, v = _dyadic_state(tiny_map, sm, shift, seed)
+            g = ctx.trace(mid, x, 1024, P_TINY)
+            gd = _dense_start(sm, x, lo)
+            o = oracle.trace(om, gd, dirs, P_TINY["max_range"])
+            s, f = _compare(g, o, sm, lo, dense.shape[::-1], f"shift {shift} seed {seed}")
+            n_same += s
+            n_flag += f
+            if seed % 4 == 0:
+                q = ctx.query(mid, x, v, 1024, P_TINY)
+                oq = oracle.combine(P_TINY, dirs, o["d"], o["hit"], v)
+                oq["visits"] = int(o["visits"].sum())
+                oq["n_tie"] = int(np.count_nonzero(o["flags"] & oracle.TIE))
+                compare_query(q, oq, f"query seed {seed}")
+    finally:
+        ctx.release(mid)
+    print(f"sparse tiny {shift}: {n_same} rays identical, {n_flag} flagged, {sm.n_blocks} blocks")
+
+
+def test_sparse_collision_start(ctx, tiny_map):
+    """A start in an occupied voxel: every ray hits it at distance 0 (IN_COLLISION)."""
+    sm = W.sparse_from_dense(tiny_map, offset_blocks=(3, -2, 1), keep_free=0.0, seed=6)
+    mid = ctx.upload_sparse(sm.coords, sm.values, sm.voxel_m, sm.origin_m, "f32")
+    try:
+        k = int(np.argmax(np.any(sm.values <= 0, axis=(1, 2, 3))))
+        z, y, x = np.argwhere(sm.values[k] <= 0)[0]
+        vox = sm.coords[k].astype(np.int64) * 8 + np.array([x, y, z])
+        pos = sm.origin_m + (vox + 0.5) * sm.voxel_m
+        q = ctx.query(mid, pos, np.array([0.3, -0.2, 0.1]), 512, P_TINY)
+        assert q["flags"] & oracle.Q_IN_COLLISION and q["n_hit"] == 512
+        t = ctx.trace(mid, pos, 512, P_TINY)
+        assert np.all(t["hit"] == k * 512 + x + 8 * y + 64 * z) and np.all(t["d"] == 0.0)
+        assert np.all(t["visits"] == 1) and np.all(t["flags"] & oracle.IN_COLLISION)
+    finally:
+        ctx.release(mid)
+
+
+def test_sparse_errors(ctx, tiny_map):
+    from paper_2301_08068_amd import binding
+    sm = W.sparse_from_dense(tiny_map, offset_blocks=(0, 0, 0), keep_free=0.0, seed=7)
+    with pytest.raises(binding.RmpcError, match="twice"):
+        ctx.upload_sparse(np.concatenate([sm.coords, sm.coords[:1]]), np.concatenate([sm.values, sm.values[:1]]),
+                          sm.voxel_m, sm.origin_m)
+    bad = sm.coords.copy()
+    bad[0, 1] = 1 << 20
+    with pytest.raises(binding.RmpcError, match="coordinate"):
+        ctx.upload_sparse(bad, sm.values, sm.voxel_m, sm.origin_m)
+    mid = ctx.upload_sparse(sm.coords, sm.values, sm.voxel_m, sm.origin_m, "f32")
+    try:
+        x, v = W.free_state(tiny_map, 100)
+        with pytest.raises(binding.RmpcError, match="subvoxel"):
+            ctx.query(mid, x, v, 256, dict(P_TINY, subvoxel=1.0))
+        with pytest.raises(binding.RmpcError, match="sparse"):
+            ctx.query_batch([dict(kind="map", map_id=mid, n=256, x=x, v=v)], map_params=P_TINY)
+        with pytest.raises(binding.RmpcError, match="dense"):
+            ctx.edt(mid, (8, 8, 8))
+        with pytest.raises(binding.RmpcError, match="far"):
+            ctx.query(mid, np.array([1e6, 0.0, 0.0]), v, 256, P_TINY)
+        # the ray policy itself is unchanged: zero velocity gives zero sums exactly
+        q = ctx.query(mid, x, np.zeros(3), 1024, P_TINY)
+        assert not np.any(q["S"]) and not np.any(q["f"]) and q["n_hit"] > 0
+    finally:
+        ctx.release(mid)
+
+
+@pytest.fixture(scope="module")
+def world():
+    return W.sparse_world(20)
+
+
+def test_sparse_world_65536(ctx, world):
+    """The outdoor-sized world of the sparse bench line (negative block coordinates, ~0.5 M
+    blocks), 65,536 rays from two states with a 10 m range: every ray against the oracle on a
+    dense crop that holds every voxel the rays can reach, and the query sums."""
+    sm = world
+    mid = ctx.upload_sparse(sm.coords, sm.values, sm.voxel_m, sm.origin_m, "f32")
+    dirs = oracle.directions(65536)
+    try:
+        for seed in (700, 701):
+            x, v = W.sparse_free_state(sm, seed)
+            # moved by under 1e-3 voxel so that g is a multiple of 1/1024 (exact in both frames)
+            x = sm.origin_m + np.round((x - sm.origin_m) / sm.voxel_m * 1024.0) / 1024.0 * sm.voxel_m
+            g = ((x - sm.origin_m) / sm.voxel_m).astype(np.float32)
+            reach = int(np.ceil(P_PAPER["max_range"] / sm.voxel_m)) + 16
+            lo = (np.floor((g.astype(np.float64) - reach) / 8) * 8).astype(np.int64)
+            hi = (np.ceil((g.astype(np.float64) + reach) / 8) * 8).astype(np.int64)
+            dense, o_dense = sm.dense_crop(lo, hi)
+            om = oracle.OracleMap(dense, sm.voxel_m, o_dense, "f32")
+            t = ctx.trace(mid, x, 65536, P_PAPER)
+            o = oracle.trace(om, _dense_start(sm, x, lo), dirs, P_PAPER["max_range"], nthreads=8)
+            s, f = _compare(t, o, sm, lo, dense.shape[::-1], f"world state {seed}")
+            q = ctx.query(mid, x, v, 65536, P_PAPER)
+            oq = oracle.combine(P_PAPER, dirs, o["d"], o["hit"], v)
+            oq["visits"] = int(o["visits"].sum())
+            oq["n_tie"] = int(np.count_nonzero(o["flags"] & oracle.TIE))
+            compare_query(q, oq, f"world query {seed}")
+            print(f"world state {seed}: {s} rays identical, {f} flagged, {int((o['hit'] >= 0).sum())} hits")
+    finally:
+        ctx.release(mid)
