@@ -218,10 +218,58 @@ __device__ __forceinline__ void jacobi_rotate(double (&S)[3][3], double (&V)[3][
     }
 }
 
+// Eigenvalues of a symmetric 3x3 matrix, ascending, from the trigonometric solution of its
+// characteristic cubic: with q = tr S / 3, p^2 = |S - q I|_F^2 / 6 and B = (S - q I) / p, the
+// eigenvalues are q + 2 p cos(phi + 2 pi k / 3), phi = acos(det B / 2) / 3.  Each is within a
+// few units of rounding of |S| of the exact value.  False for a diagonal matrix.
+__device__ inline bool sym3_eigvals(const double (&S)[3][3], double (&lam)[3])
+{
+    const double p1 = S[0][1] * S[0][1] + S[0][2] * S[0][2] + S[1][2] * S[1][2];
+    if (p1 == 0.0) return false;
+    const double q = (S[0][0] + S[1][1] + S[2][2]) * (1.0 / 3.0);
+    const double d0 = S[0][0] - q, d1 = S[1][1] - q, d2 = S[2][2] - q;
+    const double p = sqrt((d0 * d0 + d1 * d1 + d2 * d2 + 2.0 * p1) * (1.0 / 6.0));
+    const double ip = 1.0 / p;
+    const double b00 = d0 * ip, b11 = d1 * ip, b22 = d2 * ip;
+    const double b01 = S[0][1] * ip, b02 = S[0][2] * ip, b12 = S[1][2] * ip;
+    const double det = b00 * (b11 * b22 - b12 * b12) - b01 * (b01 * b22 - b12 * b02) + b02 * (b01 * b12 - b11 * b02);
+    const double r = fmin(1.0, fmax(-1.0, 0.5 * det));
+    const double phi = acos(r) * (1.0 / 3.0);
+    lam[2] = q + 2.0 * p * cos(phi);
+    lam[0] = q + 2.0 * p * cos(phi + 2.0943951023931957);          // + 2 pi / 3
+    lam[1] = 3.0 * q - lam[0] - lam[2];
+    return true;
+}
+
 // Resolve a symmetric PSD 3x3 metric sum: eigenvalues (ascending), rank, ILL flag and f.
+// A sum whose smallest eigenvalue lies clearly above the ILL band and whose condition number
+// lies clearly below the ILL limit (both by a relative margin of 1e-9, far above the closed
+// form's error) has full rank and no ILL flag: there f = S^-1 b by the adjugate, which is the
+// pseudo-inverse; every other sum takes the cyclic Jacobi path below.
 __device__ inline void resolve3(const double (&Sin)[3][3], const double (&b)[3], double rank_tol,
                                 double (&f)[3], double (&lam)[3], int32_t &rank, uint32_t &flags)
 {
+    {
+        double l[3];
+        if (sym3_eigvals(Sin, l) && l[2] > 0.0 && l[0] > 10.0 * (rank_tol * l[2]) * (1.0 + 1e-9) &&
+            l[2] < 1e3 * (1.0 - 1e-9) * l[0]) {
+            const double(&A)[3][3] = Sin;
+            // cofactors (symmetric for a symmetric matrix, so the adjugate is the same matrix)
+            const double c00 = A[1][1] * A[2][2] - A[1][2] * A[2][1];
+            const double c01 = A[1][2] * A[2][0] - A[1][0] * A[2][2];
+            const double c02 = A[1][0] * A[2][1] - A[1][1] * A[2][0];
+            const double c11 = A[0][0] * A[2][2] - A[0][2] * A[2][0];
+            const double c12 = A[0][1] * A[2][0] - A[0][0] * A[2][1];
+            const double c22 = A[0][0] * A[1][1] - A[0][1] * A[1][0];
+            const double id = 1.0 / (A[0][0] * c00 + A[0][1] * c01 + A[0][2] * c02);
+            f[0] = (c00 * b[0] + c01 * b[1] + c02 * b[2]) * id;
+            f[1] = (c01 * b[0] + c11 * b[1] + c12 * b[2]) * id;
+            f[2] = (c02 * b[0] + c12 * b[1] + c22 * b[2]) * id;
+            lam[0] = l[0]; lam[1] = l[1]; lam[2] = l[2];
+            rank = 3;
+            return;
+        }
+    }
     double S[3][3], V[3][3];
     double frob2 = 0.0;
 #pragma unroll
@@ -332,20 +380,25 @@ __device__ inline void grid_finish(const Acc &a, int b, int nb, const FinishSlot
                                    double rank_tol, int32_t n_rays, uint32_t extra_flags, float *lds)
 {
     __shared__ int last;
-    __shared__ float tot[kPartialWords];
+    __shared__ __align__(16) float tot[kPartialWords];
     block_reduce_store(a, lds, tot);
     __syncthreads();
-    if (threadIdx.x < kWave) {               // wave 0 stores the row, then takes the ticket
-        if (threadIdx.x < 22) F.tile_rows[(size_t)b * kPartialWords + threadIdx.x] = tot[threadIdx.x];
-        __threadfence();
-        if (threadIdx.x == 0) {
-            const uint32_t prev = __hip_atomic_fetch_add(F.tickets, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-            last = prev == (uint32_t)(nb - 1);
-        }
+    if (threadIdx.x == 0) {
+        // one thread stores the block's row (the 22 words and 2 of padding) and takes the ticket
+        // with release order only: the release writes this XCD's L2 back so that the last
+        // block, on any XCD, reads the row; an acquire here would invalidate the L2 that the
+        // blocks still walking on this XCD read the map through
+        float4 *dst = reinterpret_cast<float4 *>(F.tile_rows + (size_t)b * kPartialWords);
+        const float4 *src = reinterpret_cast<const float4 *>(tot);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) dst[k] = src[k];
+        const uint32_t prev = __hip_atomic_fetch_add(F.tickets, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        last = prev == (uint32_t)(nb - 1);
     }
     __syncthreads();
     if (!last) return;
-    __threadfence();
+    // the last block acquires every block's row
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     Acc m;
     m.zero();
     for (int r0 = threadIdx.x; r0 < nb; r0 += 2 * kBlock) {
