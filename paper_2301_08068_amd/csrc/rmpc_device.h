@@ -351,12 +351,20 @@ __device__ inline void finalize_result(const Acc &a, double rank_tol, int32_t n_
     out->visits = a.visits;
 }
 
+// A row in partial layout (16-byte aligned: rows are 128 bytes apart) as six 16-byte loads.
 __device__ __forceinline__ void acc_from_partial(const float *p, Acc &a)
 {
+    const float4 *q4 = reinterpret_cast<const float4 *>(p);
+    float w[24];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) { a.s[k] = p[k]; a.c[k] = p[9 + k]; }
-    const int32_t *q = reinterpret_cast<const int32_t *>(p + 18);
-    a.n_hit = q[0]; a.n_contrib = q[1]; a.n_tie = q[2]; a.visits = q[3];
+    for (int k = 0; k < 6; ++k) {
+        const float4 v = q4[k];
+        w[4 * k] = v.x; w[4 * k + 1] = v.y; w[4 * k + 2] = v.z; w[4 * k + 3] = v.w;
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) { a.s[k] = w[k]; a.c[k] = w[9 + k]; }
+    a.n_hit = __float_as_int(w[18]); a.n_contrib = __float_as_int(w[19]);
+    a.n_tie = __float_as_int(w[20]); a.visits = __float_as_int(w[21]);
 }
 
 // Where one reduction keeps its state: tile rows (one per tile), a ticket, the result slot,

@@ -115,7 +115,7 @@ struct RayArgs {
     uint32_t start_flags;        // RMPC_RAY_START_FACE when g is within 1e-5 of a face
     float tmax_lo, tmax_hi;      // float32 guard band around max_range / h
     double tmax_v;               // parameter span split into segments: min(max_range / h, grid diagonal)
-    int32_t segments;            // lanes per ray (1, 2, 4, 8 or 16)
+    int32_t segments;            // segments per ray (1, 2, 4, 8 or 16): a tile holds kBlock / segments rays
     int32_t lookahead;           // steps planned per round (4, 8 or 16)
     double max_range, h;
     int32_t subvoxel;            // non-zero: refine hit distances on the interpolated TSDF
