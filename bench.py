@@ -25,7 +25,7 @@ if ROOT not in sys.path:
 METRIC = "rays/sec (raycast+RMP+resolve) at 65536 rays/query; served p50/p99 query latency"
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_2301_08068_amd/csrc/raycast.hip", "paper_2301_08068_amd/csrc/rmpc_device.h",
-                  "paper_2301_08068_amd/csrc/rmpc_kernels.h"]
+                  "paper_2301_08068_amd/csrc/rmpc_kernels.h", "paper_2301_08068_amd/csrc/rmpc_walk.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "raycast_rmp_paper400_f32_traffic.txt")
 L2_FILE = os.path.join(ROOT, "profiles", "raycast_rmp_paper400_f32_instmix_l2.txt")
 L2_LINE_BYTES = 128
