@@ -209,43 +209,51 @@ def batch_bench(args):
 SERVE_RATES = (2000, 5000, 10000, 20000)
 
 
-def _serve_rate(binding, ctx, reqs, n_units, is_grid, arrivals, server_kw, warm):
-    """One open-loop Poisson run: submit each request at its arrival time, collect results as
-    they complete, return per-request latency from scheduled arrival (s) and counters."""
+def _serve_open_loop(binding, ctx, reqs, arrivals):
+    """Submit each request at its arrival time (s from now) and collect results as they
+    complete; returns submit times and latencies from the scheduled arrival (s)."""
+    import numpy as np
+    n = len(reqs)
+    idx_of = {}
+    sub = np.zeros(n)
+    lat = np.full(n, np.nan)
+    done_t = 0.0
+    i = done = 0
+    t0 = time.perf_counter()
+    last_progress = t0
+    while done < n:
+        now = time.perf_counter() - t0
+        while i < n and arrivals[i] <= now:
+            idx_of[binding.rmpc_submit(ctx.ptr, reqs[i])] = i
+            sub[i] = time.perf_counter() - t0
+            i += 1
+        tks, lats, _, k = binding.rmpc_poll_completed(ctx.ptr, 1024, raw=True)
+        if k:
+            tnow = time.perf_counter()
+            done_t = tnow - t0
+            last_progress = tnow
+            for t, l in zip(tks, lats):
+                j = idx_of.pop(t)
+                lat[j] = (sub[j] - arrivals[j]) + l     # arrival -> result on the host
+            done += k
+        elif time.perf_counter() - last_progress > 60.0:
+            raise RuntimeError("serving run made no progress for 60 s")
+    return sub, lat, done_t
+
+
+def _serve_rate(binding, ctx, reqs, n_units, is_grid, arrivals, server_kw, n_warm):
+    """One open-loop Poisson run: after an untimed paced pass over the first n_warm requests
+    at the same rate (the GPU's clocks ramp up under load within tens of milliseconds; a run
+    that starts from a lightly loaded GPU would measure that ramp), submit each request at its
+    arrival time, collect results as they complete, and return per-request latency from the
+    scheduled arrival (s) and counters."""
     import numpy as np
     binding.rmpc_server_start(ctx.ptr, **server_kw)
     try:
-        for r in warm:                                  # warm-up (not timed)
-            binding.rmpc_submit(ctx.ptr, r)
-        got = 0
-        while got < len(warm):
-            got += binding.rmpc_poll_completed(ctx.ptr, 512, raw=True)[3]
+        _serve_open_loop(binding, ctx, reqs[:n_warm], arrivals[:n_warm])
         base = binding.rmpc_server_stats(ctx.ptr)
         n = len(reqs)
-        idx_of = {}
-        sub = np.zeros(n)
-        lat = np.full(n, np.nan)
-        done_t = 0.0
-        i = done = 0
-        t0 = time.perf_counter()
-        last_progress = t0
-        while done < n:
-            now = time.perf_counter() - t0
-            while i < n and arrivals[i] <= now:
-                idx_of[binding.rmpc_submit(ctx.ptr, reqs[i])] = i
-                sub[i] = time.perf_counter() - t0
-                i += 1
-            tks, lats, _, k = binding.rmpc_poll_completed(ctx.ptr, 1024, raw=True)
-            if k:
-                tnow = time.perf_counter()
-                done_t = tnow - t0
-                last_progress = tnow
-                for t, l in zip(tks, lats):
-                    j = idx_of.pop(t)
-                    lat[j] = (sub[j] - arrivals[j]) + l     # arrival -> result on the host
-                done += k
-            elif time.perf_counter() - last_progress > 60.0:
-                raise RuntimeError("serving run made no progress for 60 s")
+        sub, lat, done_t = _serve_open_loop(binding, ctx, reqs, arrivals)
         st = binding.rmpc_server_stats(ctx.ptr)
     finally:
         binding.rmpc_server_stop(ctx.ptr)
@@ -262,7 +270,7 @@ def _serve_rate(binding, ctx, reqs, n_units, is_grid, arrivals, server_kw, warm)
         "offered_evals_per_s": units / float(arrivals[n - 1]),
         "launches": st["launches"] - base["launches"],
         "mean_batch": round(n / max(1, st["launches"] - base["launches"]), 2),
-        "batch_max": st["batch_max"],
+        "batch_max_since_start": st["batch_max"],
         "staging_waits": st["staging_waits"] - base["staging_waits"],
         "refused": st["refused"] - base["refused"],
         "staging_peak_bytes": st["staging_peak"],
@@ -482,7 +490,7 @@ def serve_compare(n_requests, rates, slots, check_alone=True):
             arrivals = W.poisson_arrivals(rate, n, seed=500)
             row = {"rate_req_s": rate}
             for name, kw in modes.items():
-                row[name] = _serve_rate(binding, ctx, reqs, units, is_grid, arrivals, kw, reqs[:64])
+                row[name] = _serve_rate(binding, ctx, reqs, units, is_grid, arrivals, kw, max(64, min(n, rate // 20)))
                 print(json.dumps({"progress": f"rate {rate} {name}", **row[name]}), file=sys.stderr, flush=True)
             rows.append(row)
         equal, sample = 0, []
@@ -759,7 +767,7 @@ def main():
         config["batch_rays_per_s"] = round(b["batch_rays_per_s"])
         config["plain_rays_per_s"] = round(b["plain_rays_per_s"])
         config["batch_over_plain"] = round(b["batch_rays_per_s"] / b["plain_rays_per_s"], 2)
-        sv = serve_compare(args.extras_requests, (2000, 20000), args.serve_slots, check_alone=True)
+        sv = serve_compare(args.extras_requests, (2000, 20000, 40000), args.serve_slots, check_alone=True)
         for row in sv["rows"]:
             r = row["rate_req_s"]
             for mode, tag in (("continuous", "served"), ("one_per_launch", "one_per_launch")):

@@ -1,6 +1,6 @@
 // batch.hip -- many queries in one persistent launch (rmpc_query_batch), the launch-config
 // autotuner with its on-disk cache (rmpc_tune_batch), and the launch slots that the batch
-// path and the serving loop share.  Host code only.
+// path and the serving loop share.  Host code, and one trivial kernel that starts a new stream.
 
 #include <hip/hip_runtime.h>
 
@@ -27,6 +27,16 @@ rmpc_status check_config(const rmpc_launch_config *c)
     if (c->use_graph != 0 && c->use_graph != 1) return fail(RMPC_E_INVALID, "use_graph must be 0 or 1");
     return RMPC_OK;
 }
+
+namespace {
+
+// Writes zero to a word that is zero already (the first work word of a new slot).
+__global__ void stream_touch_kernel(uint32_t *w)
+{
+    if (threadIdx.x == 0) w[0] = 0u;
+}
+
+}  // namespace
 
 rmpc_status slot_create(rmpc_ctx *ctx, LaunchSlot &slot, int max_queries, int max_tiles)
 {
@@ -61,6 +71,17 @@ rmpc_status slot_create(rmpc_ctx *ctx, LaunchSlot &slot, int max_queries, int ma
     RMPC_HIP(hipHostMalloc(reinterpret_cast<void **>(&slot.q_host), sizeof(rmpc::BatchQuery) * (size_t)max_queries, 0));
     RMPC_HIP(hipStreamCreateWithFlags(&slot.stream, hipStreamNonBlocking));
     RMPC_HIP(hipEventCreateWithFlags(&slot.ev, hipEventDisableTiming));
+    // a first kernel and first copies (a small one and one of every descriptor, the size of a
+    // scan's points) on the new stream, so that the runtime sets up its queues now and not under
+    // the first batches (a serving slot's first launches would wait)
+    std::memset(slot.hdr_host, 0, sizeof(rmpc::BatchHeader));
+    std::memset(slot.q_host, 0, sizeof(rmpc::BatchQuery) * (size_t)max_queries);
+    RMPC_HIP(hipMemcpyAsync(slot.hdr, slot.hdr_host, sizeof(rmpc::BatchHeader), hipMemcpyHostToDevice, slot.stream));
+    RMPC_HIP(hipMemcpyAsync(slot.q, slot.q_host, sizeof(rmpc::BatchQuery) * (size_t)max_queries, hipMemcpyHostToDevice,
+                            slot.stream));
+    stream_touch_kernel<<<1, 64, 0, slot.stream>>>(slot.work);
+    RMPC_HIP(hipGetLastError());
+    RMPC_HIP(hipStreamSynchronize(slot.stream));
     return RMPC_OK;
 }
 
@@ -118,16 +139,10 @@ rmpc_status batch_describe(rmpc_ctx *ctx, const rmpc_query_desc &d, int k, const
     return RMPC_OK;
 }
 
-rmpc_status slot_launch(rmpc_ctx *ctx, LaunchSlot &slot, int nq, int n_tiles,
-                        const rmpc_launch_config &cfg, hipEvent_t after, uint64_t *seq_out)
+namespace {
+
+rmpc::BatchArgs slot_args(LaunchSlot &slot)
 {
-    const uint64_t seq = ++slot.seq;
-    slot.hdr_host->n_queries = nq;
-    slot.hdr_host->n_tiles = n_tiles;
-    slot.hdr_host->seq = seq;
-    const int per_cu = cfg.blocks_per_cu > 0 ? cfg.blocks_per_cu : rmpc::batch_blocks_per_cu(cfg.lookahead);
-    const int gblocks = per_cu * ctx->cu_count;
-    const int blocks = std::max(1, std::min(gblocks, n_tiles));
     rmpc::BatchArgs B;
     B.hdr = slot.hdr;
     B.q = slot.q;
@@ -136,22 +151,51 @@ rmpc_status slot_launch(rmpc_ctx *ctx, LaunchSlot &slot, int nq, int n_tiles,
     B.partials = slot.partials;
     B.results = slot.results_host;
     B.done = slot.done_host;
+    return B;
+}
+
+int graph_blocks(rmpc_ctx *ctx, const rmpc_launch_config &cfg)
+{
+    const int per_cu = cfg.blocks_per_cu > 0 ? cfg.blocks_per_cu : rmpc::batch_blocks_per_cu(cfg.lookahead);
+    return per_cu * ctx->cu_count;
+}
+
+}  // namespace
+
+rmpc_status slot_graph(rmpc_ctx *ctx, LaunchSlot &slot, const rmpc_launch_config &cfg)
+{
+    const int gblocks = graph_blocks(ctx, cfg);
+    if (slot.graph && slot.graph_blocks == gblocks && slot.graph_lookahead == cfg.lookahead) return RMPC_OK;
+    // the grid is fixed (resident blocks) and the per-batch data sit in device memory, so one
+    // captured launch serves every batch of this slot
+    if (slot.graph) { RMPC_HIP(hipGraphExecDestroy(slot.graph)); slot.graph = nullptr; }
     hipStream_t s = slot.stream;
-    if (cfg.use_graph && (!slot.graph || slot.graph_blocks != gblocks || slot.graph_lookahead != cfg.lookahead)) {
-        // the grid is fixed (resident blocks) and the per-batch data sit in device memory, so
-        // one captured launch serves every batch of this slot
-        if (slot.graph) { RMPC_HIP(hipGraphExecDestroy(slot.graph)); slot.graph = nullptr; }
-        hipGraph_t g;
-        RMPC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        const hipError_t le = rmpc::launch_batch(B, gblocks, cfg.lookahead, s);
-        const hipError_t ce = hipStreamEndCapture(s, &g);
-        if (le != hipSuccess) return fail(RMPC_E_HIP, std::string("batch capture: ") + hipGetErrorString(le));
-        if (ce != hipSuccess) return fail(RMPC_E_HIP, std::string("batch capture: ") + hipGetErrorString(ce));
-        const hipError_t ie = hipGraphInstantiate(&slot.graph, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (ie != hipSuccess) return fail(RMPC_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(ie));
-        slot.graph_blocks = gblocks;
-        slot.graph_lookahead = cfg.lookahead;
+    hipGraph_t g;
+    RMPC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    const hipError_t le = rmpc::launch_batch(slot_args(slot), gblocks, cfg.lookahead, s);
+    const hipError_t ce = hipStreamEndCapture(s, &g);
+    if (le != hipSuccess) return fail(RMPC_E_HIP, std::string("batch capture: ") + hipGetErrorString(le));
+    if (ce != hipSuccess) return fail(RMPC_E_HIP, std::string("batch capture: ") + hipGetErrorString(ce));
+    const hipError_t ie = hipGraphInstantiate(&slot.graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) return fail(RMPC_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(ie));
+    slot.graph_blocks = gblocks;
+    slot.graph_lookahead = cfg.lookahead;
+    return RMPC_OK;
+}
+
+rmpc_status slot_launch(rmpc_ctx *ctx, LaunchSlot &slot, int nq, int n_tiles,
+                        const rmpc_launch_config &cfg, hipEvent_t after, uint64_t *seq_out)
+{
+    const uint64_t seq = ++slot.seq;
+    slot.hdr_host->n_queries = nq;
+    slot.hdr_host->n_tiles = n_tiles;
+    slot.hdr_host->seq = seq;
+    const int blocks = std::max(1, std::min(graph_blocks(ctx, cfg), n_tiles));
+    const rmpc::BatchArgs B = slot_args(slot);
+    hipStream_t s = slot.stream;
+    if (cfg.use_graph) {
+        if (rmpc_status st = slot_graph(ctx, slot, cfg)) return st;
     }
     if (after) RMPC_HIP(hipStreamWaitEvent(s, after, 0));
     RMPC_HIP(hipMemcpyAsync(slot.hdr, slot.hdr_host, sizeof(rmpc::BatchHeader), hipMemcpyHostToDevice, s));

@@ -129,6 +129,8 @@ void slot_destroy(rmpc_ctx *ctx, LaunchSlot &slot);
 // Validate query k and fill its descriptor (tiles not yet placed).
 rmpc_status batch_describe(rmpc_ctx *ctx, const rmpc_query_desc &d, int k, const rmpc_params *mp,
                            const rmpc_params *sp, const rmpc_launch_config &cfg, rmpc::BatchQuery &Q);
+// Capture (or re-capture after a change of grid or lookahead) the slot's launch as a graph.
+rmpc_status slot_graph(rmpc_ctx *ctx, LaunchSlot &slot, const rmpc_launch_config &cfg);
 // Copy slot.q_host[0..nq) to the device and launch on the slot's stream after `after` (an
 // event already recorded, or null).  Returns the launch's sequence number; non-blocking.
 rmpc_status slot_launch(rmpc_ctx *ctx, LaunchSlot &slot, int nq, int n_tiles,

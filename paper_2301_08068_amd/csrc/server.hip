@@ -77,6 +77,12 @@ struct ServerState {
     rmpc_status error = RMPC_OK;
     std::string error_msg;
     rmpc_server_counters ctr;
+    // written under mu, read without it: the server thread takes mu only when a request waits
+    // (or to sleep), and pollers only when a result or an error is there, so that a caller
+    // polling in a tight loop does not keep the server thread off the lock
+    std::atomic<int64_t> n_pending{0};       // == pending.size()
+    std::atomic<int64_t> n_ready{0};         // == done_order.size()
+    std::atomic<bool> failed{false};         // error != RMPC_OK
 
     std::thread th;
 };
@@ -89,6 +95,7 @@ void set_error(ServerState *S, rmpc_status st, const std::string &msg)
     if (S->error == RMPC_OK) {
         S->error = st;
         S->error_msg = msg;
+        S->failed.store(true, std::memory_order_release);
     }
 }
 
@@ -105,6 +112,7 @@ void collect(ServerState *S, Slot &sl, Clock::time_point now)
         S->outstanding.erase(r.ticket);
         S->done_order.push_back(r.ticket);
     }
+    S->n_ready.store((int64_t)S->done_order.size(), std::memory_order_release);
     S->ctr.completed += sl.members.size();
     S->ctr.in_flight -= sl.members.size();
     rmpc_sched::release_launch(sl.members, S->stage_alloc);
@@ -174,6 +182,13 @@ void server_loop(rmpc_ctx *ctx, ServerState *S)
         int free_slot = -1;
         for (int i = 0; i < S->n_slots && free_slot < 0; ++i)
             if (!S->slots[i].busy) free_slot = i;
+        if (in_flight && !(free_slot >= 0 && S->n_pending.load(std::memory_order_acquire) > 0) &&
+            !S->failed.load(std::memory_order_acquire)) {
+            // launches running and nothing to admit: keep watching the completion words
+            ++spins;
+            __builtin_ia32_pause();
+            continue;
+        }
         std::unique_lock<std::mutex> lk(S->mu);
         if (S->error != RMPC_OK) return;
         if (free_slot >= 0 && !S->pending.empty()) {
@@ -185,6 +200,7 @@ void server_loop(rmpc_ctx *ctx, ServerState *S)
             }
             if (f.n > 0) {
                 S->ctr.pending -= (uint64_t)f.n;
+                S->n_pending.store((int64_t)S->pending.size(), std::memory_order_release);
                 S->ctr.in_flight += (uint64_t)f.n;
                 S->ctr.launches += 1;
                 S->ctr.batch_max = std::max<uint64_t>(S->ctr.batch_max, (uint64_t)f.n);
@@ -273,7 +289,10 @@ rmpc_status rmpc_server_start(rmpc_ctx *ctx, const rmpc_server_config *cfg)
     }
     for (int i = 0; i < cfg->n_slots; ++i) {
         S->n_slots = i + 1;
-        if (rmpc_status st = slot_create(ctx, S->slots[i].ls, cfg->max_batch, S->lim.max_tiles)) {
+        rmpc_status st = slot_create(ctx, S->slots[i].ls, cfg->max_batch, S->lim.max_tiles);
+        // every slot's graph is captured now, so that no request waits for a capture
+        if (!st && cfg->launch.use_graph) st = slot_graph(ctx, S->slots[i].ls, cfg->launch);
+        if (st) {
             const std::string msg = g_last_error;
             server_destroy(ctx);
             return fail(st, msg);
@@ -321,6 +340,7 @@ rmpc_status rmpc_submit(rmpc_ctx *ctx, const rmpc_request *req, uint64_t *ticket
     *ticket = r.ticket;
     S->outstanding.insert(r.ticket);
     S->pending.push_back(std::move(r));
+    S->n_pending.store((int64_t)S->pending.size(), std::memory_order_release);
     ++S->ctr.submitted;
     ++S->ctr.pending;
     S->cv.notify_one();
@@ -354,6 +374,10 @@ rmpc_status rmpc_poll_completed(rmpc_ctx *ctx, int32_t max, uint64_t *tickets, r
     if (max < 0) return fail(RMPC_E_INVALID, "max is negative");
     ServerState *S = ctx->server;
     if (!S) return fail(RMPC_E_STOPPED, "no server is running");
+    if (S->n_ready.load(std::memory_order_acquire) == 0 && !S->failed.load(std::memory_order_acquire)) {
+        *n_out = 0;                                      // nothing there: no lock taken
+        return RMPC_OK;
+    }
     std::lock_guard<std::mutex> lk(S->mu);
     int32_t n = 0;
     while (n < max && !S->done_order.empty()) {
@@ -367,6 +391,7 @@ rmpc_status rmpc_poll_completed(rmpc_ctx *ctx, int32_t max, uint64_t *tickets, r
         S->done.erase(it);
         ++n;
     }
+    S->n_ready.store((int64_t)S->done_order.size(), std::memory_order_release);
     *n_out = n;
     if (n == 0 && S->error != RMPC_OK) return fail(RMPC_E_STOPPED, "server stopped: " + S->error_msg);
     return RMPC_OK;
