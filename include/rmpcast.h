@@ -480,6 +480,7 @@ rmpc_status rmpc_rollout(rmpc_ctx *ctx, int32_t map_id, const double x0[3], cons
  *   sqdist_dev[nx * ny * nz]: device memory (x fastest, as the map), receives for every voxel
  *     the squared distance, in voxels, from its centre to the centre of the nearest occupied
  *     voxel (an integer; 0 on occupied voxels), or -1 everywhere when no voxel is occupied.
+ * Dense maps only.
  * Runs on hip_stream and waits for it.  Errors: RMPC_E_INVALID, RMPC_E_NOMAP, RMPC_E_HIP.
  */
 rmpc_status rmpc_edt(rmpc_ctx *ctx, int32_t map_id, int32_t *sqdist_dev, void *hip_stream);

@@ -16,78 +16,198 @@ namespace {
 
 constexpr int32_t kFar = 1 << 30;   // larger than any squared distance of an allowed grid
 
-// The x pass: one wave per row.  Per chunk of 64 voxels a ballot marks the occupied ones; the
-// nearest occupied voxel at or left of each lane is the highest set bit up to the lane (else
-// the last one of earlier chunks), found in a forward sweep over the chunks, and the nearest
-// at or right of it the lowest set bit from the lane on, in a backward sweep.  The row's
-// value is the square of the nearer of the two, kFar when the row has none.
+// The x pass: one wave per row of at most 64 chunks of 64 voxels (rows of up to 4,096, the
+// largest extent a map may have).  The row is read once, four chunks' loads in flight: per
+// chunk a ballot marks the occupied voxels and lane c keeps chunk c's mask.  Scans over the
+// lanes give each chunk the last occupied voxel before it and the first after it.  Then per
+// chunk the nearest occupied voxel at or left of each voxel is the highest set bit up to it
+// (else the one before the chunk), at or right of it the lowest set bit from it on (else the
+// one after), and the row's value, written once, is the square of the nearer of the two, kFar
+// when the row has none.
 template <int DT>
 __global__ void __launch_bounds__(256) edt_rows_kernel(MapView m, int32_t *g)
 {
+    constexpr int32_t kNone = 0x7fffffff;                 // no occupied voxel after
     const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (row >= (int64_t)m.ny * m.nz) return;             // the same for the whole wave
     using T = typename Voxel<DT>::T;
     const T *data = static_cast<const T *>(m.data);
     const int lane = threadIdx.x & 63;
     const int32_t nx = m.nx;
+    const int nch = (nx + 63) >> 6;
     const int64_t base = row * nx;
-    int32_t carry = -1;                                   // last occupied index of earlier chunks
-    for (int32_t c0 = 0; c0 < nx; c0 += 64) {
-        const int32_t i = c0 + lane;
-        const uint64_t mask = __ballot(i < nx && Voxel<DT>::occ(data[base + i]));
-        const uint64_t upto = lane == 63 ? mask : mask & ((2ull << lane) - 1ull);
-        if (i < nx) g[base + i] = upto ? c0 + 63 - __clzll(upto) : carry;
-        if (mask) carry = c0 + 63 - __clzll(mask);
+    uint64_t mine = 0;                                    // lane c: the mask of chunk c
+    for (int c0 = 0; c0 < nch; c0 += 4) {
+        bool o[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int32_t i = ((c0 + u) << 6) + lane;
+            o[u] = i < nx && Voxel<DT>::occ(data[base + i]);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint64_t mask = __ballot(o[u]);
+            mine = lane == c0 + u ? mask : mine;
+        }
     }
-    carry = -1;                                           // first occupied index of later chunks
-    for (int32_t c0 = ((nx - 1) / 64) * 64; c0 >= 0; c0 -= 64) {
-        const int32_t i = c0 + lane;
-        const uint64_t mask = __ballot(i < nx && Voxel<DT>::occ(data[base + i]));
+    // inclusive prefix max of the chunks' last occupied index, suffix min of their first
+    int32_t before = mine ? (lane << 6) + 63 - __clzll(mine) : -1;
+    int32_t after = mine ? (lane << 6) + __ffsll((unsigned long long)mine) - 1 : kNone;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t b = __shfl_up(before, o, 64), a = __shfl_down(after, o, 64);
+        if (lane >= o) before = max(before, b);
+        if (lane + o < 64) after = min(after, a);
+    }
+    // exclusive: chunks strictly before / after lane's chunk
+    int32_t lc_all = __shfl_up(before, 1, 64), rc_all = __shfl_down(after, 1, 64);
+    if (lane == 0) lc_all = -1;
+    if (lane == 63) rc_all = kNone;
+    for (int c = 0; c < nch; ++c) {
+        const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)mine, c);
+        const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(mine >> 32), c);
+        const uint64_t mask = (uint64_t)lo | ((uint64_t)hi << 32);
+        const int32_t lc = __builtin_amdgcn_readlane(lc_all, c), rc = __builtin_amdgcn_readlane(rc_all, c);
+        const int32_t i = (c << 6) + lane;
+        const uint64_t upto = lane == 63 ? mask : mask & ((2ull << lane) - 1ull);
         const uint64_t from = mask & (~0ull << lane);
-        const int32_t right = from ? c0 + __ffsll((unsigned long long)from) - 1 : carry;
+        const int32_t left = upto ? (c << 6) + 63 - __clzll(upto) : lc;
+        const int32_t right = from ? (c << 6) + __ffsll((unsigned long long)from) - 1 : rc;
         if (i < nx) {
-            const int32_t left = g[base + i];
             int32_t d = kFar;
             if (left >= 0) d = i - left;
-            if (right >= 0 && right - i < d) d = right - i;
+            if (right != kNone && right - i < d) d = right - i;
             g[base + i] = d >= kFar ? kFar : d * d;
         }
-        if (mask) carry = c0 + __ffsll((unsigned long long)mask) - 1;
     }
 }
 
-// The y and z passes: one block per line of len elements, `stride` apart; line l starts at
-// (l % nx) + nx ny (l / nx) for y and at l for z.  The line is staged in LDS and every element
-// takes min over j of line_j + (i - j)^2, searching outward from j = i and stopping once
-// (i - j)^2 alone reaches the best value found (every line_j is >= 0, so no farther j can be
-// smaller): the same minimum as the full scan.  The last pass writes -1 where nothing was found
-// (a grid without occupied voxels).
-__global__ void __launch_bounds__(256) edt_lines_kernel(int32_t *g, int32_t len, int64_t stride, int32_t nx,
-                                                        int64_t plane, int y_pass, int last_pass)
+// min over j of line[j] + (i - j)^2 for element i of a line of len values (each in [0, kFar]),
+// from best = line[i], going outward two distances per pass until d^2 reaches best.  Indices
+// are clamped at the line's ends instead of tested: a clamped candidate line[0] + d^2 (or
+// line[len - 1] + d^2) is no better than the same element's own candidate at its true
+// distance, which the search reaches first or which cannot beat best; candidates past the
+// stopping distance cannot beat best either, so the result is the exact minimum.  kFar + d^2
+// stays below 2^31 for lines of at most 2^15 elements.
+__device__ __forceinline__ int32_t line_min(const int32_t *line, int32_t len, int32_t i, int32_t best)
 {
-    extern __shared__ int32_t line[];
-    const int64_t l = blockIdx.x;
-    const int64_t base = y_pass ? (l % nx) + plane * (l / nx) : l;
-    int found = 0;
-    for (int32_t i = threadIdx.x; i < len; i += blockDim.x) {
-        const int32_t v = g[base + i * stride];
-        line[i] = v;
-        found |= v < kFar;
+    const int32_t last = len - 1;
+    int32_t d = 1, dd = 1;                                // dd = d^2
+    while (d < len && dd < best) {
+        const int32_t dd1 = dd + 2 * d + 1;               // (d + 1)^2
+        const int32_t a = line[max(i - d, 0)], b = line[min(i + d, last)];
+        const int32_t c = line[max(i - d - 1, 0)], e = line[min(i + d + 1, last)];
+        best = min(best, min(a, b) + dd);
+        best = min(best, min(c, e) + dd1);
+        dd = dd1 + 2 * d + 3;                             // (d + 2)^2
+        d += 2;
     }
-    // a line with nothing finite stays "far" (the search below would scan all of it per element)
-    if (!__syncthreads_or(found)) {
-        for (int32_t i = threadIdx.x; i < len; i += blockDim.x) g[base + i * stride] = last_pass ? -1 : kFar;
-        return;
-    }
-    for (int32_t i = threadIdx.x; i < len; i += blockDim.x) {
-        int32_t best = line[i];
-        for (int32_t d = 1; d < len && d * d < best; ++d) {
-            const int32_t lo = i - d, hi = i + d;
-            if (lo >= 0 && line[lo] < kFar && line[lo] + d * d < best) best = line[lo] + d * d;
-            if (hi < len && line[hi] < kFar && line[hi] + d * d < best) best = line[hi] + d * d;
+    return best;
+}
+
+// The y and z passes: one block per group of up to 2^wlog neighbouring lines (consecutive x at
+// one z for the y pass, at one y for the z pass), each of len elements `stride` apart.  Global
+// loads and stores go element by element across the group's lines, so that a wave covers runs
+// of consecutive x, eight per thread in flight; in LDS each line is contiguous (rows of len + 1
+// words: the transposing writes and reads hit distinct banks), and the search runs along a line
+// in consecutive lanes, whose distances are alike.  Every element takes min over j of
+// line_j + (i - j)^2, searching outward from j = i and stopping once (i - j)^2 alone reaches the
+// best value found (every line_j is >= 0, so no farther j can be smaller): the same minimum as
+// the full scan.  A line with nothing finite keeps "far" without a search; the last pass writes
+// -1 there (a grid without occupied voxels).
+__global__ void __launch_bounds__(256) edt_lines_kernel(int32_t *g, int32_t len, int64_t stride, int32_t nx,
+                                                        int32_t groups_x, int wlog, int64_t plane, int y_pass,
+                                                        int last_pass)
+{
+    constexpr int kUnroll = 8;
+    extern __shared__ int32_t lds[];                      // in[W][len + 1], res[W][len + 1], found[W]
+    const int W = 1 << wlog;
+    const int row = len + 1;
+    int32_t *res = lds + (size_t)W * row;
+    int32_t *found = res + (size_t)W * row;
+    const int64_t q = blockIdx.x / groups_x;              // z (y pass) or y (z pass)
+    const int32_t x0 = (int32_t)(blockIdx.x % groups_x) * W;
+    const int64_t base = x0 + (y_pass ? plane * q : (int64_t)nx * q);
+    const int nw = min(W, nx - x0);                       // lines of this group inside the grid
+    const int n = len * W;
+    if ((int)threadIdx.x < W) found[threadIdx.x] = 0;
+    __syncthreads();
+    for (int i0 = threadIdx.x; i0 < n; i0 += kUnroll * 256) {
+        int32_t v[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int idx = i0 + u * 256;
+            const int w = idx & (W - 1), i = idx >> wlog;
+            v[u] = idx < n && w < nw ? g[base + w + (int64_t)i * stride] : kFar;
         }
-        g[base + i * stride] = last_pass && best >= kFar ? -1 : best;
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int idx = i0 + u * 256;
+            const int w = idx & (W - 1), i = idx >> wlog;
+            if (idx < n) {
+                lds[w * row + i] = v[u];
+                if (v[u] < kFar) found[w] = 1;            // every writer stores the same value
+            }
+        }
     }
+    __syncthreads();
+    // line w, element i of the thread's first item; later items are 256 further in (w, i) order
+    int w = threadIdx.x / len, i = threadIdx.x - w * len;
+    for (; w < nw; ) {
+        const int32_t *line = lds + w * row;
+        int32_t best = line[i];
+        if (found[w]) best = line_min(line, len, i, best);
+        res[w * row + i] = last_pass && best >= kFar ? -1 : best;
+        i += 256;
+        if (i >= len) {
+            const int k = i / len;
+            w += k;
+            i -= k * len;
+        }
+    }
+    __syncthreads();
+    for (int i0 = threadIdx.x; i0 < n; i0 += kUnroll * 256) {
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int idx = i0 + u * 256;
+            const int ww = idx & (W - 1), ii = idx >> wlog;
+            if (idx < n && ww < nw) g[base + ww + (int64_t)ii * stride] = res[ww * row + ii];
+        }
+    }
+}
+
+// LDS a group of 2^wlog lines of len elements may take (both copies and the flags): at most
+// 26 KiB, so that six blocks (24 waves) share a CU for the latency of the searches' LDS reads
+// (8 lines per group at the paper map's 400-voxel lines); a single line may take up to 64 KiB.
+#ifndef EDT_GROUP_LDS
+#define EDT_GROUP_LDS (26 * 1024)
+#endif
+constexpr size_t kGroupLds = EDT_GROUP_LDS;
+constexpr size_t kLinesLds = 64 * 1024;
+
+size_t lines_lds(int32_t len, int wlog)
+{
+    return (2 * ((size_t)len + 1) + 1) * ((size_t)1 << wlog) * sizeof(int32_t);
+}
+
+// The widest group (at most 64 lines) that fits kGroupLds.
+int lines_wlog(int32_t len)
+{
+    int wlog = 6;
+    while (wlog > 0 && lines_lds(len, wlog) > kGroupLds) --wlog;
+    return wlog;
+}
+
+hipError_t launch_lines(int32_t *g, int32_t len, int64_t stride, int32_t nx, int64_t other, int64_t plane,
+                        int y_pass, int last_pass, hipStream_t s)
+{
+    const int wlog = lines_wlog(len);
+    const int32_t groups_x = (nx + (1 << wlog) - 1) >> wlog;
+    const size_t lds = lines_lds(len, wlog);
+    if (lds > kLinesLds) return hipErrorInvalidValue;     // a line longer than 8,190 voxels (uploads take 4,096)
+    edt_lines_kernel<<<(unsigned)(other * groups_x), 256, lds, s>>>(g, len, stride, nx, groups_x, wlog, plane, y_pass,
+                                                                    last_pass);
+    return hipGetLastError();
 }
 
 template <int DT>
@@ -95,11 +215,10 @@ hipError_t launch_edt_dt(const MapView &m, int32_t *out, hipStream_t s)
 {
     const int64_t rows = (int64_t)m.ny * m.nz, plane = (int64_t)m.nx * m.ny;
     edt_rows_kernel<DT><<<(unsigned)((rows + 3) / 4), 256, 0, s>>>(m, out);
-    edt_lines_kernel<<<(unsigned)((int64_t)m.nx * m.nz), 256, sizeof(int32_t) * (size_t)m.ny, s>>>(
-        out, m.ny, m.nx, m.nx, plane, 1, 0);
-    edt_lines_kernel<<<(unsigned)plane, 256, sizeof(int32_t) * (size_t)m.nz, s>>>(out, m.nz, plane, m.nx, plane, 0,
-                                                                                1);
-    return hipGetLastError();
+    if (hipError_t e = hipGetLastError()) return e;
+    // y: lines (x, z), elements nx apart; z: lines (x, y), elements nx ny apart
+    if (hipError_t e = launch_lines(out, m.ny, m.nx, m.nx, m.nz, plane, 1, 0, s)) return e;
+    return launch_lines(out, m.nz, plane, m.nx, m.ny, plane, 0, 1, s);
 }
 
 // Distance in metres at voxel (i, j, k), indices clamped into the grid; -1 when the grid has

@@ -37,7 +37,10 @@ def test_tiny_map_bitwise(ctx, tiny_map, enc):
     assert np.array_equal(g, o)
 
 
-@pytest.mark.parametrize("shape,p", [((37, 23, 51), 0.002), ((5, 300, 7), 0.01), ((64, 1, 130), 0.05)])
+# line groups of the y and z passes: 64 lines of 23 (one partial group), 32 of 300, 16 of 1,000
+# with a ragged last group (37 = 2 x 16 + 5), and single-element lines
+@pytest.mark.parametrize("shape,p", [((37, 23, 51), 0.002), ((5, 300, 7), 0.01), ((64, 1, 130), 0.05),
+                                     ((3, 1000, 37), 0.003), ((1000, 2, 70), 0.002)])
 def test_ragged_random_grids(ctx, shape, p):
     rng = np.random.default_rng(sum(shape))
     occ = rng.uniform(size=shape) < p
@@ -45,6 +48,17 @@ def test_ragged_random_grids(ctx, shape, p):
     t = np.where(occ, -0.05, 0.3).astype(np.float32)
     g = _gpu_edt(ctx, t, 0.1, "f32")
     assert np.array_equal(g, oracle.edt(oracle.OracleMap(t, 0.1, np.zeros(3), "f32")))
+
+
+def test_longest_lines(ctx):
+    """y and z lines of 4,096 voxels (the largest extent a map may have): two lines per group of
+    the y and z passes; every voxel against the oracle."""
+    rng = np.random.default_rng(7)
+    for shape in ((1, 4096, 3), (4096, 1, 3)):
+        t = np.where(rng.uniform(size=shape) < 0.001, -0.05, 0.3).astype(np.float32)
+        t.reshape(-1)[1234] = -0.05
+        g = _gpu_edt(ctx, t, 0.1, "f32")
+        assert np.array_equal(g, oracle.edt(oracle.OracleMap(t, 0.1, np.zeros(3), "f32"))), shape
 
 
 def test_empty_and_full(ctx):
