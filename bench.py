@@ -349,6 +349,8 @@ def sparse_bench(args):
     params = W.params("static", max_range=rmax)
     ctx = binding.Context(0, arena_bytes=(3 << 30) // 2)
     mid = ctx.upload_sparse(sm.coords, sm.values, sm.voxel_m, sm.origin_m, "f32")
+    over = {k: v for k, v in (("lookahead", args.lookahead), ("lane_target_log2", args.lane_target)) if v}
+    launch = ctx.config(binding.CONFIG_QUERY, **over)
     step = binding.PreparedQuery(ctx.ptr, mid, x, v, n_rays, params, stream=ctx.stream)
     for _ in range(args.warmup):
         step()
@@ -374,7 +376,8 @@ def sparse_bench(args):
            "config": {"workload": "160 m x 160 m world, 0.05 m voxels, ground + 1500 obstacles, sparse 8^3 blocks; "
                                   "65536 rays, 10 m",
                       "blocks": sm.n_blocks, "stored_voxels_occupied": round(sm.occupied_fraction(), 4),
-                      "mean_visits_per_ray": round(visits / n_rays, 2), "kernel_us": round(kern_s * 1e6, 2)},
+                      "mean_visits_per_ray": round(visits / n_rays, 2), "kernel_us": round(kern_s * 1e6, 2),
+                      "launch_lookahead": launch["lookahead"], "launch_lane_target_log2": launch["lane_target_log2"]},
            "roofline": {"bound": "hbm", "achieved": round(alg_bytes / kern_s / 1e9, 1), "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": round(alg_bytes / kern_s / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
                         "kernel": "sparse_rmp_kernel", "algorithmic_bytes_per_launch": alg_bytes}}

@@ -192,7 +192,9 @@ rmpc_status setup_sparse_query(rmpc_ctx *ctx, const MapEntry &me, const double x
     A.tmax_lo = (float)(tmax * (1.0 - 1e-6) - 2e-5);
     A.tmax_hi = (float)(tmax * (1.0 + 1e-6) + 2e-5);
     A.tmax_v = tmax;
-    A.segments = 1;
+    A.segments = segments_for(n_rays, tmax, cfg.lane_target_log2);
+    if ((long)A.n_list * A.segments > (long)rmpc::kMaxPartialSlots * 256)
+        return fail(RMPC_E_INVALID, "too many lanes for one launch");
     A.lookahead = cfg.lookahead;
     A.max_range = params->max_range_m;
     A.h = me.desc.voxel_m;

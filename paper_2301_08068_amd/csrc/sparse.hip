@@ -2,9 +2,11 @@
 // GPU hash of 8^3-voxel blocks allocated where the world has content; every voxel outside an
 // allocated block is free, and the world has no edge).
 //
-// One lane walks one ray with the exact 3-D DDA of the dense kernels (float32 crossing
-// parameters, float64 decisions inside the guard band, the hit distance from the entered
-// face in float64), at two levels:
+// S adjacent lanes walk the S segments of one ray (as in the dense kernel: segment k starts
+// at the voxel that holds the float64-located boundary near k max_range / S and ends at the
+// next one; the lowest segment with a hit owns the ray) with the exact 3-D DDA of the dense
+// kernels (float32 crossing parameters, float64 decisions inside the guard band, the hit
+// distance from the entered face in float64), at two levels:
 //   block level: the walk steps block by block (block faces are voxel faces, so it enters the
 //     blocks the voxel walk enters, in the same order).  A round plans K block steps and issues
 //     the K hash-table loads at once; the first planned block that is allocated and holds an
@@ -143,7 +145,11 @@ struct SWalk {
     int ax, ay, az;                   //   voxel level, at voxel (ax, ay, az)
     bool settled;                     // finishing at the voxel level near max_range
     bool tie, rtie;                   // near-ties at decisions taken, near-tie with max_range
-    bool ended, hit;
+    float t_hi;                       // the segment stops once the next crossing exceeds this
+    float t_lo;                       // crossings at or beyond this get the float64 range test
+    bool last;                        // the segment ending at max_range
+    bool done;                        // the segment's walk is over
+    bool ended, hit;                  // the ray's walk ends in this segment (hit or max_range)
     int fx, fy, fz;                   // last voxel entered (the hit voxel on a hit)
 };
 
@@ -210,20 +216,21 @@ __device__ __forceinline__ void voxel_run(const RayArgs &A, SWalk &w, const RayF
     if (w.pending) {
         w.pending = false;
         if (mask_bit(layer, vx & 7, vy & 7)) {
-            w.hit = w.ended = true;
+            w.hit = w.ended = w.done = true;
             w.fx = vx; w.fy = vy; w.fz = vz;
             return;
         }
     }
     const int sx = R.rx > 0.0f ? 1 : -1, sy = R.ry > 0.0f ? 1 : -1, sz = R.rz > 0.0f ? 1 : -1;
-    const float t_lo = A.tmax_lo, t_hi = A.tmax_hi;
+    const float t_lo = w.t_lo, t_hi = w.t_hi;
     // every step moves one face ahead, so the nearest crossing passes t_hi within
     // 2 (t_hi + 8) steps; the bound only guards the loop
     const int max_steps = 2 * (int)t_hi + 64;
     for (int it = 0; it < max_steps; ++it) {
         int a = step_axis64(R, w.Bx, w.By, w.Bz, w.Tx, w.Ty, w.Tz, w.tie);
         const float ta = pick3(a, w.Tx, w.Ty, w.Tz);
-        if (ta >= t_lo) {
+        if (ta > t_hi || ta >= t_lo) {
+            // past the segment's end, or (the last segment) near max_range
             bool stop = ta > t_hi;
             if (!stop) {
                 // range test (closed interval) in float64 inside the guard band
@@ -235,7 +242,8 @@ __device__ __forceinline__ void voxel_run(const RayArgs &A, SWalk &w, const RayF
                 if (fabs(dist - A.max_range) < 1e-5 * A.h) w.rtie = true;
             }
             if (stop) {
-                w.ended = true;
+                w.done = true;
+                w.ended = w.last;
                 w.fx = vx; w.fy = vy; w.fz = vz;
                 return;
             }
@@ -280,12 +288,13 @@ __device__ __forceinline__ void voxel_run(const RayArgs &A, SWalk &w, const RayF
             layer = layer_word(w.m, vz & 7);
         }
         if (mask_bit(layer, vx & 7, vy & 7)) {
-            w.hit = w.ended = true;
+            w.hit = w.ended = w.done = true;
             w.fx = vx; w.fy = vy; w.fz = vz;
             return;
         }
     }
-    w.ended = true;                   // not reached: the range ends the walk first
+    w.done = true;                    // not reached: the range ends the walk first
+    w.ended = w.last;
     w.fx = vx; w.fy = vy; w.fz = vz;
 }
 
@@ -325,7 +334,8 @@ __device__ __forceinline__ void block_round(const RayArgs &A, SWalk &w, const Ra
     const float gsx = R.gsx, gsy = R.gsy, gsz = R.gsz, arx = R.arx, ary = R.ary, arz = R.arz;
     const float L = (float)(1 << kBlockLog2);
     const int sx = R.rx > 0.0f ? 1 : -1, sy = R.ry > 0.0f ? 1 : -1, sz = R.rz > 0.0f ? 1 : -1;
-    const float t_lo = A.tmax_lo;
+    const float t_lo = w.t_lo, t_hi = w.t_hi;
+    const float t_stop = fminf(t_lo, next_up(t_hi));      // a step is planned iff its crossing is below
     float Bx = w.Bx, By = w.By, Bz = w.Bz, Tx = w.Tx, Ty = w.Ty, Tz = w.Tz;
     int cx = w.cbx, cy = w.cby, cz = w.cbz;
     Entry e[K];
@@ -337,7 +347,7 @@ __device__ __forceinline__ void block_round(const RayArgs &A, SWalk &w, const Ra
         const float t1 = __builtin_amdgcn_fmed3f(Tx, fminf(Ty, Tz), -kInf);
         const float t2 = __builtin_amdgcn_fmed3f(Tx, Ty, Tz);
         const bool bx = Tx == t1, by = !bx & (Ty == t1), bz = !bx & !by;
-        going = going & (t1 < t_lo) & (t2 - t1 >= 2e-5f + 1e-6f * t2);
+        going = going & (t1 < t_stop) & (t2 - t1 >= 2e-5f + 1e-6f * t2);
         Bx = bx ? Bx + L : Bx;
         By = by ? By + L : By;
         Bz = bz ? Bz + L : Bz;
@@ -413,17 +423,27 @@ __device__ __forceinline__ void block_round(const RayArgs &A, SWalk &w, const Ra
         return;
     }
     if (nplan == K) return;
-    // the plan ended at step nplan: the range band, or a near-tie
+    // the plan ended at step nplan: the range band, the segment's end, or a near-tie
     const float t1 = __builtin_amdgcn_fmed3f(Tx, fminf(Ty, Tz), -kInf);
     if (t1 >= t_lo) {
         settle(A, w, R);
         return;
     }
+    if (t1 > t_hi) {
+        // the segment ends inside this free block: nothing before its end is occupied
+        w.done = true;
+        return;
+    }
     bool tie = false;
     const int a = step_axis64(R, Bx, By, Bz, Tx, Ty, Tz, tie);
-    if (pick3(a, Tx, Ty, Tz) >= t_lo) {
+    const float ta = pick3(a, Tx, Ty, Tz);
+    if (ta >= t_lo) {
         // the step the float64 decision takes reaches the range band
         settle(A, w, R);
+        return;
+    }
+    if (ta > t_hi) {
+        w.done = true;
         return;
     }
     w.tie = w.tie || tie;
@@ -438,52 +458,113 @@ __device__ __forceinline__ void block_round(const RayArgs &A, SWalk &w, const Ra
     if (occ) descend(A, w, R, w.cbx, w.cby, w.cbz, a, slot);
 }
 
+// Per-ray outcome of a group of S lanes (valid in the lane that reports the ray: its hit
+// segment, else segment 0), and each lane's share of the visit count.
 struct SOut {
+    bool report;
     bool hit;
     double d;
     uint32_t flags;
-    int visits;
+    int visits_lane;                  // the ray's visits in the lane whose segment ended it, else 0
     int hit_slot, hit_local;          // debug
 };
 
-// Walk one ray from the start voxel; the start block (slot0, occupancy m0) is shared by all.
+// Walk segment seg of S of one ray; every lane of the wave must call this.  The start block
+// (slot0, whether it holds an occupied voxel, its occupancy m0) is shared by every segment 0.
 template <int K>
-__device__ __forceinline__ SOut sparse_trace(const RayArgs &A, bool valid, float rx, float ry, float rz, int slot0,
-                                             bool occ0, const uint64_t (&m0)[kLayers])
+__device__ __forceinline__ SOut sparse_trace(const RayArgs &A, bool valid, int seg, int S, float rx, float ry, float rz,
+                                             int slot0, bool occ0, const uint64_t (&m0)[kLayers])
 {
     const RayF R = make_ray(A, rx, ry, rz);
+    const double tmax = A.tmax_v;
+    bool active = valid;
+    // segment start: the start voxel, or the voxel that holds the boundary near seg tmax / S
+    int ux = A.v0[0], uy = A.v0[1], uz = A.v0[2];
+    if (seg != 0) {
+        bool ok;
+        seg_boundary(tmax * seg / S, R.gx, R.gy, R.gz, rx, ry, rz, ux, uy, uz, ok);
+        if (!ok) {
+            active = false;                               // an empty segment
+            ux = A.v0[0]; uy = A.v0[1]; uz = A.v0[2];
+        }
+    }
     SWalk w;
+    // segment end: the next boundary that exists, else max_range
+    w.last = true;
+    w.t_hi = A.tmax_hi;
+    w.t_lo = A.tmax_lo;
+    for (int e = seg + 1; e < S && w.last; ++e) {
+        int bx, by, bz;
+        bool ok;
+        const double te = seg_boundary(tmax * e / S, R.gx, R.gy, R.gz, rx, ry, rz, bx, by, bz, ok);
+        if (ok) {
+            w.last = false;
+            w.t_hi = (float)te;       // no crossing lies within the segment margin of te
+            w.t_lo = kInf;
+        }
+    }
+    // the start block: a later segment looks its own up (its start voxel was tested by the
+    // segment before, so it is not tested again)
+    int slot = slot0;
+    bool occ = occ0;
+    uint64_t m[kLayers];
+#pragma unroll
+    for (int k = 0; k < kLayers; ++k) m[k] = m0[k];
+    const int b0x = ux >> kBlockLog2, b0y = uy >> kBlockLog2, b0z = uz >> kBlockLog2;
+    if (seg != 0) {
+        lookup(A.sp, b0x, b0y, b0z, slot, occ);
+        load_mask(A.sp, occ ? slot : -1, m);
+    }
     w.tie = w.rtie = false;
+    w.done = !active;
     w.ended = w.hit = false;
     w.settled = false;
     w.anchored = true;
-    w.ax = A.v0[0]; w.ay = A.v0[1]; w.az = A.v0[2];
-    w.fx = w.ax; w.fy = w.ay; w.fz = w.az;
-    const int b0x = A.v0[0] >> kBlockLog2, b0y = A.v0[1] >> kBlockLog2, b0z = A.v0[2] >> kBlockLog2;
+    w.ax = ux; w.ay = uy; w.az = uz;
+    w.fx = ux; w.fy = uy; w.fz = uz;
     w.cbx = b0x; w.cby = b0y; w.cbz = b0z;
     w.ent_a = -1;
-    w.slot = occ0 ? slot0 : -1;
+    w.slot = occ ? slot : -1;
     w.pending = false;
 #pragma unroll
-    for (int k = 0; k < kLayers; ++k) w.m[k] = m0[k];
-    if (occ0) s_enter(w, R, 0, A.v0[0], A.v0[1], A.v0[2]);
+    for (int k = 0; k < kLayers; ++k) w.m[k] = m[k];
+    if (occ) s_enter(w, R, 0, ux, uy, uz);
     else s_enter(w, R, kBlockLog2, b0x, b0y, b0z);
-    bool active = valid;
-    while (active) {
-        if (w.blk) block_round<K>(A, w, R);
-        else voxel_run(A, w, R);
-        active = !w.ended;
+
+    const int lane = threadIdx.x & (kWave - 1);
+    const int base = lane & ~(S - 1);
+    const uint64_t seg_bits = (1ull << S) - 1ull;        // S <= 16
+    const uint64_t lower = ((1ull << seg) - 1ull) << base;
+    for (;;) {
+        const uint64_t hm = __ballot(w.hit);
+        if (hm & lower) active = false;                  // a lower segment already hit
+        if (!__any(active)) break;
+        if (active) {
+            if (w.blk) block_round<K>(A, w, R);
+            else voxel_run(A, w, R);
+            active = !w.done;
+        }
     }
+    // combine the group: the lowest segment with a hit owns the ray; the lowest segment whose
+    // walk ended holds the ray's last voxel
+    const uint64_t gh = (__ballot(w.hit) >> base) & seg_bits;
+    const int h = gh ? __ffsll((unsigned long long)gh) - 1 : S;
+    const uint64_t ge = (__ballot(valid && w.ended) >> base) & seg_bits;
+    const int t = ge ? __ffsll((unsigned long long)ge) - 1 : S;
+    const bool keep = valid && seg <= h;
+    const uint64_t tm = (__ballot(keep && w.tie) >> base) & seg_bits;
+    const uint64_t rm = (__ballot(keep && w.rtie) >> base) & seg_bits;
     SOut o;
-    o.hit = valid && w.hit;
-    o.visits = valid ? 1 + abs(w.fx - A.v0[0]) + abs(w.fy - A.v0[1]) + abs(w.fz - A.v0[2]) : 0;
+    o.report = valid && seg == (h < S ? h : 0);
+    o.hit = w.hit && seg == h;
+    o.visits_lane = valid && seg == t ? 1 + abs(w.fx - A.v0[0]) + abs(w.fy - A.v0[1]) + abs(w.fz - A.v0[2]) : 0;
     double d = __builtin_huge_val();
     if (o.hit) {
         const int a = w.ent_a;
         d = (a == 0 ? entry64(w.fx, R.gx, R.rx) : (a == 1 ? entry64(w.fy, R.gy, R.ry) : entry64(w.fz, R.gz, R.rz))) * A.h;
     }
     o.d = d;
-    o.flags = A.start_flags | (w.tie ? kRayTie : 0u) | (w.rtie ? kRayRangeTie : 0u);
+    o.flags = A.start_flags | (tm ? kRayTie : 0u) | (rm ? kRayRangeTie : 0u);
     o.hit_slot = o.hit ? w.slot : -1;
     o.hit_local = (w.fx & 7) + 8 * (w.fy & 7) + 64 * (w.fz & 7);
     return o;
@@ -507,23 +588,25 @@ __global__ void __launch_bounds__(kBlock, 2) sparse_rmp_kernel(RayArgs A)
     bool occ0;
     uint64_t m0[kLayers];
     const bool in_coll = start_block(A, slot0, occ0, m0);
+    const int S = A.segments;
     const int p = tile * kBlock + threadIdx.x;
-    const int j = p < A.n_list ? p : 0;
+    const int j = p < A.n_list * S ? p / S : 0;
+    const int seg = p & (S - 1);
     const float4 rr = load_ray(A.rays, j);
-    const bool valid = p < A.n_list && __float_as_int(rr.w) < A.n_rays;
+    const bool valid = p < A.n_list * S && __float_as_int(rr.w) < A.n_rays;
     Acc acc;
     acc.zero();
     if (in_coll) {
-        if (valid) {
+        if (valid && seg == 0) {
             acc.visits = 1;
             acc.n_hit = 1;
             acc.n_contrib = contributes(A, rr.x, rr.y, rr.z, 0.0);
             policy_accumulate(A.pol, rr.x, rr.y, rr.z, 0.0f, acc);
         }
     } else {
-        const SOut o = sparse_trace<K>(A, valid, rr.x, rr.y, rr.z, slot0, occ0, m0);
-        acc.visits = o.visits;
-        if (valid) {
+        const SOut o = sparse_trace<K>(A, valid, seg, S, rr.x, rr.y, rr.z, slot0, occ0, m0);
+        acc.visits = o.visits_lane;
+        if (o.report) {
             acc.n_tie = (o.flags & kRayTie) != 0;
             if (o.hit) {
                 acc.n_hit = 1;
@@ -544,13 +627,15 @@ __global__ void __launch_bounds__(kBlock, 2) sparse_trace_kernel(RayArgs A)
     bool occ0;
     uint64_t m0[kLayers];
     const bool in_coll = start_block(A, slot0, occ0, m0);
+    const int S = A.segments;
     const int p = blockIdx.x * kBlock + threadIdx.x;
-    const int j = p < A.n_list ? p : 0;
+    const int j = p < A.n_list * S ? p / S : 0;
+    const int seg = p & (S - 1);
     const float4 rr = load_ray(A.rays, j);
     const int i = __float_as_int(rr.w);
-    const bool valid = p < A.n_list && i < A.n_rays;
+    const bool valid = p < A.n_list * S && i < A.n_rays;
     if (in_coll) {
-        if (valid) {
+        if (valid && seg == 0) {
             A.dbg_hit[i] = slot0 * kBlockVoxels + (A.v0[0] & 7) + 8 * (A.v0[1] & 7) + 64 * (A.v0[2] & 7);
             A.dbg_dist[i] = 0.0;
             A.dbg_flags[i] = (uint8_t)(A.start_flags | kRayInCollision);
@@ -558,12 +643,15 @@ __global__ void __launch_bounds__(kBlock, 2) sparse_trace_kernel(RayArgs A)
         }
         return;
     }
-    const SOut o = sparse_trace<K>(A, valid, rr.x, rr.y, rr.z, slot0, occ0, m0);
-    if (valid) {
+    const SOut o = sparse_trace<K>(A, valid, seg, S, rr.x, rr.y, rr.z, slot0, occ0, m0);
+    // the ray's visit count is the sum over its group
+    int v = o.visits_lane;
+    for (int off = 1; off < S; off <<= 1) v += __shfl_xor(v, off, kWave);
+    if (o.report) {
         A.dbg_hit[i] = o.hit ? o.hit_slot * kBlockVoxels + o.hit_local : -1;
         A.dbg_dist[i] = o.d;
         A.dbg_flags[i] = (uint8_t)o.flags;
-        if (A.dbg_visits) A.dbg_visits[i] = o.visits;
+        if (A.dbg_visits) A.dbg_visits[i] = v;
     }
 }
 
@@ -595,7 +683,7 @@ __global__ void sparse_flag_kernel(SparseView v, HashEntry *table)
 template <int K>
 hipError_t launch_sparse_k(const RayArgs &A, hipStream_t s, bool debug, hipEvent_t e0, hipEvent_t e1)
 {
-    const dim3 g((A.n_list + kBlock - 1) / kBlock), blk(kBlock);
+    const dim3 g((A.n_list * A.segments + kBlock - 1) / kBlock), blk(kBlock);
     if (debug) {
         sparse_trace_kernel<K><<<g, blk, 0, s>>>(A);
     } else if (e0) {

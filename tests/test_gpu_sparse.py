@@ -169,6 +169,38 @@ def world():
     return W.sparse_world(20)
 
 
+@pytest.mark.parametrize("lane_target", [10, 19, 20])
+def test_sparse_world_segments(ctx, world, lane_target):
+    """The world's first state at other segment counts per ray (1, 4 and 8 lanes per ray at
+    65,536 rays): every ray and the query sums against the oracle, as at the default (2)."""
+    from paper_2301_08068_amd import binding
+    sm = world
+    mid = ctx.upload_sparse(sm.coords, sm.values, sm.voxel_m, sm.origin_m, "f32")
+    old = ctx.config(binding.CONFIG_QUERY)
+    dirs = oracle.directions(65536)
+    try:
+        ctx.config(binding.CONFIG_QUERY, lane_target_log2=lane_target)
+        x, v = W.sparse_free_state(sm, 702)
+        x = sm.origin_m + np.round((x - sm.origin_m) / sm.voxel_m * 1024.0) / 1024.0 * sm.voxel_m
+        g = ((x - sm.origin_m) / sm.voxel_m).astype(np.float32)
+        reach = int(np.ceil(P_PAPER["max_range"] / sm.voxel_m)) + 16
+        lo = (np.floor((g.astype(np.float64) - reach) / 8) * 8).astype(np.int64)
+        hi = (np.ceil((g.astype(np.float64) + reach) / 8) * 8).astype(np.int64)
+        dense, o_dense = sm.dense_crop(lo, hi)
+        om = oracle.OracleMap(dense, sm.voxel_m, o_dense, "f32")
+        t = ctx.trace(mid, x, 65536, P_PAPER)
+        o = oracle.trace(om, _dense_start(sm, x, lo), dirs, P_PAPER["max_range"], nthreads=8)
+        _compare(t, o, sm, lo, dense.shape[::-1], f"world lane target {lane_target}")
+        q = ctx.query(mid, x, v, 65536, P_PAPER)
+        oq = oracle.combine(P_PAPER, dirs, o["d"], o["hit"], v)
+        oq["visits"] = int(o["visits"].sum())
+        oq["n_tie"] = int(np.count_nonzero(o["flags"] & oracle.TIE))
+        compare_query(q, oq, f"world query lane target {lane_target}")
+    finally:
+        ctx.config(binding.CONFIG_QUERY, **old)
+        ctx.release(mid)
+
+
 def test_sparse_world_65536(ctx, world):
     """The outdoor-sized world of the sparse bench line (negative block coordinates, ~0.5 M
     blocks), 65,536 rays from two states with a 10 m range: every ray against the oracle on a
