@@ -350,7 +350,7 @@ def sparse_bench(args):
     ctx = binding.Context(0, arena_bytes=(3 << 30) // 2)
     mid = ctx.upload_sparse(sm.coords, sm.values, sm.voxel_m, sm.origin_m, "f32")
     over = {k: v for k, v in (("lookahead", args.lookahead), ("lane_target_log2", args.lane_target)) if v}
-    launch = ctx.config(binding.CONFIG_QUERY, **over)
+    launch = ctx.config(binding.CONFIG_SPARSE, **over)
     step = binding.PreparedQuery(ctx.ptr, mid, x, v, n_rays, params, stream=ctx.stream)
     for _ in range(args.warmup):
         step()

@@ -276,6 +276,8 @@ typedef struct {
  * the lookahead and the segmentation (they report near-ties at the decisions the walk takes). */
 #define RMPC_CONFIG_QUERY 0     /* rmpc_query and rmpc_trace_debug */
 #define RMPC_CONFIG_BATCH 1     /* rmpc_query_batch */
+#define RMPC_CONFIG_SPARSE 2    /* rmpc_query and rmpc_trace_debug on sparse maps (blocks_per_cu and
+                                   use_graph unused) */
 typedef struct {
     int32_t lookahead;          /* steps (voxels, free bricks or free cells) planned per
                                    round: 4, 8 or 16 */
@@ -299,8 +301,9 @@ rmpc_status rmpc_query_batch(rmpc_ctx *ctx, const rmpc_query_desc *q, int32_t n,
                              const rmpc_params *map_params, const rmpc_params *scan_params,
                              void *hip_stream, rmpc_result *out);
 
-/* rmpc_config_set / _get -- the launch configuration of single queries (which =
- * RMPC_CONFIG_QUERY) or of batches (RMPC_CONFIG_BATCH).  Errors: RMPC_E_INVALID. */
+/* rmpc_config_set / _get -- the launch configuration of single queries on dense maps (which =
+ * RMPC_CONFIG_QUERY), of batches (RMPC_CONFIG_BATCH) or of single queries on sparse maps
+ * (RMPC_CONFIG_SPARSE).  Errors: RMPC_E_INVALID. */
 rmpc_status rmpc_config_set(rmpc_ctx *ctx, int32_t which, const rmpc_launch_config *cfg);
 rmpc_status rmpc_config_get(rmpc_ctx *ctx, int32_t which, rmpc_launch_config *cfg);
 

@@ -59,7 +59,7 @@ class LaunchConfig(C.Structure):
 
 
 KIND_MAP, KIND_SCAN = 0, 1
-CONFIG_QUERY, CONFIG_BATCH = 0, 1
+CONFIG_QUERY, CONFIG_BATCH, CONFIG_SPARSE = 0, 1, 2
 
 
 class Request(C.Structure):

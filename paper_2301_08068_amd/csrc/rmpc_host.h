@@ -91,7 +91,7 @@ struct rmpc_ctx {
     uint64_t seq;
     std::map<int32_t, rmpc_host::MapEntry> maps;
     int32_t next_map_id;
-    rmpc_launch_config cfg[2];  // RMPC_CONFIG_QUERY, RMPC_CONFIG_BATCH
+    rmpc_launch_config cfg[3];  // RMPC_CONFIG_QUERY, RMPC_CONFIG_BATCH, RMPC_CONFIG_SPARSE
     int cu_count;
     rmpc_host::LaunchSlot batch;          // rmpc_query_batch (allocated on first use)
     hipEvent_t ev_dep;

@@ -206,8 +206,9 @@ __device__ __forceinline__ void to_voxel_level(SWalk &w, const RayF &R, int cx, 
     w.pending = pending;
 }
 
-// Voxel-level walk from the current voxel: tests the block's occupancy bits and crosses into
-// further blocks until a hit, the end of the range, or (not settled) a block that is free.
+// Voxel-level walk from the current voxel: tests the block's occupancy bits until a hit, the
+// end of the segment or range, or a block face; a crossed face's block is looked up, and the
+// walk goes on at the block level (a free block, not settled) or in that block's voxels.
 __device__ __forceinline__ void voxel_run(const RayArgs &A, SWalk &w, const RayF &R)
 {
     const SparseView &S = A.sp;
@@ -226,6 +227,7 @@ __device__ __forceinline__ void voxel_run(const RayArgs &A, SWalk &w, const RayF
     // every step moves one face ahead, so the nearest crossing passes t_hi within
     // 2 (t_hi + 8) steps; the bound only guards the loop
     const int max_steps = 2 * (int)t_hi + 64;
+    bool crossed = false;
     for (int it = 0; it < max_steps; ++it) {
         int a = step_axis64(R, w.Bx, w.By, w.Bz, w.Tx, w.Ty, w.Tz, w.tie);
         const float ta = pick3(a, w.Tx, w.Ty, w.Tz);
@@ -268,34 +270,41 @@ __device__ __forceinline__ void voxel_run(const RayArgs &A, SWalk &w, const RayF
         }
         w.ent_a = a;
         if ((face & 7) == 0) {
-            // into the neighbouring block along a
-            const int cx = w.cbx + (a == 0 ? sx : 0), cy = w.cby + (a == 1 ? sy : 0), cz = w.cbz + (a == 2 ? sz : 0);
-            int slot;
-            bool occ;
-            lookup(S, cx, cy, cz, slot, occ);
-            w.cbx = cx; w.cby = cy; w.cbz = cz;
-            if (!occ && !w.settled) {
-                // a free block: on at the block level, anchored at its entry voxel
-                s_enter(w, R, kBlockLog2, cx, cy, cz);
-                w.anchored = true;
-                w.ax = vx; w.ay = vy; w.az = vz;
-                return;
-            }
-            w.slot = slot;
-            load_mask(S, occ ? slot : -1, w.m);
-            layer = layer_word(w.m, vz & 7);
-        } else if (a == 2) {
-            layer = layer_word(w.m, vz & 7);
+            crossed = true;
+            break;
         }
+        if (a == 2) layer = layer_word(w.m, vz & 7);
         if (mask_bit(layer, vx & 7, vy & 7)) {
             w.hit = w.ended = w.done = true;
             w.fx = vx; w.fy = vy; w.fz = vz;
             return;
         }
     }
-    w.done = true;                    // not reached: the range ends the walk first
-    w.ended = w.last;
-    w.fx = vx; w.fy = vy; w.fz = vz;
+    if (!crossed) {
+        w.done = true;                // not reached: the range ends the walk first
+        w.ended = w.last;
+        w.fx = vx; w.fy = vy; w.fz = vz;
+        return;
+    }
+    // into the neighbouring block along the last step's axis.  Looked up here, after the step
+    // loop, so that the lanes of a wave that cross block faces wait for their table and mask
+    // loads together rather than one crossing at a time.
+    const int a = w.ent_a;
+    const int cx = w.cbx + (a == 0 ? sx : 0), cy = w.cby + (a == 1 ? sy : 0), cz = w.cbz + (a == 2 ? sz : 0);
+    int slot;
+    bool occ;
+    lookup(S, cx, cy, cz, slot, occ);
+    w.cbx = cx; w.cby = cy; w.cbz = cz;
+    if (!occ && !w.settled) {
+        // a free block: on at the block level, anchored at its entry voxel
+        s_enter(w, R, kBlockLog2, cx, cy, cz);
+        w.anchored = true;
+        w.ax = vx; w.ay = vy; w.az = vz;
+        return;
+    }
+    w.slot = slot;
+    load_mask(S, occ ? slot : -1, w.m);
+    w.pending = true;                 // the next run tests the voxel entered
 }
 
 // The current free block's voxels, from the voxel the walk entered it at, to the end of the
@@ -469,13 +478,13 @@ struct SOut {
     int hit_slot, hit_local;          // debug
 };
 
-// Walk segment seg of S of one ray; every lane of the wave must call this.  The start block
-// (slot0, whether it holds an occupied voxel, its occupancy m0) is shared by every segment 0.
-template <int K>
-__device__ __forceinline__ SOut sparse_trace(const RayArgs &A, bool valid, int seg, int S, float rx, float ry, float rz,
-                                             int slot0, bool occ0, const uint64_t (&m0)[kLayers])
+// Set up segment seg of S of a ray: its start voxel (and block), its end, and its start level.
+// Returns false for an empty segment.  The start block (slot0, whether it holds an occupied
+// voxel, its occupancy m0) is shared by every segment 0.
+__device__ __forceinline__ bool sparse_segment(const RayArgs &A, bool valid, int seg, int S, const RayF &R, int slot0,
+                                               bool occ0, const uint64_t (&m0)[kLayers], SWalk &w)
 {
-    const RayF R = make_ray(A, rx, ry, rz);
+    const float rx = R.rx, ry = R.ry, rz = R.rz;
     const double tmax = A.tmax_v;
     bool active = valid;
     // segment start: the start voxel, or the voxel that holds the boundary near seg tmax / S
@@ -488,7 +497,6 @@ __device__ __forceinline__ SOut sparse_trace(const RayArgs &A, bool valid, int s
             ux = A.v0[0]; uy = A.v0[1]; uz = A.v0[2];
         }
     }
-    SWalk w;
     // segment end: the next boundary that exists, else max_range
     w.last = true;
     w.t_hi = A.tmax_hi;
@@ -530,7 +538,18 @@ __device__ __forceinline__ SOut sparse_trace(const RayArgs &A, bool valid, int s
     for (int k = 0; k < kLayers; ++k) w.m[k] = m[k];
     if (occ) s_enter(w, R, 0, ux, uy, uz);
     else s_enter(w, R, kBlockLog2, b0x, b0y, b0z);
+    return active;
+}
 
+// Walk segment seg of S of one ray and combine the segments of the ray (the group of S
+// adjacent lanes); every lane of the wave must call this.
+template <int K>
+__device__ __forceinline__ SOut sparse_trace(const RayArgs &A, bool valid, int seg, int S, float rx, float ry, float rz,
+                                             int slot0, bool occ0, const uint64_t (&m0)[kLayers])
+{
+    const RayF R = make_ray(A, rx, ry, rz);
+    SWalk w;
+    bool active = sparse_segment(A, valid, seg, S, R, slot0, occ0, m0, w);
     const int lane = threadIdx.x & (kWave - 1);
     const int base = lane & ~(S - 1);
     const uint64_t seg_bits = (1ull << S) - 1ull;        // S <= 16

@@ -169,17 +169,17 @@ def world():
     return W.sparse_world(20)
 
 
-@pytest.mark.parametrize("lane_target", [10, 19, 20])
+@pytest.mark.parametrize("lane_target", [10, 17, 19, 20])
 def test_sparse_world_segments(ctx, world, lane_target):
-    """The world's first state at other segment counts per ray (1, 4 and 8 lanes per ray at
-    65,536 rays): every ray and the query sums against the oracle, as at the default (2)."""
+    """The world at other segment counts per ray (1, 2, 8 and 16 lanes per ray at 65,536 rays;
+    the default is 4): every ray and the query sums against the oracle."""
     from paper_2301_08068_amd import binding
     sm = world
     mid = ctx.upload_sparse(sm.coords, sm.values, sm.voxel_m, sm.origin_m, "f32")
-    old = ctx.config(binding.CONFIG_QUERY)
+    old = ctx.config(binding.CONFIG_SPARSE)
     dirs = oracle.directions(65536)
     try:
-        ctx.config(binding.CONFIG_QUERY, lane_target_log2=lane_target)
+        ctx.config(binding.CONFIG_SPARSE, lane_target_log2=lane_target)
         x, v = W.sparse_free_state(sm, 702)
         x = sm.origin_m + np.round((x - sm.origin_m) / sm.voxel_m * 1024.0) / 1024.0 * sm.voxel_m
         g = ((x - sm.origin_m) / sm.voxel_m).astype(np.float32)
@@ -197,7 +197,7 @@ def test_sparse_world_segments(ctx, world, lane_target):
         oq["n_tie"] = int(np.count_nonzero(o["flags"] & oracle.TIE))
         compare_query(q, oq, f"world query lane target {lane_target}")
     finally:
-        ctx.config(binding.CONFIG_QUERY, **old)
+        ctx.config(binding.CONFIG_SPARSE, **old)
         ctx.release(mid)
 
 
