@@ -322,6 +322,23 @@ class PreparedQuery:
         return self.result
 
 
+class PreparedScan:
+    """rmpc_scan_query with its arguments marshalled once (for loops that repeat one frame)."""
+
+    def __init__(self, ctx: int, points_ptr: int, n_points: int, v, params: Dict[str, float], stream=None):
+        self._args = (C.c_void_p(ctx), C.c_void_p(points_ptr), int(n_points), _d3(v),
+                      C.byref(params_struct(params)), C.c_void_p(_stream_ptr(stream)))
+        self.result = Result()
+        self._out = C.byref(self.result)
+        self._fn = _lib.rmpc_scan_query
+
+    def __call__(self) -> Result:
+        st = self._fn(*self._args, self._out)
+        if st != RMPC_OK:
+            _check(st, "rmpc_scan_query")
+        return self.result
+
+
 def rmpc_scan_query(ctx: int, points_ptr: int, n_points: int, v, params: Dict[str, float],
                     stream=None) -> Dict:
     r = Result()
