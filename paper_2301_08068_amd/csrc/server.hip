@@ -28,6 +28,7 @@ namespace {
 constexpr int kMaxSlots = 8;
 constexpr int kDefaultPending = 65536;
 constexpr double kLaunchTimeoutS = 60.0;
+constexpr std::chrono::microseconds kIdleWatch(1000);   // queue watch before the server thread sleeps
 
 // A request between rmpc_submit and its launch.
 struct Req {
@@ -218,8 +219,17 @@ void server_loop(rmpc_ctx *ctx, ServerState *S)
         }
         if (!in_flight) {
             if (S->stop && S->pending.empty()) return;
-            // nothing running: sleep until a request arrives or stop is asked
-            if (S->pending.empty()) S->cv.wait(lk, [S] { return S->stop || !S->pending.empty(); });
+            if (S->pending.empty()) {
+                // nothing running: watch the queue for a while, then sleep until a request
+                // arrives or stop is asked (at steady request rates the next request comes
+                // within the watch, and a sleeping thread can take milliseconds to wake)
+                lk.unlock();
+                const Clock::time_point t_idle = Clock::now();
+                while (S->n_pending.load(std::memory_order_acquire) == 0 && Clock::now() - t_idle < kIdleWatch)
+                    __builtin_ia32_pause();
+                lk.lock();
+                S->cv.wait(lk, [S] { return S->stop || !S->pending.empty(); });
+            }
             continue;
         }
         lk.unlock();
