@@ -173,9 +173,10 @@ typedef struct {
  * The library keeps the values, a 512-bit occupancy mask per block and an open-addressed hash
  * table (a power of two of at least 2 n_blocks entries of 16 bytes, at least 1024) from block
  * coordinates to slots: 16 capacity + 64 n_blocks + 512 elem_bytes n_blocks arena bytes.
- * rmpc_query and rmpc_trace_debug accept sparse maps (one lane per ray; params->subvoxel must
- * be 0; the start may lie anywhere whose voxels within max_range keep |index| < 2^23;
- * RMPC_E_OUT_OF_BOUNDS otherwise); rmpc_trace_debug then reports a hit as
+ * rmpc_query and rmpc_trace_debug accept sparse maps (launch configuration
+ * RMPC_CONFIG_SPARSE; params->subvoxel must be 0; the start may lie anywhere whose voxels
+ * within max_range keep |index| < 2^23; RMPC_E_OUT_OF_BOUNDS otherwise); rmpc_trace_debug
+ * then reports a hit as
  * slot * 512 + (i + 8 j + 64 l) of the hit voxel in its block.  rmpc_rollout flies on sparse
  * maps.  Batched queries, the serving loop, batched rollouts and the distance transform take
  * dense maps only (RMPC_E_INVALID).  Blocking.

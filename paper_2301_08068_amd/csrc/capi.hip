@@ -164,7 +164,8 @@ bool grid_coords(const rmpc_map_desc &d, const double x[3], float g[3])
 }
 
 // A map query on a sparse map: the world has no edge, so the start only has to keep every
-// voxel a ray can reach within the block coordinate range; one lane per ray.
+// voxel a ray can reach within the block coordinate range; segments per ray from the sparse
+// launch configuration.
 rmpc_status setup_sparse_query(rmpc_ctx *ctx, const MapEntry &me, const double x[3], int32_t n_rays,
                                const rmpc_params *params, const rmpc_launch_config &cfg, rmpc::RayArgs &A)
 {

@@ -104,7 +104,7 @@ struct alignas(16) RayRec {
 // Everything one map query needs.
 struct RayArgs {
     MapView map;                 // dense maps
-    SparseView sp;               // sparse maps (then segments is 1)
+    SparseView sp;               // sparse maps
     int32_t sparse;
     const RayRec *rays;          // ordered ray list; entries with i >= n_rays are skipped
     int32_t n_list;              // length of `rays` (>= n_rays)
