@@ -177,9 +177,10 @@ typedef struct {
  * RMPC_CONFIG_SPARSE; params->subvoxel must be 0; the start may lie anywhere whose voxels
  * within max_range keep |index| < 2^23; RMPC_E_OUT_OF_BOUNDS otherwise); rmpc_trace_debug
  * then reports a hit as
- * slot * 512 + (i + 8 j + 64 l) of the hit voxel in its block.  rmpc_rollout flies on sparse
- * maps.  Batched queries, the serving loop, batched rollouts and the distance transform take
- * dense maps only (RMPC_E_INVALID).  Blocking.
+ * slot * 512 + (i + 8 j + 64 l) of the hit voxel in its block.  Batched queries, the serving
+ * loop and rollouts (single and batched) take sparse maps too: in a batch a sparse query uses
+ * the batch's segmentation with block rounds of 4 steps.  The distance transform takes dense
+ * maps only (RMPC_E_INVALID).  Blocking.
  * Errors: RMPC_E_INVALID (NULL, n_blocks, dtype, voxel size, coordinates, a repeated block),
  * RMPC_E_NOMEM (arena full), RMPC_E_HIP.
  */
@@ -293,7 +294,8 @@ typedef struct {
  *   q[n]: queries, 1 <= n; map queries use map_params, scan queries scan_params (either may
  *     be NULL if no query of that kind is present).
  *   out[n]: host results, the same as rmpc_query / rmpc_scan_query would return for each
- *     query alone; bitwise identical when the launch configuration is the same.
+ *     query alone; bitwise identical when the launch configuration is the same (for a query
+ *     on a sparse map: RMPC_CONFIG_SPARSE with lookahead 4 and the batch's lane target).
  * Queries are validated first; any invalid one fails the whole call (the message names its
  * index) and nothing is written.  Large batches are split into several launches.  Blocking.
  * Errors: RMPC_E_INVALID, RMPC_E_NOMAP, RMPC_E_OUT_OF_BOUNDS, RMPC_E_NOMEM, RMPC_E_HIP.

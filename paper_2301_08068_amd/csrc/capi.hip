@@ -163,6 +163,16 @@ bool grid_coords(const rmpc_map_desc &d, const double x[3], float g[3])
     return true;
 }
 
+bool sparse_position_ok(const rmpc_map_desc &d, const double x[3], double tmax)
+{
+    const double reach = (double)(1 << 23) - 16.0;
+    for (int a = 0; a < 3; ++a) {
+        const float g = (float)((x[a] - d.origin_m[a]) / d.voxel_m);
+        if (!(std::fabs((double)g) + tmax < reach)) return false;
+    }
+    return true;
+}
+
 // A map query on a sparse map: the world has no edge, so the start only has to keep every
 // voxel a ray can reach within the block coordinate range; segments per ray from the sparse
 // launch configuration.
@@ -175,11 +185,11 @@ rmpc_status setup_sparse_query(rmpc_ctx *ctx, const MapEntry &me, const double x
     // every voxel within tmax of the start keeps |coordinate| < 2^23 (block coordinates in 21 bits)
     const double reach = (double)(1 << 23) - 16.0;
     if (!(tmax < reach)) return fail(RMPC_E_INVALID, "max_range_m spans too many voxels for a sparse map");
+    if (!sparse_position_ok(me.desc, x, tmax))
+        return fail(RMPC_E_OUT_OF_BOUNDS, "position too far from the sparse map's origin");
     uint32_t start_flags = 0;
     for (int a = 0; a < 3; ++a) {
         const float g = (float)((x[a] - me.desc.origin_m[a]) / me.desc.voxel_m);
-        if (!(std::fabs((double)g) + tmax < reach))
-            return fail(RMPC_E_OUT_OF_BOUNDS, "position too far from the sparse map's origin");
         A.g[a] = g;
         A.v0[a] = (int32_t)std::floor(g);
         const double fr = (double)g - std::floor((double)g);
@@ -211,7 +221,8 @@ rmpc_status setup_sparse_query(rmpc_ctx *ctx, const MapEntry &me, const double x
 
 // Validates the query state and fills the geometry part of RayArgs.
 rmpc_status setup_query(rmpc_ctx *ctx, int32_t map_id, const double x[3], int32_t n_rays,
-                        const rmpc_params *params, const rmpc_launch_config &cfg, rmpc::RayArgs &A)
+                        const rmpc_params *params, const rmpc_launch_config &cfg, rmpc::RayArgs &A,
+                        const rmpc_launch_config *sparse_cfg)
 {
     if (!ctx) return fail(RMPC_E_INVALID, "ctx is NULL");
     if (!finite3(x)) return fail(RMPC_E_INVALID, "position is NULL or not finite");
@@ -220,7 +231,7 @@ rmpc_status setup_query(rmpc_ctx *ctx, int32_t map_id, const double x[3], int32_
     auto it = ctx->maps.find(map_id);
     if (it == ctx->maps.end()) return fail(RMPC_E_NOMAP, "unknown map id");
     const MapEntry &me = it->second;
-    if (me.sparse) return setup_sparse_query(ctx, me, x, n_rays, params, ctx->cfg[RMPC_CONFIG_SPARSE], A);
+    if (me.sparse) return setup_sparse_query(ctx, me, x, n_rays, params, sparse_cfg ? *sparse_cfg : cfg, A);
     const int32_t n[3] = {me.desc.nx, me.desc.ny, me.desc.nz};
     std::memset(&A, 0, sizeof A);
     uint32_t start_flags = 0;
@@ -632,7 +643,8 @@ rmpc_status rmpc_query(rmpc_ctx *ctx, int32_t map_id, const double x[3], const d
     DeviceGuard dg(ctx->device);
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     rmpc::RayArgs A;
-    if (rmpc_status st = setup_query(ctx, map_id, x, n_rays, params, ctx->cfg[RMPC_CONFIG_QUERY], A))
+    if (rmpc_status st = setup_query(ctx, map_id, x, n_rays, params, ctx->cfg[RMPC_CONFIG_QUERY], A,
+                                     &ctx->cfg[RMPC_CONFIG_SPARSE]))
         return st;
     A.seq = ++ctx->seq;
     A.pol = policy_f(params, v);
@@ -654,7 +666,8 @@ rmpc_status rmpc_trace_debug(rmpc_ctx *ctx, int32_t map_id, const double x[3], i
     DeviceGuard dg(ctx->device);
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     rmpc::RayArgs A;
-    if (rmpc_status st = setup_query(ctx, map_id, x, n_rays, params, ctx->cfg[RMPC_CONFIG_QUERY], A))
+    if (rmpc_status st = setup_query(ctx, map_id, x, n_rays, params, ctx->cfg[RMPC_CONFIG_QUERY], A,
+                                     &ctx->cfg[RMPC_CONFIG_SPARSE]))
         return st;
     A.seq = ++ctx->seq;
     A.dbg_hit = hit_lin_dev;

@@ -32,6 +32,7 @@
 
 #include "rmpc_device.h"
 #include "rmpc_kernels.h"
+#include "rmpc_sparse.h"
 #include "rmpc_walk.h"
 
 namespace rmpc {
@@ -755,6 +756,12 @@ __global__ void __launch_bounds__(kBlock, 3) batch_kernel(BatchArgs B)
         // the descriptor is the same for the whole block: copy it into scalar registers
         if (q_kind == 0) {
             const RayArgs A = load_uniform(&Qm.ray);
+            if (A.sparse) {
+                // block rounds of 4 steps on sparse maps (their best; larger ones would raise the
+                // kernel's register budget and make the dense path spill)
+                sparse_tile<4>(A, t, q_n_tiles, F, lds);
+                continue;
+            }
             switch (A.map.dtype) {
             case RMPC_TSDF_F32: ray_tile<RMPC_TSDF_F32, K>(A, t, q_n_tiles, F, lds); break;
             case RMPC_TSDF_F16: ray_tile<RMPC_TSDF_F16, K>(A, t, q_n_tiles, F, lds); break;

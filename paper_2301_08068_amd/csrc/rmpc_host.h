@@ -112,9 +112,14 @@ rmpc::PolicyF policy_f(const rmpc_params *p, const double v[3]);
 // Grid coordinates of a world position, (x - origin) / voxel rounded to float32 per axis;
 // false when one falls outside [0, n) (or is NaN).  The test every map query applies.
 bool grid_coords(const rmpc_map_desc &d, const double x[3], float g[3]);
-// Validate a map query and fill the geometry and policy-independent part of RayArgs.
+// Validate a map query and fill the geometry and policy-independent part of RayArgs; a query
+// on a sparse map takes its segmentation from sparse_cfg when given, else from cfg.
 rmpc_status setup_query(rmpc_ctx *ctx, int32_t map_id, const double x[3], int32_t n_rays,
-                        const rmpc_params *params, const rmpc_launch_config &cfg, rmpc::RayArgs &A);
+                        const rmpc_params *params, const rmpc_launch_config &cfg, rmpc::RayArgs &A,
+                        const rmpc_launch_config *sparse_cfg = nullptr);
+// Whether a query at x on a sparse map keeps every voxel within tmax (voxel units) of its start
+// inside the block coordinate range (|index| < 2^23 - 16), the test every sparse query applies.
+bool sparse_position_ok(const rmpc_map_desc &d, const double x[3], double tmax);
 // Largest scan query (points).
 constexpr int32_t kMaxScanPoints = 1 << 24;
 // Validate a scan query and fill ScanArgs except partials, ticket, result, done and seq.

@@ -212,20 +212,19 @@ rmpc_status rmpc_rollout_batch(rmpc_ctx *ctx, const rmpc_flight *flights, int32_
     if (!ctx || !flights || !params || !out) return fail(RMPC_E_INVALID, "NULL argument");
     if (n < 1) return fail(RMPC_E_INVALID, "n must be >= 1");
     if (rmpc_status st = rmpc_host::check_params(params)) return st;
-    std::vector<const rmpc_map_desc *> desc((size_t)n);
+    std::vector<const rmpc_host::MapEntry *> maps((size_t)n);
     for (int32_t i = 0; i < n; ++i) {
         const rmpc_flight &f = flights[i];
         const std::string where = "flight " + std::to_string(i) + ": ";
         auto it = ctx->maps.find(f.map_id);
         if (it == ctx->maps.end()) return fail(RMPC_E_NOMAP, where + "unknown map id");
-        if (it->second.sparse) return fail(RMPC_E_INVALID, where + "batched flights need dense maps (rmpc_rollout flies on sparse ones)");
         if (f.n_rays < 1 || f.n_rays > RMPC_MAX_RAYS) return fail(RMPC_E_INVALID, where + "n_rays out of [1, 65536]");
         if (!finite3(f.x0) || !finite3(f.v0)) return fail(RMPC_E_INVALID, where + "state not finite");
         if (rmpc_status st = check_rollout(&f.rp)) {
             rmpc_host::g_last_error = where + rmpc_host::g_last_error;
             return st;
         }
-        desc[(size_t)i] = &it->second.desc;
+        maps[(size_t)i] = &it->second;
     }
     std::vector<Flight> F((size_t)n);
     for (int32_t i = 0; i < n; ++i) F[(size_t)i].begin(flights[i].x0, flights[i].v0, nullptr);
@@ -240,8 +239,12 @@ rmpc_status rmpc_rollout_batch(rmpc_ctx *ctx, const rmpc_flight *flights, int32_
         for (int32_t i = 0; i < n; ++i) {
             Flight &f = F[(size_t)i];
             if (f.done || f.ends_before_query(flights[i].rp)) continue;
+            // the bounds test rmpc_query applies (dense: inside the grid; sparse: within reach)
+            const rmpc_host::MapEntry &me = *maps[(size_t)i];
             float g[3];
-            if (!rmpc_host::grid_coords(*desc[(size_t)i], f.x, g)) {   // rmpc_query's own test
+            const bool inside = me.sparse ? rmpc_host::sparse_position_ok(me.desc, f.x, params->max_range_m / me.desc.voxel_m)
+                                          : rmpc_host::grid_coords(me.desc, f.x, g);
+            if (!inside) {
                 f.end(RMPC_ROLLOUT_LEFT_GRID);
                 continue;
             }

@@ -151,8 +151,6 @@ def test_sparse_errors(ctx, tiny_map):
         x, v = W.free_state(tiny_map, 100)
         with pytest.raises(binding.RmpcError, match="subvoxel"):
             ctx.query(mid, x, v, 256, dict(P_TINY, subvoxel=1.0))
-        with pytest.raises(binding.RmpcError, match="sparse"):
-            ctx.query_batch([dict(kind="map", map_id=mid, n=256, x=x, v=v)], map_params=P_TINY)
         with pytest.raises(binding.RmpcError, match="dense"):
             ctx.edt(mid, (8, 8, 8))
         with pytest.raises(binding.RmpcError, match="far"):
@@ -230,3 +228,72 @@ def test_sparse_world_65536(ctx, world):
             print(f"world state {seed}: {s} rays identical, {f} flagged, {int((o['hit'] >= 0).sum())} hits")
     finally:
         ctx.release(mid)
+
+
+def test_sparse_in_batches_serving_and_rollouts(ctx, tiny_map):
+    """Sparse map queries inside batches (mixed with dense map queries and a scan), through the
+    serving loop, and in batched rollouts: each result equals the same query or flight made
+    alone with the same launch configuration, bit for bit (single sparse queries are checked
+    against the oracle above)."""
+    import time
+    from paper_2301_08068_amd import binding as B
+    shift = (-5, 3, 2)
+    sm = W.sparse_from_dense(tiny_map, offset_blocks=shift, keep_free=0.2, seed=8)
+    sid = ctx.upload_sparse(sm.coords, sm.values, sm.voxel_m, sm.origin_m, "f32")
+    did = ctx.upload(tiny_map.tsdf, tiny_map.voxel_m, tiny_map.origin_m, "f32")
+    old_b, old_s = ctx.config(B.CONFIG_BATCH), ctx.config(B.CONFIG_SPARSE)
+    lidar = W.params("lidar")
+    try:
+        bcfg = ctx.config(B.CONFIG_BATCH, use_graph=0)
+        # a batch walks sparse maps with block rounds of 4 steps and the batch's segmentation
+        ctx.config(B.CONFIG_SPARSE, lookahead=4, lane_target_log2=bcfg["lane_target_log2"])
+        qs = []
+        for k, seed in enumerate(range(300, 306)):
+            x, v = _dyadic_state(tiny_map, sm, shift, seed)
+            qs.append(dict(kind="map", map_id=sid, n=[256, 1024, 4096][k % 3], x=x, v=v))
+            xd, vd = W.free_state(tiny_map, seed)
+            qs.append(dict(kind="map", map_id=did, n=1024, x=xd, v=vd))
+        xd, vd = W.free_state(tiny_map, 399)
+        pts = torch.from_numpy(W.synth_scan(tiny_map, xd, 399, n_elev=16, n_azim=256)).cuda()
+        qs.append(dict(kind="scan", points=pts, v=vd))
+        res = ctx.query_batch(qs, map_params=P_TINY, scan_params=lidar)
+        for q, r in zip(qs, res):
+            alone = ctx.query_batch([q], map_params=P_TINY, scan_params=lidar)[0]
+            assert np.array_equal(r["f"], alone["f"]) and np.array_equal(r["S"], alone["S"]), q
+            if q["kind"] == "map" and q["map_id"] == sid:
+                single = ctx.query(sid, q["x"], q["v"], q["n"], P_TINY)
+                assert np.array_equal(r["f"], single["f"]) and np.array_equal(r["S"], single["S"])
+                assert r["n_hit"] == single["n_hit"] and r["visits"] == single["visits"]
+        # the serving loop: sparse requests among dense ones
+        reqs = [B.request(dict(q)) for q in qs[:-1]]
+        B.rmpc_server_start(ctx.ptr, n_slots=2, max_batch=4, map_params=P_TINY, scan_params=lidar, launch=bcfg,
+                            staging_bytes=0)
+        try:
+            tks = [B.rmpc_submit(ctx.ptr, r) for r in reqs]
+            got, t0 = {}, time.time()
+            while len(got) < len(tks):
+                for t, r, _ in B.rmpc_poll_completed(ctx.ptr, 64):
+                    got[t] = r
+                assert time.time() - t0 < 60.0
+        finally:
+            B.rmpc_server_stop(ctx.ptr)
+        for t, r in zip(tks, res[:-1]):
+            assert np.array_equal(got[t]["f"], r["f"]) and np.array_equal(got[t]["S"], r["S"])
+        # batched flights on the sparse map equal single flights
+        flights = []
+        for k, seed in enumerate(range(310, 314)):
+            x0, v0 = _dyadic_state(tiny_map, sm, shift, seed)
+            goal, _ = _dyadic_state(tiny_map, sm, shift, seed + 50)
+            flights.append(dict(map_id=sid, n_rays=[256, 1024][k % 2], x0=x0, v0=0.3 * v0, goal=goal, alpha=10.0,
+                                beta=15.0, dt=0.001, max_steps=[150, 60][k % 2], goal_tol=0.1))
+        out = ctx.rollout_batch(flights, P_TINY)
+        for f, r in zip(flights, out):
+            a = ctx.rollout(f["map_id"], f["x0"], f["v0"], f["n_rays"], P_TINY, f["goal"], f["alpha"], f["beta"],
+                            f["dt"], f["max_steps"], f["goal_tol"])
+            assert r["status"] == a["status"] and r["n_steps"] == a["n_steps"], (r, a)
+            assert np.array_equal(r["x_final"], a["x_final"]) and np.array_equal(r["v_final"], a["v_final"])
+    finally:
+        ctx.config(B.CONFIG_BATCH, **old_b)
+        ctx.config(B.CONFIG_SPARSE, **old_s)
+        ctx.release(sid)
+        ctx.release(did)
