@@ -275,15 +275,20 @@ rmpc_status setup_query(rmpc_ctx *ctx, int32_t map_id, const double x[3], int32_
 }
 
 // Wait for a query's result: spin on the completion word the kernel sets after writing the
-// result (a few microseconds sooner than a stream synchronisation), checking the stream for
-// errors now and then.
+// result (a few microseconds sooner than a stream synchronisation).  The stream is checked for
+// errors only once the wait has lasted kStreamCheck, and then once per kStreamCheck (measured:
+// with a stream query every 1,024 spins a query whose kernel takes 20 us returned after 40 us;
+// with none in its first millisecond, after 25 us).
 rmpc_status wait_done(const uint64_t *done, hipStream_t s, uint64_t seq)
 {
-    const auto t0 = std::chrono::steady_clock::now();
+    using Clock = std::chrono::steady_clock;
+    const auto t0 = Clock::now();
+    auto next_check = t0 + kStreamCheck;
     for (uint64_t it = 1;; ++it) {
         if (__atomic_load_n(done, __ATOMIC_ACQUIRE) == seq) return RMPC_OK;
-        if ((it & 1023) == 0) {
-            if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(60))
+        if ((it & 255) == 0 && Clock::now() >= next_check) {
+            next_check = Clock::now() + kStreamCheck;
+            if (Clock::now() - t0 > std::chrono::seconds(60))
                 return fail(RMPC_E_HIP, "query kernel did not finish within 60 s");
             const hipError_t e = hipStreamQuery(s);
             if (e == hipSuccess) {

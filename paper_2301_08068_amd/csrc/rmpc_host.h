@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cstdint>
 #include <map>
 #include <string>
@@ -125,7 +126,9 @@ constexpr int32_t kMaxScanPoints = 1 << 24;
 // Validate a scan query and fill ScanArgs except partials, ticket, result, done and seq.
 rmpc_status setup_scan(const float *points_dev, int32_t n_points, const double v[3], const rmpc_params *params,
                        rmpc::ScanArgs &A);
-// Spin until *done == seq (the kernel's publication), checking the stream for errors.
+// Spin until *done == seq (the kernel's publication), checking the stream for errors once the
+// wait has lasted kStreamCheck, and once per kStreamCheck after that.
+constexpr std::chrono::microseconds kStreamCheck(1000);
 rmpc_status wait_done(const uint64_t *done, hipStream_t s, uint64_t seq);
 
 // Launch slots of the batch kernel.

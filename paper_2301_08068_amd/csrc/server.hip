@@ -51,6 +51,7 @@ struct Slot {
     bool busy = false;
     uint64_t seq = 0;
     Clock::time_point t_launch;
+    Clock::time_point t_check;       // next stream check (see kStreamCheck)
     std::vector<Req> members;
 };
 
@@ -144,6 +145,7 @@ rmpc_status launch_slot(rmpc_ctx *ctx, ServerState *S, Slot &sl)
     sl.seq = seq;
     sl.busy = true;
     sl.t_launch = Clock::now();
+    sl.t_check = sl.t_launch + kStreamCheck;
     return RMPC_OK;
 }
 
@@ -162,7 +164,10 @@ void server_loop(rmpc_ctx *ctx, ServerState *S)
                 continue;
             }
             in_flight = true;
-            if ((spins & 1023) == 0) {
+            // the stream is checked for errors only for launches older than kStreamCheck, once
+            // per kStreamCheck, as wait_done does
+            if ((spins & 255) == 0 && Clock::now() >= sl.t_check) {
+                sl.t_check = Clock::now() + kStreamCheck;
                 const hipError_t e = hipStreamQuery(sl.ls.stream);
                 std::string msg;
                 if (e == hipSuccess && __atomic_load_n(sl.ls.done_host, __ATOMIC_ACQUIRE) != sl.seq)
