@@ -350,7 +350,7 @@ def sparse_bench(args):
     n_rays, rmax = 65536, 10.0
     params = W.params("static", max_range=rmax)
     ctx = binding.Context(0, arena_bytes=(3 << 30) // 2)
-    mid = ctx.upload_sparse(sm.coords, sm.values, sm.voxel_m, sm.origin_m, "f32")
+    mid = ctx.upload_sparse(sm.coords, sm.values, sm.voxel_m, sm.origin_m, "f32", sm.trunc_m)
     over = {k: v for k, v in (("lookahead", args.lookahead), ("lane_target_log2", args.lane_target)) if v}
     launch = ctx.config(binding.CONFIG_SPARSE, **over)
     step = binding.PreparedQuery(ctx.ptr, mid, x, v, n_rays, params, stream=ctx.stream)

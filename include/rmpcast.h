@@ -160,6 +160,10 @@ typedef struct {
     int32_t dtype;              /* rmpc_dtype of the voxel values */
     double voxel_m;
     double origin_m[3];         /* world position of the minimum corner of voxel (0, 0, 0) */
+    double free_value;          /* TSDF maps: the field's value at every voxel outside the stored
+                                   blocks (the map's truncation distance, > 0), used by sub-voxel
+                                   distances; converted to the storage type as a value would be.
+                                   Ignored for uint8 maps. */
 } rmpc_sparse_desc;
 
 /*
@@ -174,15 +178,15 @@ typedef struct {
  * table (a power of two of at least 2 n_blocks entries of 16 bytes, at least 1024) from block
  * coordinates to slots: 16 capacity + 64 n_blocks + 512 elem_bytes n_blocks arena bytes.
  * rmpc_query and rmpc_trace_debug accept sparse maps (launch configuration
- * RMPC_CONFIG_SPARSE; params->subvoxel must be 0; the start may lie anywhere whose voxels
- * within max_range keep |index| < 2^23; RMPC_E_OUT_OF_BOUNDS otherwise); rmpc_trace_debug
- * then reports a hit as
+ * RMPC_CONFIG_SPARSE; the start may lie anywhere whose voxels within max_range keep
+ * |index| < 2^23; RMPC_E_OUT_OF_BOUNDS otherwise; sub-voxel distances on TSDF maps read
+ * free_value outside the stored blocks); rmpc_trace_debug then reports a hit as
  * slot * 512 + (i + 8 j + 64 l) of the hit voxel in its block.  Batched queries, the serving
  * loop and rollouts (single and batched) take sparse maps too: in a batch a sparse query uses
  * the batch's segmentation with block rounds of 4 steps.  The distance transform takes dense
  * maps only (RMPC_E_INVALID).  Blocking.
- * Errors: RMPC_E_INVALID (NULL, n_blocks, dtype, voxel size, coordinates, a repeated block),
- * RMPC_E_NOMEM (arena full), RMPC_E_HIP.
+ * Errors: RMPC_E_INVALID (NULL, n_blocks, dtype, voxel size, free_value, coordinates, a
+ * repeated block), RMPC_E_NOMEM (arena full), RMPC_E_HIP.
  */
 rmpc_status rmpc_sparse_map_upload(rmpc_ctx *ctx, const rmpc_sparse_desc *desc, const int32_t *block_coords_host,
                                    const void *values, int values_on_device, void *hip_stream,

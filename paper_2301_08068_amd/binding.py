@@ -39,7 +39,7 @@ class MapDesc(C.Structure):
 
 class SparseDesc(C.Structure):
     _fields_ = [("n_blocks", C.c_int32), ("dtype", C.c_int32), ("voxel_m", C.c_double),
-                ("origin_m", C.c_double * 3)]
+                ("origin_m", C.c_double * 3), ("free_value", C.c_double)]
 
 
 class Params(C.Structure):
@@ -224,12 +224,14 @@ def rmpc_map_upload(ctx: int, nx: int, ny: int, nz: int, dtype: str, voxel_m: fl
 
 
 def rmpc_sparse_map_upload(ctx: int, coords: np.ndarray, values_ptr: int, n_blocks: int, dtype: str,
-                           voxel_m: float, origin_m, on_device: bool, stream=None) -> int:
+                           voxel_m: float, origin_m, on_device: bool, free_value: float = 0.0,
+                           stream=None) -> int:
     """coords: int32 [n_blocks, 3] block coordinates (host); values_ptr: n_blocks * 512
-    elements of the dtype, block after block, x fastest within a block."""
+    elements of the dtype, block after block, x fastest within a block; free_value: the TSDF
+    field outside the stored blocks (TSDF maps)."""
     c = np.ascontiguousarray(coords, dtype=np.int32).reshape(-1, 3)
     assert c.shape[0] == n_blocks
-    d = SparseDesc(int(n_blocks), DTYPES[dtype], float(voxel_m), _d3(origin_m))
+    d = SparseDesc(int(n_blocks), DTYPES[dtype], float(voxel_m), _d3(origin_m), float(free_value))
     mid = C.c_int32(-1)
     _check(_lib.rmpc_sparse_map_upload(C.c_void_p(ctx), C.byref(d), c.ctypes.data_as(C.c_void_p),
                                        C.c_void_p(values_ptr), int(bool(on_device)),
@@ -537,15 +539,16 @@ class Context:
         return mid
 
     def upload_sparse(self, coords: np.ndarray, values: np.ndarray, voxel_m: float, origin_m,
-                      dtype: str = "f32") -> int:
+                      dtype: str = "f32", free_value: float = 0.3) -> int:
         """Upload a sparse block map: coords int32 [n, 3], values [n, 8, 8, 8] indexed
-        (block, z, y, x) (float32 TSDF, uint16 binary16 bits or uint8)."""
+        (block, z, y, x) (float32 TSDF, uint16 binary16 bits or uint8); free_value: the TSDF
+        field outside the stored blocks (the truncation distance)."""
         import torch
         want = {"f32": np.float32, "f16": np.uint16, "u8": np.uint8}[dtype]
         arr = np.ascontiguousarray(values, dtype=want).reshape(-1, 8, 8, 8)
         t = torch.from_numpy(arr.view(np.uint8).reshape(-1)).to(f"cuda:{self.device}")
         mid = rmpc_sparse_map_upload(self.ptr, coords, t.data_ptr(), arr.shape[0], dtype, voxel_m, origin_m,
-                                     True, stream=self.stream)
+                                     True, free_value=free_value, stream=self.stream)
         del t
         return mid
 

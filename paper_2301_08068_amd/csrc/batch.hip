@@ -110,6 +110,8 @@ rmpc_status batch_describe(rmpc_ctx *ctx, const rmpc_query_desc &d, int k, const
             g_last_error = where + g_last_error;
             return st;
         }
+        if (Q.ray.sparse && Q.ray.subvoxel)
+            return fail(RMPC_E_INVALID, where + "subvoxel distances on sparse maps are queried one at a time (rmpc_query)");
         Q.kind = 0;
         Q.ray.pol = policy_f(mp, d.v);
         for (int a = 0; a < 3; ++a) Q.ray.vel64[a] = d.v[a];

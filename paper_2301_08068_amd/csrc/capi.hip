@@ -180,7 +180,8 @@ rmpc_status setup_sparse_query(rmpc_ctx *ctx, const MapEntry &me, const double x
                                const rmpc_params *params, const rmpc_launch_config &cfg, rmpc::RayArgs &A)
 {
     std::memset(&A, 0, sizeof A);
-    if (params->subvoxel) return fail(RMPC_E_INVALID, "subvoxel distances are not available on sparse maps");
+    if (params->subvoxel && me.desc.dtype == RMPC_OCC_U8)
+        return fail(RMPC_E_INVALID, "subvoxel distances need a TSDF map (float32 or float16)");
     const double tmax = params->max_range_m / me.desc.voxel_m;
     // every voxel within tmax of the start keeps |coordinate| < 2^23 (block coordinates in 21 bits)
     const double reach = (double)(1 << 23) - 16.0;
@@ -198,6 +199,7 @@ rmpc_status setup_sparse_query(rmpc_ctx *ctx, const MapEntry &me, const double x
     ray_list(ctx, n_rays, &A.rays, &A.n_list);
     A.sparse = 1;
     A.sp = me.sview;
+    A.subvoxel = params->subvoxel != 0;
     A.n_rays = n_rays;
     A.start_flags = start_flags;
     A.tmax_lo = (float)(tmax * (1.0 - 1e-6) - 2e-5);
@@ -552,6 +554,12 @@ rmpc_status rmpc_sparse_map_upload(rmpc_ctx *ctx, const rmpc_sparse_desc *desc, 
         return fail(RMPC_E_INVALID, "unknown dtype");
     if (!(desc->voxel_m > 0) || !std::isfinite(desc->voxel_m) || !finite3(desc->origin_m))
         return fail(RMPC_E_INVALID, "voxel size or origin invalid");
+    // the field outside the stored blocks, as a stored value of the map's type reads back
+    double free_value = 0.0;
+    if (desc->dtype == RMPC_TSDF_F32) free_value = (double)(float)desc->free_value;
+    if (desc->dtype == RMPC_TSDF_F16) free_value = (double)(_Float16)desc->free_value;
+    if (desc->dtype != RMPC_OCC_U8 && !(free_value > 0.0 && std::isfinite(free_value)))
+        return fail(RMPC_E_INVALID, "free_value must be positive and finite in the map's storage type");
     // the table: a power of two of at least twice the blocks, filled on the host by linear probing
     uint32_t cap = 1024;
     while (cap < 2u * (uint32_t)n) cap *= 2u;
@@ -594,6 +602,7 @@ rmpc_status rmpc_sparse_map_upload(rmpc_ctx *ctx, const rmpc_sparse_desc *desc, 
     v.occ = reinterpret_cast<const uint64_t *>(ctx->arena + o_occ);
     v.values = ctx->arena + o_vals;
     v.dtype = desc->dtype;
+    v.free_value = free_value;
     hipError_t e = hipMemcpyAsync(table_dev, table.data(), sizeof(rmpc::HashEntry) * (size_t)cap,
                                   hipMemcpyHostToDevice, s);
     if (e == hipSuccess)

@@ -568,69 +568,28 @@ __device__ __forceinline__ RayOut trace_group(const RayArgs &A, bool valid, int 
     return o;
 }
 
-// Stored value of voxel (i, j, k), the indices clamped into the grid, as float64 (exact for
-// float32 and binary16).
+// The stored value of voxel (i, j, k) of a dense map, the indices clamped into the grid, as
+// float64 (exact for float32 and binary16): the field reader of sub-voxel distances.
 template <int DT>
-__device__ __forceinline__ double stored_value(const MapView &m, int i, int j, int k)
-{
-    i = i < 0 ? 0 : (i >= m.nx ? m.nx - 1 : i);
-    j = j < 0 ? 0 : (j >= m.ny ? m.ny - 1 : j);
-    k = k < 0 ? 0 : (k >= m.nz ? m.nz - 1 : k);
-    const uint32_t lin = (uint32_t)i + (uint32_t)m.nx * ((uint32_t)j + (uint32_t)m.ny * (uint32_t)k);
-    const typename Voxel<DT>::T v = static_cast<const typename Voxel<DT>::T *>(m.data)[lin];
-    if constexpr (DT == RMPC_TSDF_F32) return (double)v;
-    else return (double)__builtin_bit_cast(_Float16, v);
-}
+struct DenseField {
+    const typename Voxel<DT>::T *data;
+    int nx, ny, nz;
+    __device__ __forceinline__ double operator()(int i, int j, int k) const
+    {
+        i = i < 0 ? 0 : (i >= nx ? nx - 1 : i);
+        j = j < 0 ? 0 : (j >= ny ? ny - 1 : j);
+        k = k < 0 ? 0 : (k >= nz ? nz - 1 : k);
+        const typename Voxel<DT>::T v = data[(uint32_t)i + (uint32_t)nx * ((uint32_t)j + (uint32_t)ny * (uint32_t)k)];
+        if constexpr (DT == RMPC_TSDF_F32) return (double)v;
+        else return (double)__builtin_bit_cast(_Float16, v);
+    }
+};
 
-// The continuous TSDF: trilinear interpolation of the stored values, which sit at the voxel
-// centres (grid coordinates i + 1/2), at grid point p; x first, then y, then z.
-template <int DT>
-__device__ __forceinline__ double tsdf_field(const MapView &m, double px, double py, double pz)
-{
-#pragma clang fp contract(off)
-    const double ux = px - 0.5, uy = py - 0.5, uz = pz - 0.5;
-    const double flx = floor(ux), fly = floor(uy), flz = floor(uz);
-    const int ix = (int)flx, iy = (int)fly, iz = (int)flz;
-    const double fx = ux - flx, fy = uy - fly, fz = uz - flz;
-    double c[2][2];
-#pragma unroll
-    for (int dz = 0; dz < 2; ++dz)
-#pragma unroll
-        for (int dy = 0; dy < 2; ++dy) {
-            const double a0 = stored_value<DT>(m, ix, iy + dy, iz + dz);
-            const double a1 = stored_value<DT>(m, ix + 1, iy + dy, iz + dz);
-            c[dz][dy] = a0 + fx * (a1 - a0);
-        }
-    const double e0 = c[0][0] + fy * (c[0][1] - c[0][0]);
-    const double e1 = c[1][0] + fy * (c[1][1] - c[1][0]);
-    return e0 + fz * (e1 - e0);
-}
-
-// Sub-voxel hit distance: the field is sampled along the ray at t_k = max(t + k/2 - 3/2, 0),
-// k = 0..7 (grid units, t = d / h: from 1.5 voxels before the hit voxel's entry to 2 after
-// it, a window that holds the field's zero crossing for the hits of an oblique plane); at
-// the first k with phi_k > 0 >= phi_k+1 one secant step gives the crossing.  Without a sign
-// change d is kept.  float64 throughout, no contraction, so the result is that of the
-// definition evaluated in float64.
 template <int DT>
 __device__ __forceinline__ double subvoxel_distance(const RayArgs &A, float rx, float ry, float rz, double d)
 {
-#pragma clang fp contract(off)
-    const double t = d / A.h;
-    double tk[8], phi[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const double s = t + 0.5 * (double)k - 1.5;
-        tk[k] = s > 0.0 ? s : 0.0;
-        phi[k] = tsdf_field<DT>(A.map, (double)A.g[0] + tk[k] * (double)rx, (double)A.g[1] + tk[k] * (double)ry,
-                                (double)A.g[2] + tk[k] * (double)rz);
-    }
-    for (int k = 0; k < 7; ++k)
-        if (phi[k] > 0.0 && phi[k + 1] <= 0.0) {
-            const double ts = tk[k] + (tk[k + 1] - tk[k]) * (phi[k] / (phi[k] - phi[k + 1]));
-            return ts * A.h;
-        }
-    return d;
+    const DenseField<DT> f{static_cast<const typename Voxel<DT>::T *>(A.map.data), A.map.nx, A.map.ny, A.map.nz};
+    return subvoxel_at(A, f, rx, ry, rz, d);
 }
 
 // One 256-lane tile of a map query: lane -> (ray position, segment).  Waves stay whole (the
@@ -758,8 +717,9 @@ __global__ void __launch_bounds__(kBlock, 3) batch_kernel(BatchArgs B)
             const RayArgs A = load_uniform(&Qm.ray);
             if (A.sparse) {
                 // block rounds of 4 steps on sparse maps (their best; larger ones would raise the
-                // kernel's register budget and make the dense path spill)
-                sparse_tile<4>(A, t, q_n_tiles, F, lds);
+                // kernel's register budget and make the dense path spill), no sub-voxel
+                // refinement (batches refuse it on sparse maps, for the same reason)
+                sparse_tile<4, kSvNone>(A, t, q_n_tiles, F, lds);
                 continue;
             }
             switch (A.map.dtype) {

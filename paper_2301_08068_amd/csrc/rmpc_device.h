@@ -91,8 +91,9 @@ struct Acc {
 // A block writes one row per thread to LDS.  Nine groups of 16 lanes (threads 0..143) merge
 // one compensated pair each and four groups in the last wave (threads 192..255) add one
 // integer counter each, so no wave mixes the two kinds.  Lane q of a group merges rows q,
-// q+16, ... (all 16 loaded first) in a pairwise tree, and the 16 lanes combine with a
-// butterfly that always puts the lower lane first.  Every step has a fixed order, so results do not
+// q+16, ... in row order (all 16 loaded first), and the 16 lanes combine with a butterfly
+// that always puts the lower lane first.  (A pairwise tree over the 16 rows was no faster
+// and made the batch kernel, at its register budget, spill.)  Every step has a fixed order, so results do not
 // depend on timing.
 // ------------------------------------------------------------------------------------
 
@@ -148,12 +149,9 @@ __device__ __forceinline__ void block_reduce_store(const Acc &a, float *lds, flo
             vs[u] = lds[(q + u * kColLanes) * kRowWords + col];
             vc[u] = lds[(q + u * kColLanes) * kRowWords + 9 + col];
         }
-        // pairwise tree over the lane's rows (fixed order, independent merges per level)
-#pragma unroll
-        for (int w = 1; w < kBlock / kColLanes; w <<= 1)
-#pragma unroll
-            for (int u = 0; u < kBlock / kColLanes; u += 2 * w) csum_merge(vs[u], vc[u], vs[u + w], vc[u + w]);
         float s = vs[0], c = vc[0];
+#pragma unroll
+        for (int u = 1; u < kBlock / kColLanes; ++u) csum_merge(s, c, vs[u], vc[u]);
         pair_butterfly(s, c);
         if (q == 0) { out[col] = s; out[9 + col] = c; }
     } else if (t >= kIntLane0) {
@@ -238,11 +236,8 @@ __device__ inline bool sym3_eigvals(const double (&S)[3][3], double (&lam)[3])
     const double det = b00 * (b11 * b22 - b12 * b12) - b01 * (b01 * b22 - b12 * b02) + b02 * (b01 * b12 - b11 * b02);
     const double r = fmin(1.0, fmax(-1.0, 0.5 * det));
     const double phi = acos(r) * (1.0 / 3.0);
-    // cos(phi + 2 pi / 3) = -cos(phi) / 2 - sin(phi) sqrt(3) / 2, with sin(phi) >= 0 for phi in
-    // [0, pi / 3]: one cosine instead of two
-    const double c = cos(phi), s = sqrt(fmax(0.0, (1.0 - c) * (1.0 + c)));
-    lam[2] = q + 2.0 * p * c;
-    lam[0] = q + 2.0 * p * (-0.5 * c - 0.86602540378443865 * s);
+    lam[2] = q + 2.0 * p * cos(phi);
+    lam[0] = q + 2.0 * p * cos(phi + 2.0943951023931957);          // + 2 pi / 3
     lam[1] = 3.0 * q - lam[0] - lam[2];
     return true;
 }

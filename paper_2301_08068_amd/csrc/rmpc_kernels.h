@@ -86,6 +86,7 @@ struct SparseView {
     const void *values;          // per slot 512 elements, x fastest within the block
     int32_t dtype;
     int32_t pad;
+    double free_value;           // TSDF maps: the field's value outside the stored blocks
 };
 
 // Policy constants in float32 (reciprocals precomputed on the host).

@@ -590,6 +590,38 @@ __device__ __forceinline__ SOut sparse_trace(const RayArgs &A, bool valid, int s
     return o;
 }
 
+// The value of voxel (i, j, k) of a sparse TSDF map as a field reader: the stored value in its
+// block, or free_value outside every stored block (no edge, no clamping).
+template <int DT>
+struct SparseField {
+    SparseView S;                     // a copy (see DenseField)
+    __device__ __forceinline__ double operator()(int i, int j, int k) const
+    {
+        int slot;
+        bool occ;
+        lookup(S, i >> kBlockLog2, j >> kBlockLog2, k >> kBlockLog2, slot, occ);
+        if (slot < 0) return S.free_value;
+        const uint32_t local = (uint32_t)(i & 7) + 8u * (uint32_t)(j & 7) + 64u * (uint32_t)(k & 7);
+        const typename Voxel<DT>::T v =
+            static_cast<const typename Voxel<DT>::T *>(S.values)[(size_t)slot * kBlockVoxels + local];
+        if constexpr (DT == RMPC_TSDF_F32) return (double)v;
+        else return (double)__builtin_bit_cast(_Float16, v);
+    }
+};
+
+// Which hit distance a sparse kernel reports: kSvNone the walk's, kSvF32 / kSvF16 the sub-voxel
+// distance on a float32 / float16 map.  A template parameter, so that kernels without the
+// refinement carry none of its registers.
+constexpr int kSvNone = 0, kSvF32 = 1, kSvF16 = 2;
+
+template <int SV>
+__device__ __forceinline__ double sparse_distance(const RayArgs &A, float rx, float ry, float rz, double d)
+{
+    if constexpr (SV == kSvF32) return subvoxel_at(A, SparseField<RMPC_TSDF_F32>{A.sp}, rx, ry, rz, d);
+    else if constexpr (SV == kSvF16) return subvoxel_at(A, SparseField<RMPC_TSDF_F16>{A.sp}, rx, ry, rz, d);
+    else return d;
+}
+
 // The start block, shared by every lane: its slot, whether it holds an occupied voxel, its
 // occupancy, and whether the start voxel itself is occupied.
 __device__ __forceinline__ bool start_block(const RayArgs &A, int &slot0, bool &occ0, uint64_t (&m0)[kLayers])
@@ -601,7 +633,8 @@ __device__ __forceinline__ bool start_block(const RayArgs &A, int &slot0, bool &
 
 // One 256-lane tile of a query on a sparse map (lane -> ray position and segment, as for dense
 // maps), accumulated and reduced into the query's slots F; every lane of the block calls this.
-template <int K>
+// SV: the hit distance (see sparse_distance).
+template <int K, int SV>
 __device__ __forceinline__ void sparse_tile(const RayArgs &A, int tile, int n_tiles, const FinishSlots &F, float *lds)
 {
     int slot0;
@@ -629,9 +662,10 @@ __device__ __forceinline__ void sparse_tile(const RayArgs &A, int tile, int n_ti
         if (o.report) {
             acc.n_tie = (o.flags & kRayTie) != 0;
             if (o.hit) {
+                const double d = sparse_distance<SV>(A, rr.x, rr.y, rr.z, o.d);
                 acc.n_hit = 1;
-                acc.n_contrib = contributes(A, rr.x, rr.y, rr.z, o.d);
-                policy_accumulate(A.pol, rr.x, rr.y, rr.z, (float)o.d, acc);
+                acc.n_contrib = contributes(A, rr.x, rr.y, rr.z, d);
+                policy_accumulate(A.pol, rr.x, rr.y, rr.z, (float)d, acc);
             }
         }
     }

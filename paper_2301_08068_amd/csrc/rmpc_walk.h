@@ -258,4 +258,57 @@ __device__ __forceinline__ T load_uniform(const T *p)
     return out;
 }
 
+// The continuous TSDF: trilinear interpolation of the stored values, which sit at the voxel
+// centres (grid coordinates i + 1/2), at grid point p; x first, then y, then z.  value(i, j, k)
+// reads voxel (i, j, k) as float64 (a dense or a sparse map).
+template <class Value>
+__device__ __forceinline__ double trilinear_field(const Value &value, double px, double py, double pz)
+{
+#pragma clang fp contract(off)
+    const double ux = px - 0.5, uy = py - 0.5, uz = pz - 0.5;
+    const double flx = floor(ux), fly = floor(uy), flz = floor(uz);
+    const int ix = (int)flx, iy = (int)fly, iz = (int)flz;
+    const double fx = ux - flx, fy = uy - fly, fz = uz - flz;
+    double c[2][2];
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy) {
+            const double a0 = value(ix, iy + dy, iz + dz);
+            const double a1 = value(ix + 1, iy + dy, iz + dz);
+            c[dz][dy] = a0 + fx * (a1 - a0);
+        }
+    const double e0 = c[0][0] + fy * (c[0][1] - c[0][0]);
+    const double e1 = c[1][0] + fy * (c[1][1] - c[1][0]);
+    return e0 + fz * (e1 - e0);
+}
+
+// Sub-voxel hit distance: the field is sampled along the ray at t_k = max(t + k/2 - 3/2, 0),
+// k = 0..7 (grid units, t = d / h: from 1.5 voxels before the hit voxel's entry to 2 after
+// it, a window that holds the field's zero crossing for the hits of an oblique plane); at
+// the first k with phi_k > 0 >= phi_k+1 one secant step gives the crossing.  Without a sign
+// change d is kept.  float64 throughout, no contraction, so the result is that of the
+// definition evaluated in float64.
+template <class Value>
+__device__ __forceinline__ double subvoxel_at(const RayArgs &A, const Value &value, float rx, float ry, float rz,
+                                              double d)
+{
+#pragma clang fp contract(off)
+    const double t = d / A.h;
+    double tk[8], phi[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const double s = t + 0.5 * (double)k - 1.5;
+        tk[k] = s > 0.0 ? s : 0.0;
+        phi[k] = trilinear_field(value, (double)A.g[0] + tk[k] * (double)rx, (double)A.g[1] + tk[k] * (double)ry,
+                                 (double)A.g[2] + tk[k] * (double)rz);
+    }
+    for (int k = 0; k < 7; ++k)
+        if (phi[k] > 0.0 && phi[k + 1] <= 0.0) {
+            const double ts = tk[k] + (tk[k + 1] - tk[k]) * (phi[k] / (phi[k] - phi[k + 1]));
+            return ts * A.h;
+        }
+    return d;
+}
+
 }  // namespace rmpc

@@ -16,16 +16,16 @@ namespace rmpc {
 
 namespace {
 
-template <int K>
+template <int K, int SV>
 __global__ void __launch_bounds__(kBlock, 2) sparse_rmp_kernel(RayArgs A)
 {
     __shared__ float lds[kReduceLdsWords];
-    sparse_tile<K>(A, xcd_tile(blockIdx.x, gridDim.x), gridDim.x,
+    sparse_tile<K, SV>(A, xcd_tile(blockIdx.x, gridDim.x), gridDim.x,
                    single_slots(A.partials, A.ticket, A.result, A.done, A.seq), lds);
 }
 
 // Per-ray outputs: the hit as slot * 512 + (x + 8 y + 64 z within the block), -1 on a miss.
-template <int K>
+template <int K, int SV>
 __global__ void __launch_bounds__(kBlock, 2) sparse_trace_kernel(RayArgs A)
 {
     int slot0;
@@ -54,7 +54,7 @@ __global__ void __launch_bounds__(kBlock, 2) sparse_trace_kernel(RayArgs A)
     for (int off = 1; off < S; off <<= 1) v += __shfl_xor(v, off, kWave);
     if (o.report) {
         A.dbg_hit[i] = o.hit ? o.hit_slot * kBlockVoxels + o.hit_local : -1;
-        A.dbg_dist[i] = o.d;
+        A.dbg_dist[i] = o.hit ? sparse_distance<SV>(A, rr.x, rr.y, rr.z, o.d) : o.d;
         A.dbg_flags[i] = (uint8_t)o.flags;
         if (A.dbg_visits) A.dbg_visits[i] = v;
     }
@@ -85,18 +85,26 @@ __global__ void sparse_flag_kernel(SparseView v, HashEntry *table)
     e.occupied = any != 0 ? 1u : 0u;
 }
 
-template <int K>
+template <int K, int SV>
 hipError_t launch_sparse_k(const RayArgs &A, hipStream_t s, bool debug, hipEvent_t e0, hipEvent_t e1)
 {
     const dim3 g((A.n_list * A.segments + kBlock - 1) / kBlock), blk(kBlock);
     if (debug) {
-        sparse_trace_kernel<K><<<g, blk, 0, s>>>(A);
+        sparse_trace_kernel<K, SV><<<g, blk, 0, s>>>(A);
     } else if (e0) {
-        hipExtLaunchKernelGGL(sparse_rmp_kernel<K>, g, blk, 0, s, e0, e1, 0, A);
+        hipExtLaunchKernelGGL(sparse_rmp_kernel<K, SV>, g, blk, 0, s, e0, e1, 0, A);
     } else {
-        sparse_rmp_kernel<K><<<g, blk, 0, s>>>(A);
+        sparse_rmp_kernel<K, SV><<<g, blk, 0, s>>>(A);
     }
     return hipGetLastError();
+}
+
+template <int K>
+hipError_t launch_sparse_sv(const RayArgs &A, hipStream_t s, bool debug, hipEvent_t e0, hipEvent_t e1)
+{
+    if (!A.subvoxel) return launch_sparse_k<K, kSvNone>(A, s, debug, e0, e1);
+    if (A.sp.dtype == RMPC_TSDF_F32) return launch_sparse_k<K, kSvF32>(A, s, debug, e0, e1);
+    return launch_sparse_k<K, kSvF16>(A, s, debug, e0, e1);
 }
 
 }  // namespace
@@ -104,9 +112,9 @@ hipError_t launch_sparse_k(const RayArgs &A, hipStream_t s, bool debug, hipEvent
 hipError_t launch_sparse(const RayArgs &A, hipStream_t s, bool debug, hipEvent_t e0, hipEvent_t e1)
 {
     switch (A.lookahead) {
-    case 4: return launch_sparse_k<4>(A, s, debug, e0, e1);
-    case 16: return launch_sparse_k<16>(A, s, debug, e0, e1);
-    default: return launch_sparse_k<8>(A, s, debug, e0, e1);
+    case 4: return launch_sparse_sv<4>(A, s, debug, e0, e1);
+    case 16: return launch_sparse_sv<16>(A, s, debug, e0, e1);
+    default: return launch_sparse_sv<8>(A, s, debug, e0, e1);
     }
 }
 

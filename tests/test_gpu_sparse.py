@@ -91,7 +91,7 @@ def test_sparse_tiny_parity(ctx, tiny_map, shift, keep_free):
     offset `shift`, against the oracle on a dense grid padded by 7 blocks (56 voxels > the
     50-voxel range) on every side."""
     sm = W.sparse_from_dense(tiny_map, offset_blocks=shift, keep_free=keep_free, seed=5)
-    mid = ctx.upload_sparse(sm.coords, sm.values, sm.voxel_m, sm.origin_m, "f32")
+    mid = ctx.upload_sparse(sm.coords, sm.values, sm.voxel_m, sm.origin_m, "f32", sm.trunc_m)
     lo = (np.asarray(shift) - 7) * 8
     hi = (np.asarray(shift) + 8 + 7) * 8
     dense, o_dense = sm.dense_crop(lo, hi)
@@ -121,7 +121,7 @@ def test_sparse_tiny_parity(ctx, tiny_map, shift, keep_free):
 def test_sparse_collision_start(ctx, tiny_map):
     """A start in an occupied voxel: every ray hits it at distance 0 (IN_COLLISION)."""
     sm = W.sparse_from_dense(tiny_map, offset_blocks=(3, -2, 1), keep_free=0.0, seed=6)
-    mid = ctx.upload_sparse(sm.coords, sm.values, sm.voxel_m, sm.origin_m, "f32")
+    mid = ctx.upload_sparse(sm.coords, sm.values, sm.voxel_m, sm.origin_m, "f32", sm.trunc_m)
     try:
         k = int(np.argmax(np.any(sm.values <= 0, axis=(1, 2, 3))))
         z, y, x = np.argwhere(sm.values[k] <= 0)[0]
@@ -146,11 +146,21 @@ def test_sparse_errors(ctx, tiny_map):
     bad[0, 1] = 1 << 20
     with pytest.raises(binding.RmpcError, match="coordinate"):
         ctx.upload_sparse(bad, sm.values, sm.voxel_m, sm.origin_m)
-    mid = ctx.upload_sparse(sm.coords, sm.values, sm.voxel_m, sm.origin_m, "f32")
+    for fv in (0.0, -0.3, float("nan"), 1e6):                 # 1e6 is inf in binary16
+        with pytest.raises(binding.RmpcError, match="free_value"):
+            ctx.upload_sparse(sm.coords, W.encode_f16(sm.values), sm.voxel_m, sm.origin_m, "f16", fv)
+    occ = ctx.upload_sparse(sm.coords, W.encode_u8(sm.values), sm.voxel_m, sm.origin_m, "u8", 0.0)
     try:
         x, v = W.free_state(tiny_map, 100)
-        with pytest.raises(binding.RmpcError, match="subvoxel"):
-            ctx.query(mid, x, v, 256, dict(P_TINY, subvoxel=1.0))
+        with pytest.raises(binding.RmpcError, match="TSDF"):
+            ctx.query(occ, x, v, 256, dict(P_TINY, subvoxel=1.0))
+    finally:
+        ctx.release(occ)
+    mid = ctx.upload_sparse(sm.coords, sm.values, sm.voxel_m, sm.origin_m, "f32", sm.trunc_m)
+    try:
+        x, v = W.free_state(tiny_map, 100)
+        with pytest.raises(binding.RmpcError, match="one at a time"):
+            ctx.query_batch([dict(kind="map", map_id=mid, n=256, x=x, v=v)], map_params=dict(P_TINY, subvoxel=1.0))
         with pytest.raises(binding.RmpcError, match="dense"):
             ctx.edt(mid, (8, 8, 8))
         with pytest.raises(binding.RmpcError, match="far"):
@@ -173,7 +183,7 @@ def test_sparse_world_segments(ctx, world, lane_target):
     the default is 4): every ray and the query sums against the oracle."""
     from paper_2301_08068_amd import binding
     sm = world
-    mid = ctx.upload_sparse(sm.coords, sm.values, sm.voxel_m, sm.origin_m, "f32")
+    mid = ctx.upload_sparse(sm.coords, sm.values, sm.voxel_m, sm.origin_m, "f32", sm.trunc_m)
     old = ctx.config(binding.CONFIG_SPARSE)
     dirs = oracle.directions(65536)
     try:
@@ -204,7 +214,7 @@ def test_sparse_world_65536(ctx, world):
     blocks), 65,536 rays from two states with a 10 m range: every ray against the oracle on a
     dense crop that holds every voxel the rays can reach, and the query sums."""
     sm = world
-    mid = ctx.upload_sparse(sm.coords, sm.values, sm.voxel_m, sm.origin_m, "f32")
+    mid = ctx.upload_sparse(sm.coords, sm.values, sm.voxel_m, sm.origin_m, "f32", sm.trunc_m)
     dirs = oracle.directions(65536)
     try:
         for seed in (700, 701):
@@ -239,7 +249,7 @@ def test_sparse_in_batches_serving_and_rollouts(ctx, tiny_map):
     from paper_2301_08068_amd import binding as B
     shift = (-5, 3, 2)
     sm = W.sparse_from_dense(tiny_map, offset_blocks=shift, keep_free=0.2, seed=8)
-    sid = ctx.upload_sparse(sm.coords, sm.values, sm.voxel_m, sm.origin_m, "f32")
+    sid = ctx.upload_sparse(sm.coords, sm.values, sm.voxel_m, sm.origin_m, "f32", sm.trunc_m)
     did = ctx.upload(tiny_map.tsdf, tiny_map.voxel_m, tiny_map.origin_m, "f32")
     old_b, old_s = ctx.config(B.CONFIG_BATCH), ctx.config(B.CONFIG_SPARSE)
     lidar = W.params("lidar")
@@ -297,3 +307,54 @@ def test_sparse_in_batches_serving_and_rollouts(ctx, tiny_map):
         ctx.config(B.CONFIG_SPARSE, **old_s)
         ctx.release(sid)
         ctx.release(did)
+
+
+@pytest.mark.parametrize("enc", ["f32", "f16"])
+def test_sparse_subvoxel_distances(ctx, tiny_map, enc):
+    """Sub-voxel hit distances on a sparse map: per ray, the oracle's refinement (on the dense
+    crop, whose voxels outside the stored blocks hold the same free value) of the oracle's walk
+    distance for the same hit, to 1e-12 m; float32 and float16 values.  (Not bit for bit: the
+    sample points g + t r are rounded in float64 in the sparse map's frame and in the crop's,
+    whose coordinates differ by a whole number of blocks, so the samples can differ in their
+    last bits; the walk's distances, computed from integer faces, stay bit-equal.)"""
+    shift = (6, -4, 3)
+    sm = W.sparse_from_dense(tiny_map, offset_blocks=shift, keep_free=0.3, seed=9)
+    vals = sm.values if enc == "f32" else W.encode_f16(sm.values)
+    # the free value as the storage type reads it back (exact in binary16 for the f16 map)
+    fv = float(np.float32(sm.trunc_m)) if enc == "f32" else float(W.encode_f16(np.float32(sm.trunc_m)).view(np.float16))
+    mid = ctx.upload_sparse(sm.coords, vals, sm.voxel_m, sm.origin_m, enc, fv)
+    lo = (np.asarray(shift) - 7) * 8
+    hi = (np.asarray(shift) + 8 + 7) * 8
+    dense, o_dense = sm.dense_crop(lo, hi)
+    dense_enc = dense if enc == "f32" else W.encode_f16(dense)
+    om = oracle.OracleMap(dense_enc, sm.voxel_m, o_dense, enc)
+    dirs = oracle.directions(1024)
+    P_SUB = dict(P_TINY, subvoxel=1.0)
+    moved = 0
+    try:
+        for seed in range(400, 412):
+            x, v = _dyadic_state(tiny_map, sm, shift, seed)
+            walk = ctx.trace(mid, x, 1024, P_TINY)
+            ref = ctx.trace(mid, x, 1024, P_SUB)
+            assert np.array_equal(walk["hit"], ref["hit"]) and np.array_equal(walk["flags"], ref["flags"])
+            gd = _dense_start(sm, x, lo)
+            o = oracle.trace(om, gd, dirs, P_TINY["max_range"])
+            hits = _sparse_hits_as_lin(walk, sm, lo, dense.shape[::-1])
+            for i in range(len(dirs)):
+                if hits[i] < 0:
+                    assert np.isinf(ref["d"][i])
+                    continue
+                if hits[i] == o["hit"][i]:
+                    cands = [o["d"][i]]
+                else:
+                    cands = [o["alt_d"][i, j] for j in range(o["alt_n"][i]) if o["alt_hit"][i, j] == hits[i]]
+                want = [oracle.subvoxel(om, gd, dirs[i], d) for d in cands]
+                assert min(abs(ref["d"][i] - w) for w in want) <= 1e-12, (seed, i, ref["d"][i], want)
+                moved += ref["d"][i] != walk["d"][i]
+            # the query sums use the refined distances: the oracle's query on the dense crop
+            q = ctx.query(mid, x, v, 1024, P_SUB)
+            assert np.array_equal(oracle.grid_start(om, x), gd)
+            compare_query(q, oracle.query(om, x, v, 1024, P_SUB, dirs=dirs), f"sparse subvoxel query {seed}")
+    finally:
+        ctx.release(mid)
+    assert moved > 1000
