@@ -92,8 +92,7 @@ struct Acc {
 // one compensated pair each and four groups in the last wave (threads 192..255) add one
 // integer counter each, so no wave mixes the two kinds.  Lane q of a group merges rows q,
 // q+16, ... in row order (all 16 loaded first), and the 16 lanes combine with a butterfly
-// that always puts the lower lane first.  (A pairwise tree over the 16 rows was no faster
-// and made the batch kernel, at its register budget, spill.)  Every step has a fixed order, so results do not
+// that always puts the lower lane first.  (A pairwise tree over the 16 rows was no faster.)  Every step has a fixed order, so results do not
 // depend on timing.
 // ------------------------------------------------------------------------------------
 
