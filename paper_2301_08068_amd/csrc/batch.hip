@@ -38,15 +38,20 @@ __global__ void stream_touch_kernel(uint32_t *w)
 
 }  // namespace
 
+// The header and the query descriptors of a launch sit in one block (the header padded to 256
+// bytes), on the device and in pinned host memory, so that one copy sends both.
+constexpr size_t kDescHead = 256;
+static_assert(sizeof(rmpc::BatchHeader) <= kDescHead, "the header fits its 256 bytes");
+
 rmpc_status slot_create(rmpc_ctx *ctx, LaunchSlot &slot, int max_queries, int max_tiles)
 {
     slot = LaunchSlot();
     const size_t rows = (size_t)max_tiles;
     const size_t tk_bytes = sizeof(uint32_t) * (size_t)max_queries;
-    const size_t sizes[5] = {sizeof(rmpc::BatchHeader), sizeof(rmpc::BatchQuery) * (size_t)max_queries, 256,
-                             tk_bytes, sizeof(float) * rmpc::kPartialWords * rows};
-    size_t off[5];
-    for (int i = 0; i < 5; ++i) {
+    const size_t desc_bytes = kDescHead + sizeof(rmpc::BatchQuery) * (size_t)max_queries;
+    const size_t sizes[4] = {desc_bytes, 256, tk_bytes, sizeof(float) * rmpc::kPartialWords * rows};
+    size_t off[4];
+    for (int i = 0; i < 4; ++i) {
         if (!ctx->alloc.alloc(sizes[i], &off[i])) {
             for (size_t o : slot.arena_offsets) ctx->alloc.release(o);
             slot.arena_offsets.clear();
@@ -57,28 +62,28 @@ rmpc_status slot_create(rmpc_ctx *ctx, LaunchSlot &slot, int max_queries, int ma
     slot.max_queries = max_queries;
     slot.max_tiles = max_tiles;
     slot.hdr = reinterpret_cast<rmpc::BatchHeader *>(ctx->arena + off[0]);
-    slot.q = reinterpret_cast<rmpc::BatchQuery *>(ctx->arena + off[1]);
-    slot.work = reinterpret_cast<uint32_t *>(ctx->arena + off[2]);
-    slot.tickets = reinterpret_cast<uint32_t *>(ctx->arena + off[3]);
-    slot.partials = reinterpret_cast<float *>(ctx->arena + off[4]);
+    slot.q = reinterpret_cast<rmpc::BatchQuery *>(ctx->arena + off[0] + kDescHead);
+    slot.work = reinterpret_cast<uint32_t *>(ctx->arena + off[1]);
+    slot.tickets = reinterpret_cast<uint32_t *>(ctx->arena + off[2]);
+    slot.partials = reinterpret_cast<float *>(ctx->arena + off[3]);
     RMPC_HIP(hipMemset(slot.work, 0, 256));
     RMPC_HIP(hipMemset(slot.tickets, 0, tk_bytes));
     RMPC_HIP(hipHostMalloc(reinterpret_cast<void **>(&slot.results_host),
                            sizeof(rmpc_result) * (size_t)max_queries, hipHostMallocCoherent));
     RMPC_HIP(hipHostMalloc(reinterpret_cast<void **>(&slot.done_host), 64, hipHostMallocCoherent));
     *slot.done_host = 0;
-    RMPC_HIP(hipHostMalloc(reinterpret_cast<void **>(&slot.hdr_host), sizeof(rmpc::BatchHeader), 0));
-    RMPC_HIP(hipHostMalloc(reinterpret_cast<void **>(&slot.q_host), sizeof(rmpc::BatchQuery) * (size_t)max_queries, 0));
+    uint8_t *desc_host = nullptr;
+    RMPC_HIP(hipHostMalloc(reinterpret_cast<void **>(&desc_host), desc_bytes, 0));
+    slot.hdr_host = reinterpret_cast<rmpc::BatchHeader *>(desc_host);
+    slot.q_host = reinterpret_cast<rmpc::BatchQuery *>(desc_host + kDescHead);
     RMPC_HIP(hipStreamCreateWithFlags(&slot.stream, hipStreamNonBlocking));
     RMPC_HIP(hipEventCreateWithFlags(&slot.ev, hipEventDisableTiming));
     // a first kernel and first copies (a small one and one of every descriptor, the size of a
     // scan's points) on the new stream, so that the runtime sets up its queues now and not under
     // the first batches (a serving slot's first launches would wait)
-    std::memset(slot.hdr_host, 0, sizeof(rmpc::BatchHeader));
-    std::memset(slot.q_host, 0, sizeof(rmpc::BatchQuery) * (size_t)max_queries);
+    std::memset(desc_host, 0, desc_bytes);
     RMPC_HIP(hipMemcpyAsync(slot.hdr, slot.hdr_host, sizeof(rmpc::BatchHeader), hipMemcpyHostToDevice, slot.stream));
-    RMPC_HIP(hipMemcpyAsync(slot.q, slot.q_host, sizeof(rmpc::BatchQuery) * (size_t)max_queries, hipMemcpyHostToDevice,
-                            slot.stream));
+    RMPC_HIP(hipMemcpyAsync(slot.hdr, desc_host, desc_bytes, hipMemcpyHostToDevice, slot.stream));
     stream_touch_kernel<<<1, 64, 0, slot.stream>>>(slot.work);
     RMPC_HIP(hipGetLastError());
     RMPC_HIP(hipStreamSynchronize(slot.stream));
@@ -93,8 +98,7 @@ void slot_destroy(rmpc_ctx *ctx, LaunchSlot &slot)
     if (slot.stream) (void)hipStreamDestroy(slot.stream);
     if (slot.results_host) (void)hipHostFree(slot.results_host);
     if (slot.done_host) (void)hipHostFree(slot.done_host);
-    if (slot.hdr_host) (void)hipHostFree(slot.hdr_host);
-    if (slot.q_host) (void)hipHostFree(slot.q_host);
+    if (slot.hdr_host) (void)hipHostFree(slot.hdr_host);      // the descriptor block (q_host lies in it)
     for (size_t o : slot.arena_offsets) ctx->alloc.release(o);
     slot = LaunchSlot();
 }
@@ -199,8 +203,9 @@ rmpc_status slot_launch(rmpc_ctx *ctx, LaunchSlot &slot, int nq, int n_tiles,
         if (rmpc_status st = slot_graph(ctx, slot, cfg)) return st;
     }
     if (after) RMPC_HIP(hipStreamWaitEvent(s, after, 0));
-    RMPC_HIP(hipMemcpyAsync(slot.hdr, slot.hdr_host, sizeof(rmpc::BatchHeader), hipMemcpyHostToDevice, s));
-    RMPC_HIP(hipMemcpyAsync(slot.q, slot.q_host, sizeof(rmpc::BatchQuery) * (size_t)nq, hipMemcpyHostToDevice, s));
+    // header and descriptors in one copy
+    RMPC_HIP(hipMemcpyAsync(slot.hdr, slot.hdr_host, kDescHead + sizeof(rmpc::BatchQuery) * (size_t)nq,
+                            hipMemcpyHostToDevice, s));
     if (cfg.use_graph) {
         RMPC_HIP(hipGraphLaunch(slot.graph, s));
     } else {

@@ -49,8 +49,8 @@ struct LaunchSlot {
     uint32_t *work = nullptr;                // device
     uint32_t *tickets = nullptr;             // device
     float *partials = nullptr;               // device
-    rmpc::BatchHeader *hdr_host = nullptr;   // pinned
-    rmpc::BatchQuery *q_host = nullptr;      // pinned
+    rmpc::BatchHeader *hdr_host = nullptr;   // pinned: the header, then (256 bytes on) q_host,
+    rmpc::BatchQuery *q_host = nullptr;      //   as hdr and q lie on the device (one copy)
     rmpc_result *results_host = nullptr;     // pinned, written by the kernel
     uint64_t *done_host = nullptr;           // pinned completion word
     uint64_t seq = 0;
