@@ -76,11 +76,16 @@ rmpc_status slot_create(rmpc_ctx *ctx, LaunchSlot &slot, int max_queries, int ma
     RMPC_HIP(hipHostMalloc(reinterpret_cast<void **>(&desc_host), desc_bytes, 0));
     slot.hdr_host = reinterpret_cast<rmpc::BatchHeader *>(desc_host);
     slot.q_host = reinterpret_cast<rmpc::BatchQuery *>(desc_host + kDescHead);
-    RMPC_HIP(hipStreamCreateWithFlags(&slot.stream, hipStreamNonBlocking));
+    if (!ctx->stream_pool.empty()) {
+        slot.stream = ctx->stream_pool.back();
+        ctx->stream_pool.pop_back();
+    } else {
+        RMPC_HIP(hipStreamCreateWithFlags(&slot.stream, hipStreamNonBlocking));
+    }
     RMPC_HIP(hipEventCreateWithFlags(&slot.ev, hipEventDisableTiming));
-    // a first kernel and first copies (a small one and one of every descriptor, the size of a
-    // scan's points) on the new stream, so that the runtime sets up its queues now and not under
-    // the first batches (a serving slot's first launches would wait)
+    // a first kernel and first copies (the header alone and the whole descriptor block) on the
+    // new stream, so that the runtime sets up its queues now and not under the first batches (a
+    // serving slot's first launches would wait)
     std::memset(desc_host, 0, desc_bytes);
     RMPC_HIP(hipMemcpyAsync(slot.hdr, slot.hdr_host, sizeof(rmpc::BatchHeader), hipMemcpyHostToDevice, slot.stream));
     RMPC_HIP(hipMemcpyAsync(slot.hdr, desc_host, desc_bytes, hipMemcpyHostToDevice, slot.stream));
@@ -95,7 +100,7 @@ void slot_destroy(rmpc_ctx *ctx, LaunchSlot &slot)
     if (slot.stream) (void)hipStreamSynchronize(slot.stream);
     if (slot.graph) (void)hipGraphExecDestroy(slot.graph);
     if (slot.ev) (void)hipEventDestroy(slot.ev);
-    if (slot.stream) (void)hipStreamDestroy(slot.stream);
+    if (slot.stream) ctx->stream_pool.push_back(slot.stream);
     if (slot.results_host) (void)hipHostFree(slot.results_host);
     if (slot.done_host) (void)hipHostFree(slot.done_host);
     if (slot.hdr_host) (void)hipHostFree(slot.hdr_host);      // the descriptor block (q_host lies in it)

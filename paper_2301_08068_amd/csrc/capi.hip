@@ -489,6 +489,7 @@ rmpc_status rmpc_destroy(rmpc_ctx *ctx)
     server_destroy(ctx);
     (void)hipDeviceSynchronize();
     slot_destroy(ctx, ctx->batch);
+    for (hipStream_t st : ctx->stream_pool) (void)hipStreamDestroy(st);
     (void)hipHostFree(ctx->result_host);
     (void)hipHostFree(ctx->done_host);
     if (ctx->ev_dep) (void)hipEventDestroy(ctx->ev_dep);

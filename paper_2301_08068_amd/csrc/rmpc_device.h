@@ -113,13 +113,13 @@ __device__ __forceinline__ void row_store(float *row, const Acc &a)
 
 // Butterfly over the 16 lanes of a pair group; the lower lane's value is always the left
 // operand of the merge.
-__device__ __forceinline__ void pair_butterfly(float &s, float &c)
+__device__ __forceinline__ void pair_butterfly(int t, float &s, float &c)
 {
 #pragma unroll
     for (int off = 1; off < kColLanes; off <<= 1) {
         const float s2 = __shfl_xor(s, off, kWave);
         const float c2 = __shfl_xor(c, off, kWave);
-        const bool upper = (threadIdx.x & off) != 0;
+        const bool upper = (t & off) != 0;
         float ls = upper ? s2 : s, lc = upper ? c2 : c;
         csum_merge(ls, lc, upper ? s : s2, upper ? c : c2);
         s = ls;
@@ -134,12 +134,22 @@ __device__ __forceinline__ int32_t int_butterfly(int32_t v)
     return v;
 }
 
+// The thread index through an empty asm statement.  The reductions' LDS addresses and lane
+// masks depend on it alone, and in a kernel that loops over tiles the compiler would otherwise
+// compute them once before the loop and keep them in registers through every walk.
+__device__ __forceinline__ int opaque_tid()
+{
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
 // The block total, written to out[] in partial layout (9 sums, 9 compensations, 4 counters).
 __device__ __forceinline__ void block_reduce_store(const Acc &a, float *lds, float *out)
 {
-    row_store(lds + threadIdx.x * kRowWords, a);
+    const int t = opaque_tid(), q = t % kColLanes;
+    row_store(lds + t * kRowWords, a);
     __syncthreads();
-    const int t = threadIdx.x, q = t % kColLanes;
     if (t < kPairLanes) {
         const int col = t / kColLanes;
         float vs[kBlock / kColLanes], vc[kBlock / kColLanes];
@@ -151,7 +161,7 @@ __device__ __forceinline__ void block_reduce_store(const Acc &a, float *lds, flo
         float s = vs[0], c = vc[0];
 #pragma unroll
         for (int u = 1; u < kBlock / kColLanes; ++u) csum_merge(s, c, vs[u], vc[u]);
-        pair_butterfly(s, c);
+        pair_butterfly(t, s, c);
         if (q == 0) { out[col] = s; out[9 + col] = c; }
     } else if (t >= kIntLane0) {
         const int col = (t - kIntLane0) / kColLanes;
@@ -409,7 +419,7 @@ __device__ inline void grid_finish(const Acc &a, int b, int nb, const FinishSlot
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     Acc m;
     m.zero();
-    for (int r0 = threadIdx.x; r0 < nb; r0 += 2 * kBlock) {
+    for (int r0 = opaque_tid(); r0 < nb; r0 += 2 * kBlock) {
         // two rows per pass, both loaded before either is merged
         Acc r1, r2;
         acc_from_partial(F.tile_rows + (size_t)r0 * kPartialWords, r1);
@@ -423,10 +433,10 @@ __device__ inline void grid_finish(const Acc &a, int b, int nb, const FinishSlot
     block_reduce_store(m, lds, tot);
     __syncthreads();
     if (threadIdx.x == 0) {
-        Acc t;
-        acc_from_partial(tot, t);
+        Acc total;
+        acc_from_partial(tot, total);
         __hip_atomic_store(F.tickets, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        finalize_result(t, rank_tol, n_rays, extra_flags, F.out);
+        finalize_result(total, rank_tol, n_rays, extra_flags, F.out);
         bool publish = true;
         if (F.finished) {
             // system scope: every query's result reaches the host before the publication

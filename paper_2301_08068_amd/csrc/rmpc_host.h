@@ -95,6 +95,10 @@ struct rmpc_ctx {
     rmpc_launch_config cfg[3];  // RMPC_CONFIG_QUERY, RMPC_CONFIG_BATCH, RMPC_CONFIG_SPARSE
     int cu_count;
     rmpc_host::LaunchSlot batch;          // rmpc_query_batch (allocated on first use)
+    // streams of destroyed launch slots, kept for the next slots: a server that is stopped and
+    // started again reuses them (creating streams again and again made a later server's first
+    // copies under load wait ~8 ms for the runtime)
+    std::vector<hipStream_t> stream_pool;
     hipEvent_t ev_dep;
     rmpc_host::ServerState *server;       // serving loop (rmpc_server_start)
     // kernel timing (rmpc_set_profiling)

@@ -29,6 +29,8 @@ constexpr int kMaxSlots = 8;
 constexpr int kDefaultPending = 65536;
 constexpr double kLaunchTimeoutS = 60.0;
 constexpr std::chrono::microseconds kIdleWatch(1000);   // queue watch before the server thread sleeps
+constexpr size_t kWarmPieceBytes = size_t(64) << 10;    // one warm-up copy (up to the staging size)
+constexpr int kWarmDepthMax = 1024;                      // warm-up copies queued per stream
 
 // A request between rmpc_submit and its launch.
 struct Req {
@@ -120,6 +122,62 @@ void collect(ServerState *S, Slot &sl, Clock::time_point now)
     rmpc_sched::release_launch(sl.members, S->stage_alloc);
     sl.members.clear();
     sl.busy = false;
+}
+
+// Spins for `ticks` of the GPU's constant-rate clock (and at most 2^24 iterations).
+__global__ void warm_spin_kernel(uint64_t ticks)
+{
+    const uint64_t t0 = wall_clock64();
+    for (uint32_t n = 0; n < (1u << 24) && wall_clock64() - t0 < ticks; ++n) {
+    }
+}
+
+// Before the server takes requests, every slot's stream does once what serving makes it do, so
+// that the runtime grows its per-stream state now and not under load, where each growth held
+// the server thread for milliseconds while requests queued behind it:
+//  * copies from pinned host memory queued deep behind a running kernel, to twice the depth that
+//    a launch of max_batch scans makes (measured: the first time a stream held more than about
+//    four outstanding copies, and a few times after as the depth rose, one copy call took
+//    6-11 ms; at a constant depth, never again);
+//  * an empty batch launch (no queries, no tiles: every block leaves at once), as the first
+//    launch of the batch kernel in a process took ~3 ms;
+//  * a device-to-device copy and a fill.
+rmpc_status warm_slots(rmpc_ctx *ctx, ServerState *S)
+{
+    const size_t stage = S->cfg.staging_bytes / kAlign * kAlign;
+    if (stage) {
+        const size_t piece = std::min<size_t>(stage, kWarmPieceBytes);
+        const size_t n_pieces = stage / piece;
+        const int depth = std::min(2 * (S->cfg.max_batch + 1), kWarmDepthMax);
+        void *h = nullptr;
+        RMPC_HIP(hipHostMalloc(&h, piece, 0));
+        hipError_t e = hipSuccess;
+        for (int round = 0; round < 3 && e == hipSuccess; ++round) {
+            for (int i = 0; i < S->n_slots && e == hipSuccess; ++i) {
+                warm_spin_kernel<<<1, 64, 0, S->slots[i].ls.stream>>>(20000);   // 200 us at 100 MHz
+                e = hipGetLastError();
+            }
+            for (int k = 0; k < depth && e == hipSuccess; ++k)
+                for (int i = 0; i < S->n_slots && e == hipSuccess; ++i)
+                    e = hipMemcpyAsync(S->staging + piece * ((size_t)k % n_pieces), h, piece,
+                                       hipMemcpyHostToDevice, S->slots[i].ls.stream);
+            for (int i = 0; i < S->n_slots && e == hipSuccess; ++i) e = hipStreamSynchronize(S->slots[i].ls.stream);
+        }
+        (void)hipHostFree(h);
+        if (e != hipSuccess) return fail(RMPC_E_HIP, std::string("server warm-up: ") + hipGetErrorString(e));
+    }
+    for (int i = 0; i < S->n_slots; ++i) {
+        LaunchSlot &ls = S->slots[i].ls;
+        if (ls.graph) RMPC_HIP(hipGraphUpload(ls.graph, ls.stream));
+        uint64_t seq = 0;
+        if (rmpc_status st = slot_launch(ctx, ls, 0, 0, S->cfg.launch, nullptr, &seq)) return st;
+        // the tile rows are written before they are read: their contents do not matter
+        RMPC_HIP(hipMemcpyAsync(ls.partials + rmpc::kPartialWords, ls.partials, sizeof(float) * rmpc::kPartialWords,
+                                hipMemcpyDeviceToDevice, ls.stream));
+        RMPC_HIP(hipMemsetAsync(ls.partials, 0, sizeof(float) * rmpc::kPartialWords, ls.stream));
+        RMPC_HIP(hipStreamSynchronize(ls.stream));
+    }
+    return RMPC_OK;
 }
 
 // Copies of host points and the launch of a formed batch on slot sl (server thread).
@@ -312,6 +370,11 @@ rmpc_status rmpc_server_start(rmpc_ctx *ctx, const rmpc_server_config *cfg)
             server_destroy(ctx);
             return fail(st, msg);
         }
+    }
+    if (rmpc_status st = warm_slots(ctx, S)) {
+        const std::string msg = g_last_error;
+        server_destroy(ctx);
+        return fail(st, msg);
     }
     S->th = std::thread(server_loop, ctx, S);
     return RMPC_OK;
