@@ -390,8 +390,12 @@ typedef struct {
 
 /*
  * rmpc_server_start -- start the serving loop on this context.  Slots, their buffers and the
- * staging memory come from the arena.  Errors: RMPC_E_INVALID (bad config, already running),
- * RMPC_E_NOMEM (arena too small), RMPC_E_HIP.
+ * staging memory come from the arena.  Before it returns, every slot's stream makes copies
+ * from pinned host memory into the staging memory (queued up to twice the depth of a launch of
+ * max_batch scans, at most 1,024) and one empty launch, so that the runtime's one-time set-up
+ * of a stream does not delay served requests; this takes milliseconds.  Slot streams stay with
+ * the context after rmpc_server_stop and serve the next server.  Errors: RMPC_E_INVALID (bad
+ * config, already running), RMPC_E_NOMEM (arena too small), RMPC_E_HIP.
  */
 rmpc_status rmpc_server_start(rmpc_ctx *ctx, const rmpc_server_config *cfg);
 
