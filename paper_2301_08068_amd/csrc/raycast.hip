@@ -636,29 +636,41 @@ __device__ __forceinline__ void ray_tile(const RayArgs &A, int tile, int n_tiles
 
 // One tile of a LiDAR scan query (Sec. III-G): point p gives direction p/|p| and distance
 // |p|; non-finite points and points closer than min_range are skipped.  Tile t covers points
-// t*256 + lane + k * n_tiles * 256.
+// t*256 + lane + k * n_tiles * 256, which a thread takes in increasing k.  A thread loads
+// kScanBatch of its points before it evaluates the first, so that their loads wait once.
 __device__ __forceinline__ void scan_tile(const ScanArgs &A, int tile, int n_tiles, const FinishSlots &F,
                                           float *lds)
 {
     Acc acc;
     acc.zero();
     const int stride = n_tiles * kBlock;
-    for (int i = tile * kBlock + threadIdx.x; i < A.n_points; i += stride) {
-        const float px = A.points[3 * (size_t)i], py = A.points[3 * (size_t)i + 1],
-                    pz = A.points[3 * (size_t)i + 2];
-        if (!(isfinite(px) && isfinite(py) && isfinite(pz))) continue;
-        double n2, vp;
-        {
-#pragma clang fp contract(off)
-            n2 = ((double)px * (double)px + (double)py * (double)py) + (double)pz * (double)pz;
-            vp = (A.vel64[0] * (double)px + A.vel64[1] * (double)py) + A.vel64[2] * (double)pz;
+    for (int i0 = tile * kBlock + threadIdx.x; i0 < A.n_points; i0 += kScanBatch * stride) {
+        float p[kScanBatch][3];
+#pragma unroll
+        for (int k = 0; k < kScanBatch; ++k) {
+            const int i = i0 + k * stride;
+            const size_t j = i < A.n_points ? 3 * (size_t)i : 0;      // past the end: point 0, unused
+            p[k][0] = A.points[j];
+            p[k][1] = A.points[j + 1];
+            p[k][2] = A.points[j + 2];
         }
-        if (!(n2 >= A.min_range2)) continue;
-        const double d64 = sqrt(n2);
-        const float inv = (float)(1.0 / d64);
-        acc.n_hit += 1;
-        acc.n_contrib += d64 < A.radius64 && vp > 0.0;
-        policy_accumulate(A.pol, px * inv, py * inv, pz * inv, (float)d64, acc);
+#pragma unroll
+        for (int k = 0; k < kScanBatch; ++k) {
+            const float px = p[k][0], py = p[k][1], pz = p[k][2];
+            if (i0 + k * stride >= A.n_points || !(isfinite(px) && isfinite(py) && isfinite(pz))) continue;
+            double n2, vp;
+            {
+#pragma clang fp contract(off)
+                n2 = ((double)px * (double)px + (double)py * (double)py) + (double)pz * (double)pz;
+                vp = (A.vel64[0] * (double)px + A.vel64[1] * (double)py) + A.vel64[2] * (double)pz;
+            }
+            if (!(n2 >= A.min_range2)) continue;
+            const double d64 = sqrt(n2);
+            const float inv = (float)(1.0 / d64);
+            acc.n_hit += 1;
+            acc.n_contrib += d64 < A.radius64 && vp > 0.0;
+            policy_accumulate(A.pol, px * inv, py * inv, pz * inv, (float)d64, acc);
+        }
     }
     grid_finish(acc, tile, n_tiles, F, A.rank_tol, A.n_points, 0u, lds);
 }

@@ -24,6 +24,7 @@ constexpr int kPartialWords = 32;
 // Blocks of one scan query (each block's ticket costs a release/acquire, so the points are
 // looped over instead of adding blocks).
 constexpr int kScanMaxBlocks = 128;
+constexpr int kScanBatch = 8;                // scan points a thread loads before it evaluates them
 
 // A resident map: the voxel grid x-fastest (element offset x + nx (y + ny z)), then, at
 // element offset cell_base, one summary element per cell of 8 x 8 x 8 voxels, also x-fastest:
