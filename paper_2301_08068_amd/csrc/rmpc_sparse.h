@@ -251,30 +251,27 @@ __device__ __forceinline__ void voxel_run(const RayArgs &A, SWalk &w, const RayF
                 return;
             }
         }
-        // take the step; the face crossed is a block face when its coordinate is a multiple of 8
-        int face;
-        if (a == 0) {
-            face = R.rx > 0.0f ? (int)w.Bx : -(int)w.Bx;
-            w.Bx += 1.0f;
-            w.Tx = (w.Bx - R.gsx) * R.arx;
-            vx += sx;
-        } else if (a == 1) {
-            face = R.ry > 0.0f ? (int)w.By : -(int)w.By;
-            w.By += 1.0f;
-            w.Ty = (w.By - R.gsy) * R.ary;
-            vy += sy;
-        } else {
-            face = R.rz > 0.0f ? (int)w.Bz : -(int)w.Bz;
-            w.Bz += 1.0f;
-            w.Tz = (w.Bz - R.gsz) * R.arz;
-            vz += sz;
-        }
+        // take the step, with selects rather than branches (a wave's lanes step along different
+        // axes); the face crossed is a block face when its coordinate is a multiple of 8
+        const bool bx = a == 0, by = a == 1, bz = !bx && !by;
+        const float Ba = bx ? w.Bx : (by ? w.By : w.Bz);
+        const float rA = bx ? R.rx : (by ? R.ry : R.rz);
+        const int face = rA > 0.0f ? (int)Ba : -(int)Ba;
+        w.Bx = bx ? w.Bx + 1.0f : w.Bx;
+        w.By = by ? w.By + 1.0f : w.By;
+        w.Bz = bz ? w.Bz + 1.0f : w.Bz;
+        w.Tx = bx ? (w.Bx - R.gsx) * R.arx : w.Tx;
+        w.Ty = by ? (w.By - R.gsy) * R.ary : w.Ty;
+        w.Tz = bz ? (w.Bz - R.gsz) * R.arz : w.Tz;
+        vx += bx ? sx : 0;
+        vy += by ? sy : 0;
+        vz += bz ? sz : 0;
         w.ent_a = a;
         if ((face & 7) == 0) {
             crossed = true;
             break;
         }
-        if (a == 2) layer = layer_word(w.m, vz & 7);
+        layer = bz ? layer_word(w.m, vz & 7) : layer;
         if (mask_bit(layer, vx & 7, vy & 7)) {
             w.hit = w.ended = w.done = true;
             w.fx = vx; w.fy = vy; w.fz = vz;
