@@ -175,8 +175,9 @@ typedef struct {
  *     values_on_device == 0, device memory otherwise.  Only read during the call.
  *   map_id_out: receives the map's id (the same id space as dense maps).
  * The library keeps the values, a 512-bit occupancy mask per block and an open-addressed hash
- * table (a power of two of at least 2 n_blocks entries of 16 bytes, at least 1024) from block
+ * table (a power of two of at least 16 n_blocks entries of 16 bytes, at least 1024) from block
  * coordinates to slots: 16 capacity + 64 n_blocks + 512 elem_bytes n_blocks arena bytes.
+ * More than 2^27 blocks: RMPC_E_INVALID.
  * rmpc_query and rmpc_trace_debug accept sparse maps (launch configuration
  * RMPC_CONFIG_SPARSE; the start may lie anywhere whose voxels within max_range keep
  * |index| < 2^23; RMPC_E_OUT_OF_BOUNDS otherwise; sub-voxel distances on TSDF maps read

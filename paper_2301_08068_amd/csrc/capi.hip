@@ -544,6 +544,8 @@ rmpc_status rmpc_map_upload(rmpc_ctx *ctx, const rmpc_map_desc *desc, const void
     return RMPC_OK;
 }
 
+constexpr uint64_t kTableSlack = 16;       // block-table entries per stored block, at least
+
 rmpc_status rmpc_sparse_map_upload(rmpc_ctx *ctx, const rmpc_sparse_desc *desc, const int32_t *block_coords_host,
                                    const void *values, int values_on_device, void *hip_stream, int32_t *map_id_out)
 {
@@ -561,9 +563,14 @@ rmpc_status rmpc_sparse_map_upload(rmpc_ctx *ctx, const rmpc_sparse_desc *desc, 
     if (desc->dtype == RMPC_TSDF_F16) free_value = (double)(_Float16)desc->free_value;
     if (desc->dtype != RMPC_OCC_U8 && !(free_value > 0.0 && std::isfinite(free_value)))
         return fail(RMPC_E_INVALID, "free_value must be positive and finite in the map's storage type");
-    // the table: a power of two of at least twice the blocks, filled on the host by linear probing
-    uint32_t cap = 1024;
-    while (cap < 2u * (uint32_t)n) cap *= 2u;
+    // the table: a power of two of at least kTableSlack times the blocks, filled on the host by
+    // linear probing.  Most lookups are of blocks that are not stored; at a load factor of 1/2
+    // nearly half of them met another key at their first entry and probed on (a further
+    // dependent load, and the end of a block round), at 1/16 few do
+    uint64_t cap64 = 1024;
+    while (cap64 < kTableSlack * (uint64_t)n) cap64 *= 2u;
+    if (cap64 > (1ull << 31)) return fail(RMPC_E_INVALID, "too many blocks for the block table");
+    const uint32_t cap = (uint32_t)cap64;
     std::vector<rmpc::HashEntry> table(cap, rmpc::HashEntry{rmpc::kEmptyKey, -1, 0u});
     const uint32_t mask = cap - 1u;
     for (int32_t k = 0; k < n; ++k) {
