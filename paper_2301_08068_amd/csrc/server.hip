@@ -140,8 +140,7 @@ __global__ void warm_spin_kernel(uint64_t ticks)
 //    four outstanding copies, and a few times after as the depth rose, one copy call took
 //    6-11 ms; at a constant depth, never again);
 //  * an empty batch launch (no queries, no tiles: every block leaves at once), as the first
-//    launch of the batch kernel in a process took ~3 ms;
-//  * a device-to-device copy and a fill.
+//    launch of the batch kernel in a process took ~3 ms.
 rmpc_status warm_slots(rmpc_ctx *ctx, ServerState *S)
 {
     const size_t stage = S->cfg.staging_bytes / kAlign * kAlign;
@@ -171,10 +170,6 @@ rmpc_status warm_slots(rmpc_ctx *ctx, ServerState *S)
         if (ls.graph) RMPC_HIP(hipGraphUpload(ls.graph, ls.stream));
         uint64_t seq = 0;
         if (rmpc_status st = slot_launch(ctx, ls, 0, 0, S->cfg.launch, nullptr, &seq)) return st;
-        // the tile rows are written before they are read: their contents do not matter
-        RMPC_HIP(hipMemcpyAsync(ls.partials + rmpc::kPartialWords, ls.partials, sizeof(float) * rmpc::kPartialWords,
-                                hipMemcpyDeviceToDevice, ls.stream));
-        RMPC_HIP(hipMemsetAsync(ls.partials, 0, sizeof(float) * rmpc::kPartialWords, ls.stream));
         RMPC_HIP(hipStreamSynchronize(ls.stream));
     }
     return RMPC_OK;
