@@ -203,3 +203,31 @@ def test_stop_finishes_queued_work(env, paper_map):
     got = _drain(B, ctx, 1)
     B.rmpc_server_stop(ctx.ptr)
     assert t in got
+
+
+@pytest.mark.parametrize("use_graph", [0, 1])
+def test_one_tile_slots(env, paper_map, use_graph):
+    """A server whose launches hold a single 256-lane tile starts (its warm-up stays inside the
+    slots' buffers), serves a request that fits one tile bit-equal to the same query alone,
+    refuses one that does not, and stops cleanly."""
+    from paper_2301_08068_amd import binding as B
+    ctx, maps = env
+    x, v = W.free_state(paper_map, 3)
+    q = dict(kind="map", map_id=maps["f32"], n=16, x=x, v=v)
+    launch = dict(ctx.config(B.CONFIG_BATCH), use_graph=use_graph)
+    B.rmpc_server_start(ctx.ptr, n_slots=2, max_batch=1, max_tiles=1, map_params=P, scan_params=L,
+                        launch=launch, staging_bytes=1 << 16)
+    try:
+        with pytest.raises(B.RmpcError) as e:
+            B.rmpc_submit(ctx.ptr, B.request(dict(q, n=4096)))
+        assert e.value.status == B.RMPC_E_INVALID
+        t = B.rmpc_submit(ctx.ptr, B.request(q))
+        got = _drain(B, ctx, 1)
+    finally:
+        B.rmpc_server_stop(ctx.ptr)
+    alone = ctx.query_batch([q], map_params=P)[0]
+    res = got[t][0]
+    for k in ("S", "b", "f", "lam"):
+        assert np.array_equal(res[k], alone[k]), k
+    for k in ("rank", "n_hit", "n_contrib", "n_tie", "flags", "visits", "n_rays"):
+        assert res[k] == alone[k], k
