@@ -177,10 +177,11 @@ __global__ void __launch_bounds__(256) edt_lines_kernel(int32_t *g, int32_t len,
 }
 
 // LDS a group of 2^wlog lines of len elements may take (both copies and the flags): at most
-// 26 KiB, so that six blocks (24 waves) share a CU for the latency of the searches' LDS reads
-// (8 lines per group at the paper map's 400-voxel lines); a single line may take up to 64 KiB.
+// 13 KiB, so that many blocks share a CU for the latency of the searches' LDS reads (4 lines per
+// group at the paper map's 400-voxel lines: 1.3 % faster than 8, while 2 lost 21 %); a single
+// line may take up to 64 KiB.
 #ifndef EDT_GROUP_LDS
-#define EDT_GROUP_LDS (26 * 1024)
+#define EDT_GROUP_LDS (13 * 1024)
 #endif
 constexpr size_t kGroupLds = EDT_GROUP_LDS;
 constexpr size_t kLinesLds = 64 * 1024;
