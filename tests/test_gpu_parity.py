@@ -174,6 +174,24 @@ def test_scan_os0_scale_parity(ctx, paper_map):
         assert g["n_rays"] == pts.shape[0] == 262144 and g["n_hit"] == o["n_hit"]
 
 
+@pytest.mark.parametrize("n", [1001, 262145, 300001, 600000])
+def test_scan_sizes_across_point_batches(ctx, n):
+    """Scans whose threads take their points in several batches of eight with a ragged last one
+    (128 blocks x 256 threads x 8 points = 262,144 points per batch round): random points within
+    12 m, some dropouts (zeros) and non-finite entries."""
+    L = W.params("lidar")
+    rng = np.random.default_rng(n)
+    pts = (rng.normal(size=(n, 3)) * rng.uniform(0.05, 12.0, size=(n, 1)) /
+           np.sqrt(3.0)).astype(np.float32)
+    pts[rng.uniform(size=n) < 0.1] = 0.0
+    pts[rng.integers(0, n, size=3), rng.integers(0, 3, size=3)] = np.nan
+    v = [1.5, -0.5, 0.25]
+    g = ctx.scan_query(pts, v, L)
+    o = oracle.scan(pts, v, L)
+    compare_query(g, o, f"scan of {n} points")
+    assert g["n_rays"] == n and g["n_hit"] == o["n_hit"]
+
+
 def test_scan_reproduces_grid_query(ctx, tiny, tiny_map):
     mid, om = tiny
     dirs = oracle.directions(1024)
