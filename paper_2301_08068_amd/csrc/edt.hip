@@ -182,14 +182,14 @@ __global__ void __launch_bounds__(256) edt_lines_kernel(int32_t *g, int32_t len,
     }
 }
 
-// LDS a group of 2^wlog lines of len elements may take (both copies and the flags): at most
-// 13 KiB, so that many blocks share a CU for the latency of the searches' LDS reads (4 lines per
-// group at the paper map's 400-voxel lines: 1.3 % faster than 8, while 2 lost 21 %); a single
-// line may take up to 64 KiB.
-#ifndef EDT_GROUP_LDS
-#define EDT_GROUP_LDS (13 * 1024)
-#endif
-constexpr size_t kGroupLds = EDT_GROUP_LDS;
+// LDS a group of 2^wlog lines of len elements may take (both copies and the flags).  The y pass
+// takes at most 13 KiB, so that many blocks share a CU for the latency of the searches' LDS
+// reads (4 lines per group at the paper map's 400-voxel lines: 1.3 % faster than 8, while 2 lost
+// 21 %); the z pass, whose elements lie a whole plane apart, at most 26 KiB, so that a group's
+// loads and stores cover longer runs of consecutive x (8 lines at 400: 2.8 % faster than 4 over
+// the transform, 16 slower).  A single line may take up to 64 KiB.
+constexpr size_t kGroupLdsY = 13 * 1024;
+constexpr size_t kGroupLdsZ = 26 * 1024;
 constexpr size_t kLinesLds = 64 * 1024;
 
 size_t lines_lds(int32_t len, int wlog)
@@ -197,18 +197,18 @@ size_t lines_lds(int32_t len, int wlog)
     return (2 * ((size_t)len + 1) + 1) * ((size_t)1 << wlog) * sizeof(int32_t);
 }
 
-// The widest group (at most 64 lines) that fits kGroupLds.
-int lines_wlog(int32_t len)
+// The widest group (at most 64 lines) that fits cap bytes.
+int lines_wlog(int32_t len, size_t cap)
 {
     int wlog = 6;
-    while (wlog > 0 && lines_lds(len, wlog) > kGroupLds) --wlog;
+    while (wlog > 0 && lines_lds(len, wlog) > cap) --wlog;
     return wlog;
 }
 
 hipError_t launch_lines(int32_t *g, int32_t len, int64_t stride, int32_t nx, int64_t other, int64_t plane,
                         int y_pass, int last_pass, hipStream_t s)
 {
-    const int wlog = lines_wlog(len);
+    const int wlog = lines_wlog(len, y_pass ? kGroupLdsY : kGroupLdsZ);
     const int32_t groups_x = (nx + (1 << wlog) - 1) >> wlog;
     const size_t lds = lines_lds(len, wlog);
     if (lds > kLinesLds) return hipErrorInvalidValue;     // a line longer than 8,190 voxels (uploads take 4,096)
